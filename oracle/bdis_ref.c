@@ -1,0 +1,607 @@
+/*
+ * bdis_ref.c -- FP64 CPU oracle for Bayesian Dense Inverse Search stereo.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, plain, obviously correct
+ * statement of what the GPU path computes.  It is used by the test-suite, the
+ * smoke check and the CPU-baseline leg of the benchmark, and by nothing in
+ * the product path.  It shares no code, header, table or constant generator
+ * with the HIP library.
+ *
+ * Method: J. Song, Q. Zhu, J. Lin, M. Ghaffari, "Bayesian dense inverse
+ * searching algorithm for real-time stereo matching in minimally invasive
+ * surgery" (arXiv 2106.07136).
+ *   - Sec. 2.1, eq. (1): per-patch inverse-compositional Lucas-Kanade search,
+ *     Hessian taken once on the left (template) patch; coarse-to-fine.
+ *   - Sec. 2.1, eq. (2): the DIS inverse-residual fusion (ablation mode).
+ *   - Sec. 2.2, eqs. (3)-(4): patch posterior, Boltzmann likelihood normalised
+ *     over a small window of candidate disparities.
+ *   - Sec. 2.3, eq. (5) and the unnumbered final equation: spatial Gaussian
+ *     mask times the patch posterior as the per-pixel fusion weight.
+ *   - Sec. 3, first paragraph: sigma_r = sigma_s = 4, five window samples at
+ *     offsets 0.5 and 1 px, valid-pixel ratio gamma.
+ *   - Sec. 3.2, second paragraph: discard non-converged patches, lower the
+ *     weight of patches with invalid pixels, leave uncovered pixels unestimated.
+ *
+ * Readings of points the paper leaves open are stated where they are used.
+ * Everything is FP64, single-threaded, plain loops, in the paper's order.
+ * Sign convention of eq. (1): u is the shift with I_r(x + u) ~ I_l(x); the
+ * returned disparity is d = -u (left x matches right x - d).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define REF_MAX_LEVELS 12
+
+/* Patch outcome codes. */
+enum { REF_KEPT = 0, REF_DEGENERATE = 1, REF_DIVERGED = 2, REF_GATED = 3 };
+
+typedef struct {
+    int levels;          /* pyramid levels requested (capped by size)          */
+    int patch;           /* p: square patch side                               */
+    int stride;          /* st: patch grid spacing                             */
+    int iters;           /* K: LK iterations per level, no early exit          */
+    double sigma_r;      /* eq. (4) brightness spread                          */
+    double sigma_s;      /* eq. (5) spatial spread, level pixels               */
+    int window;          /* number of window samples in P' (odd)               */
+    double window_step;  /* spacing of the window samples, level pixels        */
+    double gamma;        /* valid-pixel ratio gate                             */
+    int s_mode;          /* 0: s = window samples; 1: s = patch side           */
+    int fusion;          /* 0: Bayesian (Sec. 2.3); 1: DIS eq. (2)             */
+    int valid_lo;        /* pixel valid iff valid_lo <= v <= valid_hi          */
+    int valid_hi;
+    double eps_h;        /* degenerate patch: H <= eps_h * n                   */
+} ref_params;
+
+typedef struct {
+    /* Optional per-level taps, caller-allocated, any entry may be NULL. */
+    double *pyr_l[REF_MAX_LEVELS], *pyr_r[REF_MAX_LEVELS];
+    uint8_t *mask_l[REF_MAX_LEVELS], *mask_r[REF_MAX_LEVELS];
+    double *u_init[REF_MAX_LEVELS];   /* per patch, row-major (ny, nx) */
+    double *u_final[REF_MAX_LEVELS];  /* per patch after K iterations  */
+    double *post[REF_MAX_LEVELS];     /* per patch posterior p_k       */
+    int8_t *status[REF_MAX_LEVELS];   /* per patch outcome code        */
+    double *field[REF_MAX_LEVELS];    /* dense U_l, level pixels       */
+} ref_trace;
+
+/* ------------------------------------------------------------------------ */
+/* Sizes                                                                     */
+/* ------------------------------------------------------------------------ */
+
+/* Level sizes: each coarser level halves with rounding up. */
+void ref_level_dims(int W, int H, int level, int *Wl, int *Hl)
+{
+    int w = W, h = H;
+    for (int l = 0; l < level; l++) {
+        w = (w + 1) / 2;
+        h = (h + 1) / 2;
+    }
+    *Wl = w;
+    *Hl = h;
+}
+
+/* Levels actually used: the request, cut so the coarsest level still holds
+ * a whole patch in both directions. */
+int ref_num_levels(int W, int H, int patch, int requested)
+{
+    int n = 0;
+    for (int l = 0; l < requested && l < REF_MAX_LEVELS; l++) {
+        int w, h;
+        ref_level_dims(W, H, l, &w, &h);
+        if (w < patch || h < patch)
+            break;
+        n = l + 1;
+    }
+    return n;
+}
+
+/* Patch grid along one axis: positions j*st, the last one snapped so the
+ * patch ends at the border (Sec. 1: patches are square segments on a grid). */
+int ref_grid_count(int n, int patch, int stride)
+{
+    if (n < patch)
+        return 0;
+    return (n - patch + stride - 1) / stride + 1;
+}
+
+int ref_grid_pos(int j, int n, int patch, int stride)
+{
+    int x = j * stride;
+    return x < n - patch ? x : n - patch;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Pyramid (Sec. 1 and Fig. 1: left and right resized to coarser scales).    */
+/* Reading: binomial [1 4 6 4 1]/16 blur in x then y, reflect-101 border,    */
+/* keep even indices, coarse size = ceil(fine / 2).                          */
+/* ------------------------------------------------------------------------ */
+
+static int reflect101(int i, int n)
+{
+    if (n == 1)
+        return 0;
+    while (i < 0 || i >= n) {
+        if (i < 0)
+            i = -i;
+        if (i >= n)
+            i = 2 * (n - 1) - i;
+    }
+    return i;
+}
+
+void ref_blur_decimate(const double *src, int W, int H, double *dst)
+{
+    static const double w5[5] = {1.0 / 16, 4.0 / 16, 6.0 / 16, 4.0 / 16, 1.0 / 16};
+    double *tmp = (double *)malloc(sizeof(double) * (size_t)W * H);
+    /* blur along x */
+    for (int y = 0; y < H; y++)
+        for (int x = 0; x < W; x++) {
+            double s = 0.0;
+            for (int a = -2; a <= 2; a++)
+                s += w5[a + 2] * src[(size_t)y * W + reflect101(x + a, W)];
+            tmp[(size_t)y * W + x] = s;
+        }
+    /* blur along y, then keep even rows and columns */
+    int Wc = (W + 1) / 2, Hc = (H + 1) / 2;
+    for (int yc = 0; yc < Hc; yc++)
+        for (int xc = 0; xc < Wc; xc++) {
+            int y = 2 * yc, x = 2 * xc;
+            double s = 0.0;
+            for (int a = -2; a <= 2; a++)
+                s += w5[a + 2] * tmp[(size_t)reflect101(y + a, H) * W + x];
+            dst[(size_t)yc * Wc + xc] = s;
+        }
+    free(tmp);
+}
+
+/* Validity (Sec. 3.2: invalid, dark and bright pixels break photometric
+ * consistency).  Level 0: intensity inside [lo, hi].  Coarser levels: a pixel
+ * is valid iff every existing one of its 2x2 fine children is valid. */
+void ref_mask_base(const uint8_t *img, int W, int H, int pitch, int lo, int hi, uint8_t *m)
+{
+    for (int y = 0; y < H; y++)
+        for (int x = 0; x < W; x++) {
+            int v = img[(size_t)y * pitch + x];
+            m[(size_t)y * W + x] = (uint8_t)(v >= lo && v <= hi);
+        }
+}
+
+void ref_mask_down(const uint8_t *m, int W, int H, uint8_t *mc)
+{
+    int Wc = (W + 1) / 2, Hc = (H + 1) / 2;
+    for (int yc = 0; yc < Hc; yc++)
+        for (int xc = 0; xc < Wc; xc++) {
+            int ok = 1;
+            for (int dy = 0; dy < 2; dy++)
+                for (int dx = 0; dx < 2; dx++) {
+                    int y = 2 * yc + dy, x = 2 * xc + dx;
+                    if (y < H && x < W && !m[(size_t)y * W + x])
+                        ok = 0;
+                }
+            mc[(size_t)yc * Wc + xc] = (uint8_t)ok;
+        }
+}
+
+/* Template-side gradient for eq. (1): the inverse-compositional form needs
+ * only the left patch's derivative along the search direction (x).
+ * Reading: central difference, replicate border. */
+void ref_grad_x(const double *img, int W, int H, double *g)
+{
+    for (int y = 0; y < H; y++)
+        for (int x = 0; x < W; x++) {
+            int xp = x + 1 < W ? x + 1 : W - 1;
+            int xm = x - 1 > 0 ? x - 1 : 0;
+            g[(size_t)y * W + x] = 0.5 * (img[(size_t)y * W + xp] - img[(size_t)y * W + xm]);
+        }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Samplers                                                                  */
+/* ------------------------------------------------------------------------ */
+
+/* I_r(x + u) on one image row.  Rows are integer in a rectified pair, so the
+ * bilinear sampler reduces to linear interpolation in x; the coordinate is
+ * clamped to the row. */
+double ref_sample_row(const double *row, int W, double X)
+{
+    if (W == 1)
+        return row[0];
+    if (X < 0.0)
+        X = 0.0;
+    if (X > (double)(W - 1))
+        X = (double)(W - 1);
+    int m = (int)floor(X);
+    if (m > W - 2)
+        m = W - 2;
+    double f = X - (double)m;
+    return (1.0 - f) * row[m] + f * row[m + 1];
+}
+
+/* Bilinear read of a coarse field at (X, Y), coordinates clamped. */
+double ref_bilinear(const double *F, int W, int H, double X, double Y)
+{
+    if (X < 0.0) X = 0.0;
+    if (X > (double)(W - 1)) X = (double)(W - 1);
+    if (Y < 0.0) Y = 0.0;
+    if (Y > (double)(H - 1)) Y = (double)(H - 1);
+    int mx = (int)floor(X), my = (int)floor(Y);
+    if (mx > W - 2) mx = W - 2;
+    if (my > H - 2) my = H - 2;
+    if (mx < 0) mx = 0;
+    if (my < 0) my = 0;
+    double fx = W > 1 ? X - mx : 0.0, fy = H > 1 ? Y - my : 0.0;
+    int mx1 = W > 1 ? mx + 1 : mx, my1 = H > 1 ? my + 1 : my;
+    double a = (1.0 - fx) * F[(size_t)my * W + mx] + fx * F[(size_t)my * W + mx1];
+    double b = (1.0 - fx) * F[(size_t)my1 * W + mx] + fx * F[(size_t)my1 * W + mx1];
+    return (1.0 - fy) * a + fy * b;
+}
+
+/* ------------------------------------------------------------------------ */
+/* One patch: eq. (1) then eqs. (3)-(4) and the gates.                       */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    double u0, u, H, post, valid_ratio;
+    int n, status;
+} ref_patch_out;
+
+/* Mean-normalised residual energy of the patch at shift u:
+ * E(u) = sum over left-valid pixels of (d_j - mean d)^2, d_j = I_r(x_j+u) - I_l(x_j).
+ * The same residual drives the LK update (eq. (1)) and the likelihood (eq. (4)). */
+double ref_patch_energy(const double *L, const double *R, const uint8_t *ML, int W, int H,
+                        int x0, int y0, int p, double u)
+{
+    (void)H;
+    double sum = 0.0;
+    int n = 0;
+    for (int r = 0; r < p; r++)
+        for (int c = 0; c < p; c++) {
+            size_t i = (size_t)(y0 + r) * W + (x0 + c);
+            if (!ML[i])
+                continue;
+            sum += ref_sample_row(R + (size_t)(y0 + r) * W, W, x0 + c + u) - L[i];
+            n++;
+        }
+    if (n == 0)
+        return 0.0;
+    double mean = sum / n, E = 0.0;
+    for (int r = 0; r < p; r++)
+        for (int c = 0; c < p; c++) {
+            size_t i = (size_t)(y0 + r) * W + (x0 + c);
+            if (!ML[i])
+                continue;
+            double d = ref_sample_row(R + (size_t)(y0 + r) * W, W, x0 + c + u) - L[i] - mean;
+            E += d * d;
+        }
+    return E;
+}
+
+/* Posterior of the converged disparity, eqs. (3)-(4): Boltzmann likelihood of
+ * each window sample, normalised over the window P' (the ratio r is the same
+ * for every patch and cancels in the normalised fusion).  Written with the
+ * centre energy factored out, p = 1 / sum_i exp(-(E_i - E_c)/tau), which is
+ * the same number without underflow. */
+double ref_posterior(const double *E, int n, int centre, double tau)
+{
+    double s = 0.0;
+    for (int i = 0; i < n; i++)
+        s += exp(-(E[i] - E[centre]) / tau);
+    return 1.0 / s;
+}
+
+/* Inverse-compositional LK on one patch (Sec. 2.1, eq. (1)).  The update is
+ * taken on the template (left) side, so its Jacobian and Hessian come from
+ * the left patch once: J_j = g_j - mean g (the mean-normalised template
+ * gradient), H = sum J_j^2.  Each iteration samples the right image at the
+ * current shift, forms the mean-normalised residual e_j and moves
+ * u <- u - (sum J_j e_j) / H.  Only left-valid pixels enter the sums. */
+int ref_patch_lk(const double *L, const double *R, const double *G, const uint8_t *ML,
+                 int W, int H, int x0, int y0, int p, int iters, double u0, double eps_h,
+                 double *u_out, double *H_out, int *n_out, double *step_hist)
+{
+    (void)H;
+    int n = 0;
+    double gsum = 0.0;
+    for (int r = 0; r < p; r++)
+        for (int c = 0; c < p; c++) {
+            size_t i = (size_t)(y0 + r) * W + (x0 + c);
+            if (ML[i]) {
+                gsum += G[i];
+                n++;
+            }
+        }
+    *n_out = n;
+    *u_out = u0;
+    *H_out = 0.0;
+    if (n == 0)
+        return REF_DEGENERATE;
+    double gmean = gsum / n, Hs = 0.0;
+    for (int r = 0; r < p; r++)
+        for (int c = 0; c < p; c++) {
+            size_t i = (size_t)(y0 + r) * W + (x0 + c);
+            if (ML[i]) {
+                double J = G[i] - gmean;
+                Hs += J * J;
+            }
+        }
+    *H_out = Hs;
+    if (!(Hs > eps_h * n))
+        return REF_DEGENERATE;
+    double u = u0;
+    for (int t = 0; t < iters; t++) {
+        double dsum = 0.0;
+        for (int r = 0; r < p; r++)
+            for (int c = 0; c < p; c++) {
+                size_t i = (size_t)(y0 + r) * W + (x0 + c);
+                if (ML[i])
+                    dsum += ref_sample_row(R + (size_t)(y0 + r) * W, W, x0 + c + u) - L[i];
+            }
+        double dmean = dsum / n, b = 0.0;
+        for (int r = 0; r < p; r++)
+            for (int c = 0; c < p; c++) {
+                size_t i = (size_t)(y0 + r) * W + (x0 + c);
+                if (!ML[i])
+                    continue;
+                double e = ref_sample_row(R + (size_t)(y0 + r) * W, W, x0 + c + u) - L[i] - dmean;
+                b += (G[i] - gmean) * e;
+            }
+        if (step_hist)
+            step_hist[t] = b / Hs;
+        u = u - b / Hs;
+    }
+    *u_out = u;
+    return REF_KEPT;
+}
+
+/* Fraction of the patch that gives usable evidence at shift u: left pixel
+ * valid, its right sample inside the row, and both right taps valid
+ * (Sec. 3 gamma; Sec. 3.2 invalid pixels lower a patch's weight). */
+double ref_valid_ratio(const uint8_t *ML, const uint8_t *MR, int W, int x0, int y0, int p, double u)
+{
+    int cnt = 0;
+    for (int r = 0; r < p; r++)
+        for (int c = 0; c < p; c++) {
+            size_t i = (size_t)(y0 + r) * W + (x0 + c);
+            double X = x0 + c + u;
+            if (!ML[i] || X < 0.0 || X > (double)(W - 1))
+                continue;
+            int m = (int)floor(X);
+            if (W > 1 && m > W - 2)
+                m = W - 2;
+            int m1 = W > 1 ? m + 1 : m;
+            size_t rr = (size_t)(y0 + r) * W;
+            if (MR[rr + m] && MR[rr + m1])
+                cnt++;
+        }
+    return (double)cnt / ((double)p * p);
+}
+
+/* Whole per-patch pipeline at one level. */
+static void ref_patch(const ref_params *P, const double *L, const double *R, const double *G,
+                      const uint8_t *ML, const uint8_t *MR, int W, int H, int x0, int y0,
+                      double u0, ref_patch_out *o)
+{
+    int p = P->patch;
+    o->u0 = u0;
+    o->post = 0.0;
+    o->valid_ratio = 0.0;
+    o->status = ref_patch_lk(L, R, G, ML, W, H, x0, y0, p, P->iters, u0, P->eps_h,
+                             &o->u, &o->H, &o->n, NULL);
+    if (o->status != REF_KEPT)
+        return;
+    if (P->fusion == 1) { /* DIS eq. (2): no window, no gate, no discard */
+        if (!isfinite(o->u))
+            o->status = REF_DIVERGED;
+        else
+            o->post = 1.0;
+        return;
+    }
+    /* Sec. 3.2: the patch that does not converge is discarded.  Reading:
+     * a non-finite shift, or one that left the initial estimate by more
+     * than a patch side. */
+    if (!isfinite(o->u) || fabs(o->u - u0) > (double)p) {
+        o->status = REF_DIVERGED;
+        return;
+    }
+    /* eqs. (3)-(4) over the window P' = {u + (i - c) * step}. */
+    double E[64];
+    int nw = P->window, c = (P->window - 1) / 2;
+    for (int i = 0; i < nw; i++)
+        E[i] = ref_patch_energy(L, R, ML, W, H, x0, y0, p, o->u + (i - c) * P->window_step);
+    double s = P->s_mode == 0 ? (double)P->window : (double)p;
+    double tau = 2.0 * P->sigma_r * P->sigma_r * s * s;
+    o->post = ref_posterior(E, nw, c, tau);
+    o->valid_ratio = ref_valid_ratio(ML, MR, W, x0, y0, p, o->u);
+    if (o->valid_ratio < P->gamma) {
+        o->status = REF_GATED;
+        o->post = 0.0;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Densification (Sec. 2.3): written as a scatter over patches.              */
+/* ------------------------------------------------------------------------ */
+
+/* Spatial Gaussian mask of eq. (5): weight of pixel (r, c) of a patch is
+ * exp(-|x - centre|^2 / (2 sigma_s^2)); it depends on the offset inside the
+ * patch only, so it is the same for every patch. */
+double ref_spatial_weight(int r, int c, int p, double sigma_s)
+{
+    double cy = (p - 1) * 0.5, cx = (p - 1) * 0.5;
+    double d2 = (r - cy) * (r - cy) + (c - cx) * (c - cx);
+    return exp(-d2 / (2.0 * sigma_s * sigma_s));
+}
+
+/* Per-pixel posterior-weighted mean over the kept covering patches
+ * (final equation of Sec. 2.3 used as weights).  acc_w and acc_wu are
+ * caller buffers of W*H.  In DIS mode the weight is eq. (2)'s inverse
+ * residual 1/max((I_r(x+u_k) - I_l(x))^2, 1). */
+void ref_densify(const ref_params *P, int W, int H, int nx, int ny, const double *u,
+                 const double *post, const int8_t *status, const double *L, const double *R,
+                 double *acc_w, double *acc_wu)
+{
+    int p = P->patch;
+    for (size_t i = 0; i < (size_t)W * H; i++) {
+        acc_w[i] = 0.0;
+        acc_wu[i] = 0.0;
+    }
+    for (int jy = 0; jy < ny; jy++)
+        for (int jx = 0; jx < nx; jx++) {
+            int k = jy * nx + jx;
+            if (status[k] != REF_KEPT)
+                continue;
+            int x0 = ref_grid_pos(jx, W, p, P->stride), y0 = ref_grid_pos(jy, H, p, P->stride);
+            for (int r = 0; r < p; r++)
+                for (int c = 0; c < p; c++) {
+                    size_t i = (size_t)(y0 + r) * W + (x0 + c);
+                    double w;
+                    if (P->fusion == 1) {
+                        double res = ref_sample_row(R + (size_t)(y0 + r) * W, W, x0 + c + u[k]) - L[i];
+                        double q = res * res;
+                        w = 1.0 / (q > 1.0 ? q : 1.0);
+                    } else {
+                        w = post[k] * ref_spatial_weight(r, c, p, P->sigma_s);
+                    }
+                    acc_w[i] += w;
+                    acc_wu[i] += w * u[k];
+                }
+        }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Whole pair, coarse to fine (Sec. 2.1, Fig. 1).                            */
+/* ------------------------------------------------------------------------ */
+
+/* Returns 0 on success, -1 on bad arguments, -2 on allocation failure.
+ * disp: W*H doubles, row-major, d = -U_0, NaN where no patch covered the
+ * pixel (Sec. 3.2: such pixels are not estimated). */
+int ref_compute(const ref_params *P, const uint8_t *Limg, const uint8_t *Rimg, int W, int H,
+                int pitch, double *disp, ref_trace *trace)
+{
+    if (!P || !Limg || !Rimg || !disp || W < 1 || H < 1 || pitch < W || P->patch < 1 ||
+        P->stride < 1 || P->iters < 0 || P->window < 1 || (P->window % 2) == 0 ||
+        P->window > 63 || W < P->patch || H < P->patch)
+        return -1;
+    int NL = ref_num_levels(W, H, P->patch, P->levels);
+    if (NL < 1)
+        return -1;
+
+    double *pl[REF_MAX_LEVELS], *pr[REF_MAX_LEVELS], *gl[REF_MAX_LEVELS], *U[REF_MAX_LEVELS];
+    uint8_t *ml[REF_MAX_LEVELS], *mr[REF_MAX_LEVELS];
+    int Ws[REF_MAX_LEVELS], Hs[REF_MAX_LEVELS];
+    memset(pl, 0, sizeof pl); memset(pr, 0, sizeof pr); memset(gl, 0, sizeof gl);
+    memset(U, 0, sizeof U); memset(ml, 0, sizeof ml); memset(mr, 0, sizeof mr);
+    int rc = 0;
+    double *aw = NULL, *awu = NULL;
+
+    for (int l = 0; l < NL; l++) {
+        ref_level_dims(W, H, l, &Ws[l], &Hs[l]);
+        size_t n = (size_t)Ws[l] * Hs[l];
+        pl[l] = (double *)malloc(n * sizeof(double));
+        pr[l] = (double *)malloc(n * sizeof(double));
+        gl[l] = (double *)malloc(n * sizeof(double));
+        U[l] = (double *)malloc(n * sizeof(double));
+        ml[l] = (uint8_t *)malloc(n);
+        mr[l] = (uint8_t *)malloc(n);
+        if (!pl[l] || !pr[l] || !gl[l] || !U[l] || !ml[l] || !mr[l]) {
+            rc = -2;
+            goto done;
+        }
+    }
+    aw = (double *)malloc((size_t)W * H * sizeof(double));
+    awu = (double *)malloc((size_t)W * H * sizeof(double));
+    if (!aw || !awu) {
+        rc = -2;
+        goto done;
+    }
+
+    /* Intensities stay in gray levels 0..255: sigma_r is in those units. */
+    for (int y = 0; y < H; y++)
+        for (int x = 0; x < W; x++) {
+            pl[0][(size_t)y * W + x] = Limg[(size_t)y * pitch + x];
+            pr[0][(size_t)y * W + x] = Rimg[(size_t)y * pitch + x];
+        }
+    ref_mask_base(Limg, W, H, pitch, P->valid_lo, P->valid_hi, ml[0]);
+    ref_mask_base(Rimg, W, H, pitch, P->valid_lo, P->valid_hi, mr[0]);
+    for (int l = 1; l < NL; l++) {
+        ref_blur_decimate(pl[l - 1], Ws[l - 1], Hs[l - 1], pl[l]);
+        ref_blur_decimate(pr[l - 1], Ws[l - 1], Hs[l - 1], pr[l]);
+        ref_mask_down(ml[l - 1], Ws[l - 1], Hs[l - 1], ml[l]);
+        ref_mask_down(mr[l - 1], Ws[l - 1], Hs[l - 1], mr[l]);
+    }
+    for (int l = 0; l < NL; l++)
+        ref_grad_x(pl[l], Ws[l], Hs[l], gl[l]);
+
+    for (int l = NL - 1; l >= 0; l--) {
+        int w = Ws[l], h = Hs[l], p = P->patch;
+        int nx = ref_grid_count(w, p, P->stride), ny = ref_grid_count(h, p, P->stride);
+        size_t np = (size_t)nx * ny;
+        double *pu = (double *)malloc(np * sizeof(double));
+        double *pp = (double *)malloc(np * sizeof(double));
+        int8_t *ps = (int8_t *)malloc(np);
+        if (!pu || !pp || !ps) {
+            free(pu); free(pp); free(ps);
+            rc = -2;
+            goto done;
+        }
+        for (int jy = 0; jy < ny; jy++)
+            for (int jx = 0; jx < nx; jx++) {
+                int k = jy * nx + jx;
+                int x0 = ref_grid_pos(jx, w, p, P->stride), y0 = ref_grid_pos(jy, h, p, P->stride);
+                /* Sec. 2.1: the fine level starts from the optimised coarse
+                 * field, read bilinearly at the patch centre and doubled. */
+                double u0 = 0.0;
+                if (l < NL - 1) {
+                    double cx = x0 + 0.5 * (p - 1), cy = y0 + 0.5 * (p - 1);
+                    u0 = 2.0 * ref_bilinear(U[l + 1], Ws[l + 1], Hs[l + 1], 0.5 * cx, 0.5 * cy);
+                }
+                ref_patch_out o;
+                ref_patch(P, pl[l], pr[l], gl[l], ml[l], mr[l], w, h, x0, y0, u0, &o);
+                pu[k] = o.u;
+                pp[k] = o.status == REF_KEPT ? o.post : 0.0;
+                ps[k] = (int8_t)o.status;
+                if (trace && trace->u_init[l]) trace->u_init[l][k] = u0;
+            }
+        ref_densify(P, w, h, nx, ny, pu, pp, ps, pl[l], pr[l], aw, awu);
+        for (int y = 0; y < h; y++)
+            for (int x = 0; x < w; x++) {
+                size_t i = (size_t)y * w + x;
+                double v;
+                if (aw[i] > 0.0)
+                    v = awu[i] / aw[i];
+                else if (l == 0)
+                    v = NAN; /* Sec. 3.2: uncovered pixels stay unestimated */
+                else if (l == NL - 1)
+                    v = 0.0;
+                else
+                    v = 2.0 * ref_bilinear(U[l + 1], Ws[l + 1], Hs[l + 1], 0.5 * x, 0.5 * y);
+                U[l][i] = v;
+            }
+        if (trace) {
+            if (trace->u_final[l]) memcpy(trace->u_final[l], pu, np * sizeof(double));
+            if (trace->post[l]) memcpy(trace->post[l], pp, np * sizeof(double));
+            if (trace->status[l]) memcpy(trace->status[l], ps, np);
+        }
+        free(pu); free(pp); free(ps);
+    }
+    for (int y = 0; y < H; y++)
+        for (int x = 0; x < W; x++)
+            disp[(size_t)y * W + x] = -U[0][(size_t)y * W + x];
+    if (trace)
+        for (int l = 0; l < NL; l++) {
+            size_t n = (size_t)Ws[l] * Hs[l];
+            if (trace->pyr_l[l]) memcpy(trace->pyr_l[l], pl[l], n * sizeof(double));
+            if (trace->pyr_r[l]) memcpy(trace->pyr_r[l], pr[l], n * sizeof(double));
+            if (trace->mask_l[l]) memcpy(trace->mask_l[l], ml[l], n);
+            if (trace->mask_r[l]) memcpy(trace->mask_r[l], mr[l], n);
+            if (trace->field[l]) memcpy(trace->field[l], U[l], n * sizeof(double));
+        }
+done:
+    for (int l = 0; l < NL; l++) {
+        free(pl[l]); free(pr[l]); free(gl[l]); free(U[l]); free(ml[l]); free(mr[l]);
+    }
+    free(aw);
+    free(awu);
+    return rc;
+}

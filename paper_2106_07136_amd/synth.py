@@ -1,0 +1,174 @@
+"""Seeded synthetic stereo pairs shaped like the paper's surgical data.
+
+The paper evaluates on a Unity3D colon phantom and on in-vivo videos
+(Section 3, first paragraph), neither of which is available here.  This
+module stands in for them with rectified 8-bit grayscale pairs that carry the
+two failure modes the paper designs against (Section 1, fourth paragraph):
+weakly textured regions and non-Lambertian specular highlights, plus a smooth
+photometric gain.  It holds none of the stereo method's arithmetic: it only
+draws images, a ground-truth disparity and its validity.
+
+Conventions: disparity d >= 0 means left pixel x is seen at right pixel x - d.
+Every random draw comes from one numpy PCG64 stream in a fixed order, so a
+seed fixes the pair bit for bit.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+from scipy.ndimage import gaussian_filter
+
+__all__ = ["StereoPair", "make_pair", "integer_shift_pair", "random_pair_tiny"]
+
+
+@dataclass
+class StereoPair:
+    left: np.ndarray       # uint8 (H, W)
+    right: np.ndarray      # uint8 (H, W)
+    disp: np.ndarray       # float32 (H, W), ground truth on the left grid
+    valid: np.ndarray      # bool (H, W), left pixel visible in the right image
+    seed: int
+    d_max: float
+
+
+def _bumps(rng, W, H, n, wlo, whi, alo, ahi):
+    yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
+    out = np.zeros((H, W))
+    for _ in range(n):
+        cx = rng.uniform(0, W)
+        cy = rng.uniform(0, H)
+        w = rng.uniform(wlo, whi)
+        a = rng.uniform(alo, ahi)
+        out += a * np.exp(-((xx - cx) ** 2 + (yy - cy) ** 2) / (2.0 * w * w))
+    return out
+
+
+def _minmax(a):
+    lo, hi = a.min(), a.max()
+    if hi - lo <= 0:
+        return np.zeros_like(a)
+    return (a - lo) / (hi - lo)
+
+
+def _keys_cubic_rows(img, xs):
+    """Keys cubic convolution (a = -0.5) along each row at columns xs (H, W'),
+    replicate border.  A different interpolant from the method's linear one,
+    so the generated pair carries no interpolation bias toward the method."""
+    H, W = img.shape
+    x0 = np.floor(xs).astype(np.int64)
+    t = xs - x0
+    a = -0.5
+
+    def k(s):
+        s = np.abs(s)
+        return np.where(
+            s <= 1, (a + 2) * s**3 - (a + 3) * s**2 + 1,
+            np.where(s < 2, a * s**3 - 5 * a * s**2 + 8 * a * s - 4 * a, 0.0))
+
+    rows = np.arange(H)[:, None]
+    out = np.zeros_like(xs)
+    for o in (-1, 0, 1, 2):
+        idx = np.clip(x0 + o, 0, W - 1)
+        out += k(t - o) * img[rows, idx]
+    return out
+
+
+def _lin_rows(f, xs):
+    H, W = f.shape
+    xs = np.clip(xs, 0, W - 1)
+    m = np.minimum(np.floor(xs).astype(np.int64), W - 2)
+    t = xs - m
+    rows = np.arange(H)[:, None]
+    return (1 - t) * f[rows, m] + t * f[rows, m + 1]
+
+
+def make_pair(W: int, H: int, d_max: float, seed: int, *, low_contrast=True,
+              gain=True, specular=True, noise=True) -> StereoPair:
+    """One synthetic rectified pair (W x H) with disparity in [0, d_max].
+
+    Recipe, in draw order:
+      1. texture: uniform noise blurred with a sigma-2 Gaussian;
+      2. low contrast: the 30 % of pixels where a smooth random field is lowest
+         get their contrast cut to a tenth (weak texture);
+      3. disparity: four random 2-D Gaussians min-max mapped to [0, d_max],
+         redrawn until the horizontal slope stays below 0.5 (no occlusion);
+      4. warp: each right pixel x' takes the left value at x = x' + D(x)
+         (30 fixed-point steps), sampled with Keys cubic interpolation;
+      5. gain: the right image times a smooth field in [0.8, 1.2];
+      6. specular: five Gaussian blobs added to the right image, saturating
+         at 255 in their cores;
+      7. sensor noise N(0, 2^2) on the right; both images rounded half to
+         even and clipped to uint8.
+    The flags switch off steps 2, 5, 6 and 7 for the "diffuse" variant.
+    """
+    if W < 4 or H < 4:
+        raise ValueError("image too small")
+    rng = np.random.Generator(np.random.PCG64(seed))
+    base = gaussian_filter(rng.uniform(0.0, 255.0, (H, W)), sigma=2.0,
+                           mode="mirror", truncate=4.0)
+    lf = base.copy()
+    field = gaussian_filter(rng.uniform(0.0, 1.0, (H, W)), sigma=W / 16.0,
+                            mode="mirror", truncate=4.0)
+    if low_contrast:
+        k = int(round(0.3 * H * W))
+        thr = np.sort(field.ravel())[k - 1]
+        mask = field <= thr
+        mu = base.mean()
+        lf[mask] = mu + 0.1 * (base[mask] - mu)
+
+    D = None
+    for _ in range(100):
+        cand = _minmax(_bumps(rng, W, H, 4, W / 8.0, W / 4.0, 0.5, 1.0)) * d_max
+        if W < 2 or np.abs(np.diff(cand, axis=1)).max() < 0.5:
+            D = cand
+            break
+    if D is None:
+        raise RuntimeError("no disparity field with slope < 0.5 in 100 draws")
+
+    xp = np.broadcast_to(np.arange(W, dtype=np.float64), (H, W))
+    x = xp.copy()
+    for _ in range(30):
+        x = xp + _lin_rows(D, x)
+    rf = _keys_cubic_rows(lf, x)
+
+    g = _minmax(_bumps(rng, W, H, 3, W / 4.0, W / 2.0, 0.5, 1.0))
+    if gain:
+        rf = rf * (0.8 + 0.4 * g)
+    yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
+    for _ in range(5):
+        cx = rng.uniform(0, W)
+        cy = rng.uniform(0, H)
+        r = rng.uniform(W / 64.0, W / 32.0)
+        if specular:
+            rf = rf + 1.5 * 255.0 * np.exp(-((xx - cx) ** 2 + (yy - cy) ** 2) / (2 * r * r))
+    nz = rng.normal(0.0, 2.0, (H, W))
+    if noise:
+        rf = rf + nz
+    left = np.clip(np.rint(lf), 0, 255).astype(np.uint8)
+    right = np.clip(np.rint(rf), 0, 255).astype(np.uint8)
+    valid = (np.arange(W)[None, :] - D) >= 0
+    return StereoPair(left, right, D.astype(np.float32), valid, seed, float(d_max))
+
+
+def integer_shift_pair(W: int, H: int, s: int, seed: int) -> StereoPair:
+    """Right image = left image shifted by an integer s (R(x') = L(x' + s),
+    replicate border): no low contrast, gain, highlights or noise."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    base = gaussian_filter(rng.uniform(0.0, 255.0, (H, W)), sigma=2.0,
+                           mode="mirror", truncate=4.0)
+    left = np.clip(np.rint(base), 0, 255).astype(np.uint8)
+    idx = np.clip(np.arange(W) + s, 0, W - 1)
+    right = left[:, idx].copy()
+    disp = np.full((H, W), float(s), np.float32)
+    valid = (np.arange(W)[None, :] - s) >= 0
+    valid = np.broadcast_to(valid, (H, W)).copy()
+    return StereoPair(left, right, disp, valid, seed, float(s))
+
+
+def random_pair_tiny(W: int, H: int, seed: int, lo=0, hi=256) -> tuple[np.ndarray, np.ndarray]:
+    """Two independent uniform uint8 images (edge-case inputs)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    a = rng.integers(lo, hi, (H, W), dtype=np.uint8)
+    b = rng.integers(lo, hi, (H, W), dtype=np.uint8)
+    return a, b

@@ -1,0 +1,461 @@
+"""Pins for the FP64 oracle: each check ties it to something other than
+itself -- a library routine, a closed form, an invariant, brute force or a
+number the paper prints -- so that a dropped term, a wrong sign or index or a
+transposed operand fails here.  CPU only."""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.ndimage import convolve1d
+from scipy.special import softmax
+
+from paper_2106_07136_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden_hparams():
+    out = {}
+    with open(os.path.join(GOLDEN, "paper_hyperparameters.txt")) as f:
+        for line in f:
+            line = line.split("#")[0].strip()
+            if not line:
+                continue
+            k, *v = line.split()
+            out[k] = [float(x) for x in v]
+    return out
+
+
+# ---------------------------------------------------------------- defaults
+
+def test_defaults_match_paper_section3(ref):
+    g = _golden_hparams()
+    p = ref.Params()
+    assert p.sigma_r == g["sigma_r"][0] and p.sigma_s == g["sigma_s"][0]
+    assert p.window == g["window"][0]
+    c = (p.window - 1) // 2
+    offs = sorted({abs((i - c) * p.window_step) for i in range(p.window)} - {0.0})
+    assert offs == g["window_offsets"]
+    assert p.gamma == g["gamma_640x480"][0]
+
+
+# ---------------------------------------------------------------- pyramid
+
+@pytest.mark.parametrize("shape", [(12, 16), (13, 17), (9, 9), (30, 41)])
+def test_pyramid_equals_scipy_mirror_convolution(ref, shape):
+    rng = np.random.default_rng(7)
+    img = rng.uniform(0, 255, shape)
+    k = np.array([1, 4, 6, 4, 1]) / 16.0
+    exp = convolve1d(convolve1d(img, k, axis=1, mode="mirror"), k, axis=0, mode="mirror")[::2, ::2]
+    got = ref.blur_decimate(img)
+    assert got.shape == ((shape[0] + 1) // 2, (shape[1] + 1) // 2)
+    np.testing.assert_allclose(got, exp, rtol=0, atol=1e-11)
+
+
+def test_pyramid_constant_and_ramp(ref):
+    c = np.full((15, 22), 37.25)
+    np.testing.assert_allclose(ref.blur_decimate(c), 37.25, atol=1e-12)
+    yy, xx = np.mgrid[0:20, 0:24].astype(float)
+    ramp = 3.0 * xx - 2.0 * yy + 5.0
+    out = ref.blur_decimate(ramp)
+    # symmetric normalised kernel reproduces a linear function away from the border
+    for yc in range(1, out.shape[0] - 1):
+        for xc in range(1, out.shape[1] - 1):
+            assert abs(out[yc, xc] - (3.0 * 2 * xc - 2.0 * 2 * yc + 5.0)) < 1e-10
+
+
+def test_mask_down_hand_counted(ref):
+    m = np.array([[1, 1, 1, 0, 1],
+                  [1, 1, 1, 1, 1],
+                  [0, 1, 1, 1, 1]], np.uint8)
+    # 2x2 AND over existing children: cols (0,1),(2,3),(4); rows (0,1),(2)
+    exp = np.array([[1, 0, 1],
+                    [0, 1, 1]], np.uint8)
+    np.testing.assert_array_equal(ref.mask_down(m), exp)
+
+
+def test_mask_base_band(ref):
+    img = np.array([[0, 1, 2, 253, 254, 255]], np.uint8)
+    np.testing.assert_array_equal(ref.mask_base(img, 1, 254), [[0, 1, 1, 1, 1, 0]])
+
+
+# ---------------------------------------------------------------- gradient
+
+def test_gradient_exact_on_quadratic(ref):
+    a, b, c = 0.37, -1.5, 4.0
+    x = np.arange(11, dtype=float)
+    img = np.tile(a * x**2 + b * x + c, (3, 1))
+    g = ref.grad_x(img)
+    np.testing.assert_allclose(g[:, 1:-1], np.tile((2 * a * x + b)[1:-1], (3, 1)), atol=1e-12)
+    # replicate border: one-sided half difference
+    np.testing.assert_allclose(g[:, 0], 0.5 * (img[:, 1] - img[:, 0]), atol=1e-12)
+    np.testing.assert_allclose(g[:, -1], 0.5 * (img[:, -1] - img[:, -2]), atol=1e-12)
+
+
+# ---------------------------------------------------------------- samplers
+
+def test_row_sampler(ref):
+    row = np.array([3.0, 7.0, -2.0, 10.0])
+    for i, v in enumerate(row):
+        assert ref.sample_row(row, i) == v
+    assert abs(ref.sample_row(row, 1.25) - (0.75 * 7 + 0.25 * -2)) < 1e-15
+    assert ref.sample_row(row, -5.0) == 3.0
+    assert ref.sample_row(row, 9.0) == 10.0
+    assert ref.sample_row(row, 3.0) == 10.0
+
+
+def test_bilinear_exact_on_affine_fields(ref):
+    yy, xx = np.mgrid[0:6, 0:9].astype(float)
+    F = 0.5 * xx - 1.25 * yy + 2.0
+    for X, Y in [(0.3, 0.7), (4.5, 2.25), (7.99, 4.01), (8.0, 5.0)]:
+        assert abs(ref.bilinear(F, X, Y) - (0.5 * X - 1.25 * Y + 2.0)) < 1e-12
+    # clamped outside
+    assert abs(ref.bilinear(F, -3, -1) - F[0, 0]) < 1e-12
+    assert abs(ref.bilinear(np.full((4, 4), 1.75), 2.2, 1.1) - 1.75) < 1e-15
+
+
+# ---------------------------------------------------------------- LK (eq. 1)
+
+def _textured(W, H, seed):
+    return synth.integer_shift_pair(W, H, 0, seed).left.astype(np.float64)
+
+
+@pytest.mark.parametrize("s", [1, 3, 6])
+def test_lk_integer_shift_fixed_point(ref, s):
+    L = _textured(48, 20, 11)
+    R = np.empty_like(L)
+    R[:, :] = L[:, np.clip(np.arange(48) + s, 0, 47)]
+    ML = np.ones_like(L, np.uint8)
+    # I_r(x + u) = I_l(x) at u = -s: zero residual, zero step
+    st, u, h, n, steps = ref.patch_lk(L, R, ML, 20, 6, 8, 5, -float(s))
+    assert st == 0 and n == 64 and h > 0
+    assert abs(u + s) < 1e-12 and np.all(np.abs(steps) < 1e-12)
+    # from a start inside the basin it converges to -s
+    st, u, h, n, steps = ref.patch_lk(L, R, ML, 20, 6, 8, 30, -float(s) + 0.6)
+    assert abs(u + s) < 1e-6
+    assert abs(steps[-1]) < 1e-6  # |b|/H -> 0
+
+
+def test_lk_sign_and_direction(ref):
+    """A right image shifted so that content moves left (positive disparity)
+    must give a negative u: the update direction and sign are pinned."""
+    L = _textured(40, 12, 3)
+    R = L[:, np.clip(np.arange(40) + 2, 0, 39)]  # R(x) = L(x+2) -> d = 2, u = -2
+    st, u, *_ = ref.patch_lk(L, R, np.ones_like(L, np.uint8), 16, 2, 8, 20, 0.0)
+    assert st == 0 and abs(u + 2.0) < 1e-5
+
+
+def test_lk_additive_offset_invariance(ref):
+    L = _textured(40, 12, 5)
+    R = L[:, np.clip(np.arange(40) + 1, 0, 39)] + 0.0
+    rng = np.random.default_rng(1)
+    R = R + rng.normal(0, 2, R.shape)
+    ML = np.ones_like(L, np.uint8)
+    a = ref.patch_lk(L, R, ML, 12, 2, 8, 10, 0.3)
+    b = ref.patch_lk(L, R + 17.0, ML, 12, 2, 8, 10, 0.3)
+    assert abs(a[1] - b[1]) < 1e-9
+
+
+def test_lk_ramp_is_degenerate(ref):
+    xx = np.tile(np.arange(30, dtype=float) * 2.0, (10, 1))
+    st, u, h, n, _ = ref.patch_lk(xx, xx, np.ones_like(xx, np.uint8), 8, 1, 8, 5, 0.7)
+    assert st == 1 and h < 1e-20 and u == 0.7
+    c = np.full((10, 30), 100.0)
+    assert ref.patch_lk(c, c, np.ones_like(c, np.uint8), 8, 1, 8, 5, 0.0)[0] == 1
+    # no valid pixel at all
+    assert ref.patch_lk(xx, xx, np.zeros_like(xx, np.uint8), 8, 1, 8, 5, 0.0)[0] == 1
+
+
+def test_lk_uses_left_valid_pixels_only(ref):
+    L = _textured(40, 12, 8)
+    R = L[:, np.clip(np.arange(40) + 3, 0, 39)].copy()
+    ML = np.ones_like(L, np.uint8)
+    ML[4, 14:18] = 0
+    L2 = L.copy()
+    L2[4, 14:18] = 999.0  # garbage on masked pixels must not matter...
+    a = ref.patch_lk(L, R, ML, 12, 2, 8, 12, -2.4)
+    b = ref.patch_lk(L2, R, ML, 12, 2, 8, 12, -2.4)
+    # ...except through the central-difference gradient of their neighbours
+    assert a[3] == b[3] == 60
+    assert abs(a[1] + 3) < 1e-6
+
+
+def _brute_argmin(ref, L, R, ML, x0, y0, p, lo, hi, step=1 / 1024):
+    us = np.arange(lo, hi + step / 2, step)
+    E = np.array([ref.patch_energy(L, R, ML, x0, y0, p, u) for u in us])
+    return us[np.argmin(E)], E
+
+
+def test_lk_matches_brute_force_ssd_noise_free(ref):
+    L = _textured(32, 16, 21)
+    for s in (1, 2):
+        R = L[:, np.clip(np.arange(32) + s, 0, 31)]
+        ML = np.ones_like(L, np.uint8)
+        ub, _ = _brute_argmin(ref, L, R, ML, 12, 4, 8, -s - 1.5, -s + 1.5)
+        st, u, *_ = ref.patch_lk(L, R, ML, 12, 4, 8, 20, -s + 0.4)
+        assert abs(u - ub) <= 1e-6
+
+
+@pytest.mark.parametrize("noise,gain", [(0.0, 1.0), (2.0, 4.0)])
+def test_lk_close_to_brute_force_ssd_subpixel(ref, noise, gain):
+    """Sub-pixel shift (R(x) = L(x + 1.37) by linear interpolation): the LK
+    fixed point (sum J e = 0) sits within 0.05 px of the brute-force minimum
+    of the mean-normalised SSD on a 1/1024 px grid.  With N(0, 2) noise the
+    texture is amplified so every patch has a unique, well-defined minimum."""
+    rng = np.random.default_rng(4)
+    L = _textured(32, 16, 22) * gain
+    R = np.array([[ref.sample_row(L[y], x + 1.37) for x in range(32)] for y in range(16)])
+    R = R + rng.normal(0, noise, R.shape)
+    ML = np.ones_like(L, np.uint8)
+    for x0 in (8, 12, 16):
+        ub, E = _brute_argmin(ref, L, R, ML, x0, 4, 8, -3.0, 0.0)
+        st, u, h, *_ = ref.patch_lk(L, R, ML, x0, 4, 8, 30, -1.0)
+        assert st == 0
+        assert abs(u - ub) <= 0.05
+
+
+# ---------------------------------------------------------------- posterior (eqs. 3-4)
+
+def test_posterior_is_softmax_of_window(ref):
+    rng = np.random.default_rng(0)
+    for _ in range(20):
+        E = rng.uniform(0, 3000, 5)
+        tau = rng.uniform(50, 2000)
+        assert abs(ref.posterior(E, 2, tau) - softmax(-E / tau)[2]) < 1e-12
+    # the five normalised values sum to one
+    E = rng.uniform(0, 500, 5)
+    tot = sum(ref.posterior(np.roll(E, -i), 2, 800.0) for i in range(-2, 3))
+    assert abs(tot - 1.0) < 1e-12
+
+
+def test_posterior_flat_and_sharp(ref):
+    assert abs(ref.posterior(np.full(5, 123.0), 2, 800.0) - 0.2) < 1e-15
+    assert abs(ref.posterior(np.array([1e9, 1e9, 0.0, 1e9, 1e9]), 2, 800.0) - 1.0) < 1e-15
+    # sigma_r -> infinity: uniform
+    assert abs(ref.posterior(np.array([5.0, 1.0, 0.0, 2.0, 9.0]), 2, 1e15) - 0.2) < 1e-12
+
+
+def test_textureless_patch_posterior_is_flat(ref):
+    """Sec. 2.2: on a textureless surface the residual barely changes with the
+    shift, so the window posterior is near uniform; textured is sharper."""
+    rng = np.random.default_rng(2)
+    flat = 100.0 + rng.normal(0, 0.05, (16, 40))
+    tex = _textured(40, 16, 9)
+    ML = np.ones((16, 40), np.uint8)
+    tau = 2 * 4.0**2 * 5**2
+
+    def post(img):
+        E = [ref.patch_energy(img, img, ML, 16, 4, 8, d) for d in (-1, -0.5, 0, 0.5, 1)]
+        return ref.posterior(np.array(E), 2, tau)
+    assert abs(post(flat) - 0.2) < 1e-3
+    assert post(tex) > 0.3
+
+
+def test_patch_energy_mean_normalised(ref):
+    L = _textured(24, 10, 1)
+    ML = np.ones_like(L, np.uint8)
+    # a pure brightness offset costs nothing
+    assert ref.patch_energy(L, L + 40.0, ML, 8, 1, 8, 0.0) < 1e-18
+    # brute: explicit residual for a half-pixel shift
+    u = 0.5
+    d = [(0.5 * L[y, x] + 0.5 * L[y, x + 1]) - L[y, x] for y in range(1, 9) for x in range(8, 16)]
+    d = np.array(d)
+    assert abs(ref.patch_energy(L, L, ML, 8, 1, 8, u) - ((d - d.mean()) ** 2).sum()) < 1e-8
+
+
+# ---------------------------------------------------------------- gate
+
+def test_valid_ratio_hand_counted(ref):
+    W, p = 12, 8
+    ML = np.ones((8, W), np.uint8)
+    MR = np.ones((8, W), np.uint8)
+    ML[0, 2:4] = 0          # 2 left-invalid pixels
+    MR[5, 6] = 0            # right pixel 6 invalid on row 5
+    # patch at x0 = 2, u = 0.5: right taps m = x, m+1 = x + 1 for x = 2..9
+    # row 5: pixels x = 5 (taps 5,6) and x = 6 (taps 6,7) lose -> 2
+    r = ref.valid_ratio(ML, MR, 2, 0, p, 0.5)
+    assert r == (64 - 2 - 2) / 64
+    # u = 2.5: x = 2..9 -> X = 4.5..11.5; X = 11.5 > W-1 = 11 is out of row (8 pixels)
+    r = ref.valid_ratio(ML, MR, 2, 0, p, 2.5)
+    # row 0: x=2,3 left invalid, x=9 out -> 5 ok; row 5: taps (m,m+1) with m=x+2:
+    # x=4 -> (6,7) bad, x=3 -> (5,6) bad, x=9 out -> 5 ok; other 6 rows: 7 ok
+    assert r == (5 + 5 + 6 * 7) / 64
+
+
+# ---------------------------------------------------------------- densify (Sec. 2.3)
+
+def test_spatial_weight_closed_form(ref):
+    p, s = 8, 4.0
+    assert ref.spatial_weight(0, 0, p, s) == ref.spatial_weight(7, 7, p, s)
+    assert abs(ref.spatial_weight(3, 3, p, s) - math.exp(-0.5 / (2 * s * s))) < 1e-15
+    assert abs(ref.spatial_weight(1, 1, 3, s) - 1.0) < 1e-15
+    assert abs(ref.spatial_weight(0, 1, 3, s) - math.exp(-1 / (2 * s * s))) < 1e-15
+
+
+def _grid_case(ref, W=29, H=21, seed=0, p=8, st=4):
+    rng = np.random.default_rng(seed)
+    nx, ny = ref.grid_count(W, p, st), ref.grid_count(H, p, st)
+    u = rng.uniform(-5, 1, (ny, nx))
+    post = rng.uniform(0.2, 1.0, (ny, nx))
+    status = np.where(rng.uniform(size=(ny, nx)) < 0.2, 3, 0).astype(np.int8)
+    return W, H, nx, ny, u, post, status
+
+
+def test_grid_snaps_last_patch_to_border(ref):
+    assert ref.grid_count(29, 8, 4) == 7
+    assert [ref.grid_pos(j, 29, 8, 4) for j in range(7)] == [0, 4, 8, 12, 16, 20, 21]
+    assert ref.grid_count(8, 8, 4) == 1 and ref.grid_count(7, 8, 4) == 0
+    assert ref.grid_count(640, 8, 4) == 159 and ref.grid_count(480, 8, 4) == 119
+
+
+def test_densify_is_convex_and_normalised(ref):
+    W, H, nx, ny, u, post, status = _grid_case(ref)
+    prm = ref.Params()
+    aw, awu = ref.densify(prm, W, H, u, post, status)
+    U = np.where(aw > 0, awu / np.where(aw > 0, aw, 1), np.nan)
+    # constant patch values reproduce the constant (weights normalise to one)
+    aw2, awu2 = ref.densify(prm, W, H, np.full_like(u, 2.5), post, status)
+    m = aw2 > 0
+    np.testing.assert_allclose(awu2[m] / aw2[m], 2.5, atol=1e-12)
+    # convexity against the kept covering patches, by brute force
+    for y in range(H):
+        for x in range(W):
+            cov = [u[jy, jx] for jy in range(ny) for jx in range(nx)
+                   if status[jy, jx] == 0
+                   and ref.grid_pos(jx, W, 8, 4) <= x < ref.grid_pos(jx, W, 8, 4) + 8
+                   and ref.grid_pos(jy, H, 8, 4) <= y < ref.grid_pos(jy, H, 8, 4) + 8]
+            if cov:
+                assert min(cov) - 1e-12 <= U[y, x] <= max(cov) + 1e-12
+            else:
+                assert np.isnan(U[y, x])
+
+
+def test_densify_single_patch_and_box_mean(ref):
+    W, H, nx, ny, u, post, status = _grid_case(ref, seed=3)
+    prm = ref.Params()
+    only = np.full_like(status, 3)
+    only[1, 2] = 0
+    aw, awu = ref.densify(prm, W, H, u, post, only)
+    x0, y0 = ref.grid_pos(2, W, 8, 4), ref.grid_pos(1, H, 8, 4)
+    blk = awu[y0:y0 + 8, x0:x0 + 8] / aw[y0:y0 + 8, x0:x0 + 8]
+    np.testing.assert_allclose(blk, u[1, 2], atol=1e-12)
+    assert (aw > 0).sum() == 64
+    # sigma_s -> inf and equal posteriors: plain mean of the covering patches
+    prm2 = ref.Params(sigma_s=1e9)
+    aw, awu = ref.densify(prm2, W, H, u, np.ones_like(post), status)
+    for (y, x) in [(0, 0), (5, 9), (10, 27), (20, 20)]:
+        cov = [u[jy, jx] for jy in range(ny) for jx in range(nx) if status[jy, jx] == 0
+               and ref.grid_pos(jx, W, 8, 4) <= x < ref.grid_pos(jx, W, 8, 4) + 8
+               and ref.grid_pos(jy, H, 8, 4) <= y < ref.grid_pos(jy, H, 8, 4) + 8]
+        assert abs(awu[y, x] / aw[y, x] - np.mean(cov)) < 1e-9
+
+
+def test_densify_weights_by_posterior(ref):
+    """Final equation of Sec. 2.3: with a flat spatial mask (sigma_s -> inf) a
+    pixel covered by two kept patches gets (p1 u1 + p2 u2) / (p1 + p2)."""
+    W, H = 12, 8
+    prm = ref.Params(sigma_s=1e12)
+    u = np.array([[1.0, 5.0]])
+    post = np.array([[0.25, 0.75]])
+    st = np.zeros((1, 2), np.int8)
+    aw, awu = ref.densify(prm, W, H, u, post, st)
+    U = awu / aw
+    np.testing.assert_allclose(U[:, :4], 1.0, atol=1e-12)       # first patch only
+    np.testing.assert_allclose(U[:, 8:], 5.0, atol=1e-12)       # second patch only
+    np.testing.assert_allclose(U[:, 4:8], (0.25 * 1 + 0.75 * 5) / 1.0, atol=1e-9)
+    # sharper spatial mask: each pixel leans to the nearer centre
+    aw, awu = ref.densify(ref.Params(sigma_s=1.0), W, H, u, np.ones((1, 2)), st)
+    U = awu / aw
+    x = 5
+    w1, w2 = math.exp(-(x - 3.5) ** 2 / 2), math.exp(-(x - 7.5) ** 2 / 2)
+    assert abs(U[3, x] - (w1 * 1 + w2 * 5) / (w1 + w2)) < 1e-9
+
+
+def test_densify_dis_mode_inverse_residual(ref):
+    """eq. (2) with a perfect match: every residual is 0, every weight
+    1/max(0,1) = 1, so the fusion is the box mean of the covering patches."""
+    W, H = 20, 12
+    L = _textured(W, H, 2)
+    prm = ref.Params(fusion=1)
+    nx, ny = ref.grid_count(W, 8, 4), ref.grid_count(H, 8, 4)
+    u = np.zeros((ny, nx))
+    aw, awu = ref.densify(prm, W, H, u, np.ones((ny, nx)), np.zeros((ny, nx), np.int8), L, L)
+    # aw counts covering patches
+    cnt = np.zeros((H, W))
+    for jy in range(ny):
+        for jx in range(nx):
+            x0, y0 = ref.grid_pos(jx, W, 8, 4), ref.grid_pos(jy, H, 8, 4)
+            cnt[y0:y0 + 8, x0:x0 + 8] += 1
+    np.testing.assert_allclose(aw, cnt, atol=1e-12)
+    # a residual of 3 gray levels weighs 1/9
+    R = L + 3.0
+    aw, _ = ref.densify(prm, W, H, u, np.ones((ny, nx)), np.zeros((ny, nx), np.int8), L, R)
+    np.testing.assert_allclose(aw, cnt / 9.0, atol=1e-12)
+
+
+# ---------------------------------------------------------------- end to end
+
+@pytest.mark.parametrize("W,H,s,levels", [(160, 120, 5, 3), (97, 61, 3, 2), (128, 64, 9, 3)])
+def test_e2e_integer_shift_recovered(ref, W, H, s, levels):
+    P = synth.integer_shift_pair(W, H, s, seed=W + s)
+    prm = ref.Params(levels=levels, iters=12)
+    d = ref.compute(P.left, P.right, prm)
+    inner = d[8:-8, s + 8:-8]
+    assert np.isfinite(inner).mean() > 0.99
+    assert np.nanmax(np.abs(inner - s)) <= 1e-3
+
+
+def test_e2e_constant_image_is_unestimated(ref):
+    c = np.full((40, 48), 100, np.uint8)
+    d = ref.compute(c, c, ref.Params(levels=2))
+    assert np.isnan(d).all()
+
+
+def test_e2e_single_level_nan_where_all_discarded(ref):
+    # left invalid (saturated) everywhere except a textured stripe
+    P = synth.integer_shift_pair(64, 32, 2, seed=5)
+    left = P.left.copy()
+    left[:, 40:] = 255
+    d = ref.compute(left, P.right, ref.Params(levels=1))
+    assert np.isnan(d[:, 48:]).all()
+    assert np.isfinite(d[8:24, 8:30]).all()
+
+
+def test_e2e_config_small_sanity(ref):
+    """160x120, disparity 0-16, 3 levels, 8 iterations: coverage and error
+    are sane (no number from the paper applies to generated pairs)."""
+    P = synth.make_pair(160, 120, 16, seed=1)
+    d = ref.compute(P.left, P.right, ref.Params(levels=3, iters=8))
+    m = np.isfinite(d)
+    assert m.mean() > 0.5
+    epe = np.abs(d - P.disp)[m].mean()
+    assert epe < np.abs(P.disp[m]).mean()
+
+
+def test_e2e_trace_is_consistent(ref):
+    P = synth.make_pair(96, 64, 8, seed=3)
+    prm = ref.Params(levels=2, iters=6)
+    d, tr = ref.compute(P.left, P.right, prm, trace=True)
+    np.testing.assert_array_equal(tr[0]["pyr_l"], P.left.astype(float))
+    np.testing.assert_allclose(tr[1]["pyr_l"], ref.blur_decimate(P.left.astype(float)), atol=1e-12)
+    np.testing.assert_array_equal(tr[1]["mask_r"], ref.mask_down(ref.mask_base(P.right)))
+    np.testing.assert_allclose(-tr[0]["field"], d, atol=0, equal_nan=True)
+    # coarsest level starts from zero; finer from twice the coarse field
+    assert np.all(tr[1]["u_init"] == 0)
+    k = (3, 4)
+    x0, y0 = ref.grid_pos(k[1], 96, 8, 4), ref.grid_pos(k[0], 64, 8, 4)
+    exp = 2 * ref.bilinear(tr[1]["field"], (x0 + 3.5) / 2, (y0 + 3.5) / 2)
+    assert abs(tr[0]["u_init"][k] - exp) < 1e-12
+    # status codes and posterior consistent
+    for l in tr:
+        st, po = tr[l]["status"], tr[l]["post"]
+        assert np.all(po[st != 0] == 0) and np.all((po[st == 0] > 0) & (po[st == 0] <= 1))
+
+
+def test_e2e_invalid_arguments(ref):
+    a = np.zeros((4, 4), np.uint8)
+    with pytest.raises(ValueError):
+        ref.compute(a, a, ref.Params(patch=8))
+    with pytest.raises(ValueError):
+        ref.compute(np.zeros((20, 20), np.uint8), np.zeros((20, 20), np.uint8), ref.Params(window=4))
