@@ -1,0 +1,184 @@
+/*
+ * bdis.h -- C ABI of the MI355X (gfx950) Bayesian Dense Inverse Search
+ * stereo library.
+ *
+ * Method: J. Song, Q. Zhu, J. Lin, M. Ghaffari, "Bayesian dense inverse
+ * searching algorithm for real-time stereo matching in minimally invasive
+ * surgery", arXiv 2106.07136.  One call runs the whole hot path on the GPU:
+ * image pyramid (Sec. 1, Fig. 1), per-patch inverse-compositional LK search
+ * along x (Sec. 2.1, eq. (1)), the windowed patch posterior (Sec. 2.2,
+ * eqs. (3)-(4)) and the spatial-Gaussian fusion of overlapping patches
+ * (Sec. 2.3, eq. (5) and the final equation), coarse to fine.
+ *
+ * Conventions shared by every entry point
+ *   - Images are rectified 8-bit grayscale, row-major, `pitch_bytes` apart.
+ *   - Output disparity is float32, row-major, `disp_pitch_elems` floats apart:
+ *     disp(x, y) = d means left pixel x matches right pixel x - d; NaN marks a
+ *     pixel no kept patch covers (Sec. 3.2: such pixels are not estimated).
+ *   - Image and output pointers are DEVICE pointers owned by the caller.  They
+ *     must stay valid until the work enqueued on `stream` has finished.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the null stream.
+ *     Calls enqueue and return; results are valid once the stream syncs.
+ *   - Every entry point validates its arguments before enqueuing anything.
+ *     On error nothing is enqueued, outputs are untouched, and a status < 0
+ *     is returned; bdis_last_error() then holds a message.  Nothing aborts,
+ *     throws or prints.
+ *   - A handle is bound to one device and is not thread-safe: use one handle
+ *     per host thread.  The handle owns its device workspace, grown on demand
+ *     (bdis_reserve pre-sizes it) and freed by bdis_destroy.
+ */
+#ifndef BDIS_H
+#define BDIS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define BDIS_API __attribute__((visibility("default")))
+#else
+#define BDIS_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BDIS_OK = 0,
+    BDIS_E_INVALID_ARG = -1,  /* bad pointer, size or parameter             */
+    BDIS_E_NO_DEVICE = -2,    /* no usable gfx950 device                     */
+    BDIS_E_OOM = -3,          /* device allocation failed                    */
+    BDIS_E_HIP = -4,          /* a HIP runtime call failed (see last_error)  */
+    BDIS_E_UNSUPPORTED = -5,  /* valid request this build does not handle    */
+    BDIS_E_STATE = -6         /* call out of order (e.g. trace before run)   */
+} bdis_status;
+
+typedef enum { BDIS_FUSION_BAYES = 0, BDIS_FUSION_DIS = 1 } bdis_fusion;
+typedef enum { BDIS_INIT_ZERO = 0, BDIS_INIT_LEARNED = 1 } bdis_init;
+
+/* Method parameters.  Defaults (bdis_default_params) follow Sec. 3 of the
+ * paper: sigma_r = sigma_s = 4, five window samples 0.5 px apart, gamma 0.75;
+ * conv_tol = 0.05. */
+typedef struct {
+    uint32_t struct_size;     /* = sizeof(bdis_params), checked             */
+    int32_t levels;           /* pyramid levels; 0 = auto from max_disparity:
+                                 1 + ceil(log2(max_disparity / 4)); always cut
+                                 so the coarsest level holds a whole patch   */
+    float max_disparity;      /* level-0 pixels, used when levels == 0      */
+    int32_t patch;            /* p, square patch side: 4, 6, 8, 10, 12, 16  */
+    int32_t stride;           /* st, patch grid spacing, 1 <= st <= p        */
+    int32_t iters;            /* K, LK iterations per level (no early exit)  */
+    float sigma_r;            /* eq. (4) brightness spread, gray levels      */
+    float sigma_s;            /* eq. (5) spatial spread, level pixels        */
+    int32_t window;           /* samples in the posterior window (odd, <=15) */
+    float window_step;        /* spacing of the window samples, level px     */
+    float gamma;              /* valid-pixel ratio below which a patch is
+                                 discarded, in [0, 1]                         */
+    int32_t s_mode;           /* eq. (4) "s": 0 = window samples, 1 = patch  */
+    int32_t fusion;           /* bdis_fusion                                  */
+    int32_t valid_lo;         /* a pixel is valid iff valid_lo <= v <= valid_hi */
+    int32_t valid_hi;
+    float eps_h;              /* degenerate patch iff H <= eps_h * n          */
+    float conv_tol;           /* Sec. 3.2 "does not converge": a patch whose
+                                 last LK step exceeds conv_tol level pixels
+                                 is discarded; <= 0 turns the test off       */
+    int32_t precision;        /* arithmetic of the GPU path: 0 = FP64 (the
+                                 default: matches the FP64 reference to
+                                 rounding), 1 = FP32                          */
+    int32_t init;             /* bdis_init                                    */
+    float conf_threshold;     /* learned init: confidence gate               */
+    int32_t learned_fine_levels; /* learned init: levels run below the net   */
+    int32_t learned_iters;    /* learned init: LK iterations per level       */
+    int32_t autotune;         /* batch: 1 = per-size (patch, stride) from the
+                                 tuning table set by bdis_set_tuning          */
+} bdis_params;
+
+typedef struct bdis_ctx bdis_t;
+
+/* One stereo pair for bdis_compute_batch (device pointers, caller-owned). */
+typedef struct {
+    const uint8_t *left;
+    const uint8_t *right;
+    float *disp;
+    int32_t width, height, pitch_bytes, disp_pitch_elems;
+} bdis_pair;
+
+/* Sizes the library derives for one image under given parameters. */
+typedef struct {
+    int32_t levels;                 /* levels actually run                   */
+    int32_t width[16], height[16];  /* level sizes, level 0 = input          */
+    int32_t nx[16], ny[16];         /* patch grid per level                  */
+    int64_t patches;                /* patches over all levels               */
+    int64_t workspace_bytes;        /* device workspace for one pair         */
+} bdis_plan_info;
+
+/* Fills *p with the defaults above.  p may not be NULL. */
+BDIS_API void bdis_default_params(bdis_params *p);
+
+/* Host-only: validates p against a width x height image and describes the
+ * pyramid and patch grids it implies.  No device needed.
+ * Returns BDIS_OK or BDIS_E_INVALID_ARG / BDIS_E_UNSUPPORTED. */
+BDIS_API bdis_status bdis_plan(const bdis_params *p, int32_t width, int32_t height, bdis_plan_info *out);
+
+/* Creates a handle on HIP device `device`.  p is copied; NULL = defaults.
+ * Errors: BDIS_E_INVALID_ARG (bad params or out == NULL), BDIS_E_NO_DEVICE
+ * (no such device, or not gfx950), BDIS_E_HIP.  On error *out is NULL. */
+BDIS_API bdis_status bdis_create(const bdis_params *p, int device, bdis_t **out);
+
+/* Replaces the handle's parameters (same validation as bdis_create). */
+BDIS_API bdis_status bdis_set_params(bdis_t *h, const bdis_params *p);
+
+/* Grows the workspace so pairs up to width x height (and batches of up to
+ * n_pairs such pairs) need no allocation inside bdis_compute*. */
+BDIS_API bdis_status bdis_reserve(bdis_t *h, int32_t width, int32_t height, int32_t n_pairs);
+
+/* Disparity of one rectified pair, coarse to fine over the whole pyramid
+ * (Sec. 2.1-2.3).  left/right: device uint8, width x height, pitch_bytes >=
+ * width.  disp: device float32, disp_pitch_elems >= width.  width and height
+ * must be at least the patch side. */
+BDIS_API bdis_status bdis_compute(bdis_t *h, const uint8_t *left, const uint8_t *right, int32_t width,
+                         int32_t height, int32_t pitch_bytes, float *disp,
+                         int32_t disp_pitch_elems, void *stream);
+
+/* The same for n independent pairs of mixed sizes in one pass: each kernel of
+ * the path is launched once for all pairs (level by level, coarsest first).
+ * `pairs` is a HOST array of n entries, read during the call only.  Each
+ * pair's result equals bdis_compute on that pair with the same parameters
+ * (bit for bit).  With params.autotune = 1, each pair uses the (patch,
+ * stride) that bdis_set_tuning recorded for its size class. */
+BDIS_API bdis_status bdis_compute_batch(bdis_t *h, const bdis_pair *pairs, int32_t n, void *stream);
+
+/* Autotuner table: for images whose width is <= max_width[i] (ascending),
+ * use patch[i] and stride[i].  n <= 8.  n = 0 clears it. */
+BDIS_API bdis_status bdis_set_tuning(bdis_t *h, int32_t n, const int32_t *max_width, const int32_t *patch,
+                            const int32_t *stride);
+
+/* Stage taps of the most recent single-pair bdis_compute, for parity checks.
+ * Synchronises the handle's last stream, then copies to HOST memory `dst`
+ * (capacity `bytes`):
+ *   stage 0: left pyramid level `level` (float, W_l x H_l; level >= 1)
+ *   stage 1: right pyramid level (float, level >= 1)
+ *   stage 2: per-patch shift u after the LK iterations (float, ny x nx)
+ *   stage 3: per-patch fusion weight (float, ny x nx; 0 = discarded)
+ *   stage 4: per-patch outcome (int8: 0 kept, 1 degenerate, 2 diverged,
+ *            3 gated by gamma)
+ *   stage 5: dense field U_l in level pixels (float, W_l x H_l; level >= 1)
+ *   stage 6: per-patch initial shift u0 (float, ny x nx)
+ * Pyramid values hold validity in the sign bit (negative or -0 = invalid).
+ * Errors: BDIS_E_STATE (no single-pair compute yet), BDIS_E_INVALID_ARG. */
+BDIS_API bdis_status bdis_debug_stage(bdis_t *h, int32_t stage, int32_t level, void *dst, size_t bytes);
+
+/* Frees the handle and its workspace; NULL is allowed. */
+BDIS_API void bdis_destroy(bdis_t *h);
+
+/* Static text for a status code. */
+BDIS_API const char *bdis_status_string(bdis_status s);
+
+/* Last error message of h, or of the calling thread's last failed
+ * bdis_create / bdis_plan when h is NULL.  Never NULL. */
+BDIS_API const char *bdis_last_error(const bdis_t *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BDIS_H */

@@ -35,7 +35,7 @@ class _Params(C.Structure):
                 ("iters", C.c_int), ("sigma_r", C.c_double), ("sigma_s", C.c_double),
                 ("window", C.c_int), ("window_step", C.c_double), ("gamma", C.c_double),
                 ("s_mode", C.c_int), ("fusion", C.c_int), ("valid_lo", C.c_int),
-                ("valid_hi", C.c_int), ("eps_h", C.c_double)]
+                ("valid_hi", C.c_int), ("eps_h", C.c_double), ("conv_tol", C.c_double)]
 
 
 _PD = C.POINTER(C.c_double)
@@ -54,7 +54,10 @@ class _Trace(C.Structure):
 @dataclass
 class Params:
     """Method parameters; defaults follow Sec. 3 (sigma_r = sigma_s = 4,
-    five window samples 0.5 px apart, gamma = 0.75 at 640x480)."""
+    five window samples 0.5 px apart, gamma = 0.75 at 640x480).  conv_tol is
+    the reading of Sec. 3.2's "discarding the patch that does not converge":
+    a patch whose last LK step is larger than conv_tol level pixels is
+    discarded (<= 0 turns the test off)."""
     levels: int = 5
     patch: int = 8
     stride: int = 4
@@ -69,11 +72,12 @@ class Params:
     valid_lo: int = 1
     valid_hi: int = 254
     eps_h: float = 1e-6
+    conv_tol: float = 0.05
 
     def _c(self) -> _Params:
         return _Params(self.levels, self.patch, self.stride, self.iters, self.sigma_r,
                        self.sigma_s, self.window, self.window_step, self.gamma, self.s_mode,
-                       self.fusion, self.valid_lo, self.valid_hi, self.eps_h)
+                       self.fusion, self.valid_lo, self.valid_hi, self.eps_h, self.conv_tol)
 
 
 _lib = None

@@ -52,6 +52,7 @@ typedef struct {
     int valid_lo;        /* pixel valid iff valid_lo <= v <= valid_hi          */
     int valid_hi;
     double eps_h;        /* degenerate patch: H <= eps_h * n                   */
+    double conv_tol;     /* not converged: |last LK step| > conv_tol (<= 0: off) */
 } ref_params;
 
 typedef struct {
@@ -386,8 +387,9 @@ static void ref_patch(const ref_params *P, const double *L, const double *R, con
     o->u0 = u0;
     o->post = 0.0;
     o->valid_ratio = 0.0;
+    double steps[1024];
     o->status = ref_patch_lk(L, R, G, ML, W, H, x0, y0, p, P->iters, u0, P->eps_h,
-                             &o->u, &o->H, &o->n, NULL);
+                             &o->u, &o->H, &o->n, steps);
     if (o->status != REF_KEPT)
         return;
     if (P->fusion == 1) { /* DIS eq. (2): no window, no gate, no discard */
@@ -400,7 +402,8 @@ static void ref_patch(const ref_params *P, const double *L, const double *R, con
     /* Sec. 3.2: the patch that does not converge is discarded.  Reading:
      * a non-finite shift, or one that left the initial estimate by more
      * than a patch side. */
-    if (!isfinite(o->u) || fabs(o->u - u0) > (double)p) {
+    if (!isfinite(o->u) || fabs(o->u - u0) > (double)p ||
+        (P->conv_tol > 0 && P->iters > 0 && !(fabs(steps[P->iters - 1]) <= P->conv_tol))) {
         o->status = REF_DIVERGED;
         return;
     }
@@ -480,7 +483,7 @@ int ref_compute(const ref_params *P, const uint8_t *Limg, const uint8_t *Rimg, i
                 int pitch, double *disp, ref_trace *trace)
 {
     if (!P || !Limg || !Rimg || !disp || W < 1 || H < 1 || pitch < W || P->patch < 1 ||
-        P->stride < 1 || P->iters < 0 || P->window < 1 || (P->window % 2) == 0 ||
+        P->stride < 1 || P->iters < 0 || P->iters > 1000 || P->window < 1 || (P->window % 2) == 0 ||
         P->window > 63 || W < P->patch || H < P->patch)
         return -1;
     int NL = ref_num_levels(W, H, P->patch, P->levels);

@@ -1,0 +1,228 @@
+"""ctypes binding of the C ABI in include/bdis.h.
+
+Argument marshalling only: every step of the stereo path runs in the HIP
+kernels of libbdis.so.  Device memory and streams come from torch tensors and
+torch streams.  If libbdis.so is missing this module raises; there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, fields
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbdis.so")
+
+OK, E_INVALID_ARG, E_NO_DEVICE, E_OOM, E_HIP, E_UNSUPPORTED, E_STATE = 0, -1, -2, -3, -4, -5, -6
+STAGE_PYR_L, STAGE_PYR_R, STAGE_U, STAGE_W, STAGE_STATUS, STAGE_FIELD, STAGE_U0 = range(7)
+
+
+class BdisError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"bdis status {status}: {msg}")
+        self.status = status
+
+
+class CParams(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("levels", C.c_int32), ("max_disparity", C.c_float),
+                ("patch", C.c_int32), ("stride", C.c_int32), ("iters", C.c_int32),
+                ("sigma_r", C.c_float), ("sigma_s", C.c_float), ("window", C.c_int32),
+                ("window_step", C.c_float), ("gamma", C.c_float), ("s_mode", C.c_int32),
+                ("fusion", C.c_int32), ("valid_lo", C.c_int32), ("valid_hi", C.c_int32),
+                ("eps_h", C.c_float), ("conv_tol", C.c_float), ("precision", C.c_int32),
+                ("init", C.c_int32), ("conf_threshold", C.c_float),
+                ("learned_fine_levels", C.c_int32), ("learned_iters", C.c_int32),
+                ("autotune", C.c_int32)]
+
+
+class CPair(C.Structure):
+    _fields_ = [("left", C.c_void_p), ("right", C.c_void_p), ("disp", C.c_void_p),
+                ("width", C.c_int32), ("height", C.c_int32), ("pitch_bytes", C.c_int32),
+                ("disp_pitch_elems", C.c_int32)]
+
+
+class CPlan(C.Structure):
+    _fields_ = [("levels", C.c_int32), ("width", C.c_int32 * 16), ("height", C.c_int32 * 16),
+                ("nx", C.c_int32 * 16), ("ny", C.c_int32 * 16), ("patches", C.c_int64),
+                ("workspace_bytes", C.c_int64)]
+
+
+@dataclass
+class Params:
+    """Mirror of bdis_params (defaults = bdis_default_params)."""
+    levels: int = 5
+    max_disparity: float = 64.0
+    patch: int = 8
+    stride: int = 4
+    iters: int = 12
+    sigma_r: float = 4.0
+    sigma_s: float = 4.0
+    window: int = 5
+    window_step: float = 0.5
+    gamma: float = 0.75
+    s_mode: int = 0
+    fusion: int = 0
+    valid_lo: int = 1
+    valid_hi: int = 254
+    eps_h: float = 1e-6
+    conv_tol: float = 0.05
+    precision: int = 0
+    init: int = 0
+    conf_threshold: float = 0.5
+    learned_fine_levels: int = 2
+    learned_iters: int = 12
+    autotune: int = 0
+
+    def to_c(self) -> CParams:
+        c = CParams()
+        c.struct_size = C.sizeof(CParams)
+        for f in fields(self):
+            setattr(c, f.name, getattr(self, f.name))
+        return c
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, i32 = C.c_void_p, C.c_int32
+        L.bdis_default_params.argtypes = [C.POINTER(CParams)]
+        L.bdis_default_params.restype = None
+        L.bdis_plan.argtypes = [C.POINTER(CParams), i32, i32, C.POINTER(CPlan)]
+        L.bdis_create.argtypes = [C.POINTER(CParams), C.c_int, C.POINTER(vp)]
+        L.bdis_set_params.argtypes = [vp, C.POINTER(CParams)]
+        L.bdis_reserve.argtypes = [vp, i32, i32, i32]
+        L.bdis_compute.argtypes = [vp, vp, vp, i32, i32, i32, vp, i32, vp]
+        L.bdis_compute_batch.argtypes = [vp, C.POINTER(CPair), i32, vp]
+        L.bdis_set_tuning.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
+        L.bdis_debug_stage.argtypes = [vp, i32, i32, vp, C.c_size_t]
+        L.bdis_destroy.argtypes = [vp]
+        L.bdis_destroy.restype = None
+        L.bdis_status_string.argtypes = [C.c_int]
+        L.bdis_status_string.restype = C.c_char_p
+        L.bdis_last_error.argtypes = [vp]
+        L.bdis_last_error.restype = C.c_char_p
+        for name in ("bdis_plan", "bdis_create", "bdis_set_params", "bdis_reserve", "bdis_compute",
+                     "bdis_compute_batch", "bdis_set_tuning", "bdis_debug_stage"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status: int, handle=None):
+    if status != OK:
+        msg = lib().bdis_last_error(handle).decode(errors="replace")
+        raise BdisError(status, msg)
+
+
+def default_params() -> Params:
+    c = CParams()
+    lib().bdis_default_params(C.byref(c))
+    return Params(**{f.name: getattr(c, f.name) for f in fields(Params)})
+
+
+def plan(params: Params, width: int, height: int) -> dict:
+    info = CPlan()
+    _check(lib().bdis_plan(C.byref(params.to_c()), width, height, C.byref(info)))
+    L = info.levels
+    return dict(levels=L, width=list(info.width[:L]), height=list(info.height[:L]),
+                nx=list(info.nx[:L]), ny=list(info.ny[:L]), patches=info.patches,
+                workspace_bytes=info.workspace_bytes)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Bdis:
+    """A handle on one device.  ``compute`` takes uint8 device tensors."""
+
+    def __init__(self, params: Params | None = None, device: int = 0):
+        self.params = params or Params()
+        self.device = device
+        h = C.c_void_p()
+        _check(lib().bdis_create(C.byref(self.params.to_c()), device, C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().bdis_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params: Params):
+        _check(lib().bdis_set_params(self._h, C.byref(params.to_c())), self._h)
+        self.params = params
+
+    def reserve(self, width: int, height: int, n_pairs: int = 1):
+        _check(lib().bdis_reserve(self._h, width, height, n_pairs), self._h)
+
+    def set_tuning(self, table):
+        """table: list of (max_width, patch, stride), ascending max_width."""
+        n = len(table)
+        arr = C.c_int32 * max(n, 1)
+        mw = arr(*[t[0] for t in table])
+        pp = arr(*[t[1] for t in table])
+        ss = arr(*[t[2] for t in table])
+        _check(lib().bdis_set_tuning(self._h, n, mw, pp, ss), self._h)
+
+    def compute(self, left, right, out=None, stream=None):
+        import torch
+        if left.dtype != torch.uint8 or right.dtype != torch.uint8:
+            raise TypeError("left/right must be uint8")
+        if left.shape != right.shape or left.dim() != 2 or not left.is_cuda or not right.is_cuda:
+            raise ValueError("left/right must be equal 2-D device tensors")
+        if left.stride(1) != 1 or right.stride(1) != 1 or left.stride(0) != right.stride(0):
+            raise ValueError("rows must be contiguous with equal pitch")
+        H, W = left.shape
+        if out is None:
+            out = torch.empty((H, W), dtype=torch.float32, device=left.device)
+        if out.shape != (H, W) or out.dtype != torch.float32 or out.stride(1) != 1:
+            raise ValueError("out must be a float32 (H, W) tensor with contiguous rows")
+        _check(lib().bdis_compute(self._h, left.data_ptr(), right.data_ptr(), W, H, left.stride(0),
+                                  out.data_ptr(), out.stride(0), _stream_ptr(stream)), self._h)
+        self._last_shape = (W, H)
+        return out
+
+    def compute_batch(self, lefts, rights, outs=None, stream=None):
+        import torch
+        n = len(lefts)
+        if outs is None:
+            outs = [torch.empty(l.shape, dtype=torch.float32, device=l.device) for l in lefts]
+        arr = (CPair * n)()
+        for i, (l, r, o) in enumerate(zip(lefts, rights, outs)):
+            if l.dtype != torch.uint8 or r.dtype != torch.uint8 or l.shape != r.shape:
+                raise ValueError(f"pair {i}: uint8 tensors of equal shape required")
+            if l.stride(1) != 1 or l.stride(0) != r.stride(0) or o.stride(1) != 1:
+                raise ValueError(f"pair {i}: rows must be contiguous with equal pitch")
+            arr[i] = CPair(l.data_ptr(), r.data_ptr(), o.data_ptr(), l.shape[1], l.shape[0],
+                           l.stride(0), o.stride(0))
+        _check(lib().bdis_compute_batch(self._h, arr, n, _stream_ptr(stream)), self._h)
+        return outs
+
+    def debug_stage(self, stage: int, level: int):
+        """Host numpy copy of one stage tap of the last single-pair compute."""
+        import numpy as np
+        info = plan(self.params, *self._last_shape)
+        if stage in (STAGE_PYR_L, STAGE_PYR_R, STAGE_FIELD):
+            shape = (info["height"][level], info["width"][level])
+        else:
+            shape = (info["ny"][level], info["nx"][level])
+        dt = np.int8 if stage == STAGE_STATUS else (np.float64 if self.params.precision == 0 else np.float32)
+        a = np.empty(shape, dt)
+        _check(lib().bdis_debug_stage(self._h, stage, level, a.ctypes.data, a.nbytes), self._h)
+        return a

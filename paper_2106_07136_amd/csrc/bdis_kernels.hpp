@@ -1,0 +1,434 @@
+// bdis_kernels.hpp -- gfx950 kernels of the BDIS stereo hot path.
+//
+// Paper: J. Song et al., "Bayesian dense inverse searching algorithm for
+// real-time stereo matching in minimally invasive surgery", arXiv 2106.07136.
+//
+// Three kernels per pyramid level, each launched once for every pair of a
+// call (a "job" is one pair at one level):
+//   k_pyr    blur + decimate one level of the left and right pyramids
+//            (Sec. 1, Fig. 1), validity carried in the sign bit;
+//   k_lk     per-patch inverse-compositional LK along x (Sec. 2.1, eq. (1)),
+//            then the windowed posterior (Sec. 2.2, eqs. (3)-(4)) and the
+//            discard gates (Sec. 3 gamma, Sec. 3.2);
+//   k_dense  per-pixel gather of the covering patches with the spatial
+//            Gaussian mask times the posterior as weight (Sec. 2.3, eq. (5)
+//            and the final equation), or eq. (2)'s inverse residual.
+//
+// Arithmetic type T: double (default; matches the FP64 reference to rounding)
+// or float.  Data layout: level 0 is the caller's uint8 image (pitch in
+// bytes); levels >= 1 are T images of the level size whose sign bit marks
+// invalid pixels (value = |x|), so one load gives intensity and validity.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bdis {
+
+constexpr int kBlock = 256;
+
+// Method constants for one launch.
+struct KParams {
+    int iters;           // LK iterations, no early exit
+    int window;          // posterior window samples (odd)
+    double window_step;  // spacing of the samples, level px
+    double tau;          // 2 sigma_r^2 s^2, eq. (4)
+    int min_valid;       // gamma gate: kept iff valid count >= min_valid
+    int fusion;          // 0 Bayesian, 1 DIS eq. (2)
+    int vlo, vhi;        // level-0 validity band
+    double eps_h;        // degenerate iff H <= eps_h * n
+    double conv_tol;     // not converged iff |last LK step| > conv_tol (<= 0: off)
+};
+
+struct PyrJob {
+    const void *src_l, *src_r;  // level l-1 (uint8 when l-1 == 0)
+    int src_pitch;              // elements
+    int ws, hs;                 // level l-1 size
+    void *dst_l, *dst_r;        // level l (arithmetic type), pitch = wd
+    int wd, hd;
+    int block0;
+};
+
+struct LkJob {
+    const void *L, *R;     // this level's images
+    int pitch;             // elements
+    int W, H;
+    const void *Uc;        // coarse field (level + 1), pitch Wc; null at coarsest
+    int Wc, Hc;
+    int nx, ny, stride;
+    void *rec_u, *rec_w, *rec_u0;  // arithmetic type
+    int8_t *rec_st;
+    int block0;
+};
+
+struct DenseJob {
+    const void *L, *R;     // images (DIS fusion only)
+    int pitch;
+    int W, H, patch, stride, nx, ny;
+    const void *rec_u, *rec_w;
+    const void *gtab;      // patch x patch spatial weights
+    const void *Uc;        // fallback source (0 < l < L-1)
+    int Wc, Hc;
+    int mode;              // 0: fallback to 2*Uc, 1: zero (coarsest), 2: NaN (level 0)
+    void *U;               // level field out (pitch W), or null
+    float *out;            // level 0: disparity out (= -U), or null
+    int out_pitch;
+    int block0;
+};
+
+// ---------------------------------------------------------------- helpers
+
+template <typename Job>
+__device__ __forceinline__ int find_job(const Job *jobs, int njobs, int b) {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].block0 <= b) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int reflect101(int i, int n) {
+    if (n == 1) return 0;
+    while (i < 0 || i >= n) {
+        if (i < 0) i = -i;
+        if (i >= n) i = 2 * (n - 1) - i;
+    }
+    return i;
+}
+
+__device__ __forceinline__ int grid_pos(int j, int n, int p, int st) {
+    int x = j * st;
+    return x < n - p ? x : n - p;
+}
+
+// Value and validity of one pixel.  U8: the caller's image and the level-0
+// intensity band; float: sign bit = invalid.
+template <typename T, bool U8>
+__device__ __forceinline__ T pix(const void *img, size_t idx, const KParams &kp, bool &valid) {
+    if constexpr (U8) {
+        int v = static_cast<const uint8_t *>(img)[idx];
+        valid = v >= kp.vlo && v <= kp.vhi;
+        return static_cast<T>(v);
+    } else {
+        T v = static_cast<const T *>(img)[idx];
+        valid = !signbit(v);
+        return fabs(v);
+    }
+}
+
+template <typename T, bool U8>
+__device__ __forceinline__ T pixv(const void *img, size_t idx) {
+    if constexpr (U8) return static_cast<T>(static_cast<const uint8_t *>(img)[idx]);
+    else return fabs(static_cast<const T *>(img)[idx]);
+}
+
+// Sum over aligned segments of SEG lanes; every lane of a segment receives
+// the bitwise-same total (the butterfly adds commuting pairs).
+template <int SEG, typename T>
+__device__ __forceinline__ T seg_sum(T v) {
+#pragma unroll
+    for (int m = SEG / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, SEG);
+    return v;
+}
+template <int SEG>
+__device__ __forceinline__ int seg_sum_i(int v) {
+#pragma unroll
+    for (int m = SEG / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, SEG);
+    return v;
+}
+
+// Bilinear read of a coarse field, coordinates clamped to the field.
+template <typename T>
+__device__ __forceinline__ T bilinear(const T *F, int W, int H, T X, T Y) {
+    X = fmin(fmax(X, T(0)), (T)(W - 1));
+    Y = fmin(fmax(Y, T(0)), (T)(H - 1));
+    int mx = (int)floor(X), my = (int)floor(Y);
+    mx = min(mx, W - 2); my = min(my, H - 2);
+    mx = max(mx, 0); my = max(my, 0);
+    T fx = W > 1 ? X - (T)mx : T(0), fy = H > 1 ? Y - (T)my : T(0);
+    int mx1 = W > 1 ? mx + 1 : mx, my1 = H > 1 ? my + 1 : my;
+    T a = (T(1) - fx) * F[(size_t)my * W + mx] + fx * F[(size_t)my * W + mx1];
+    T b = (T(1) - fx) * F[(size_t)my1 * W + mx] + fx * F[(size_t)my1 * W + mx1];
+    return (T(1) - fy) * a + fy * b;
+}
+
+// Right-image sample at column xi + uf of one row (xi integer, 0 <= uf < 1),
+// the coordinate clamped to [0, W-1] as in the linear sampler of eq. (1).
+// Splitting the shift into integer and fraction keeps the fraction exact.
+template <typename T, bool U8>
+__device__ __forceinline__ T sample_row(const void *img, size_t row0, int W, int xi, T uf) {
+    if (xi < 0) return pixv<T, U8>(img, row0);
+    if (xi >= W - 1) return pixv<T, U8>(img, row0 + (W - 1));
+    T a = pixv<T, U8>(img, row0 + xi), b = pixv<T, U8>(img, row0 + xi + 1);
+    return (T(1) - uf) * a + uf * b;
+}
+
+// ---------------------------------------------------------------- pyramid
+
+// One coarse pixel of both images: binomial [1 4 6 4 1]/16 in x then y with
+// reflect-101 borders, taken at the even fine position; valid iff all
+// existing 2x2 fine children are valid.  In double precision every level up
+// to the fifth is exact (dyadic sums of 8-bit values).
+template <typename T, bool U8>
+__global__ __launch_bounds__(kBlock) void k_pyr(const PyrJob *jobs, int njobs, KParams kp) {
+    const PyrJob &J = jobs[find_job(jobs, njobs, (int)blockIdx.x)];
+    int i = ((int)blockIdx.x - J.block0) * kBlock + (int)threadIdx.x;
+    if (i >= J.wd * J.hd) return;
+    int yc = i / J.wd, xc = i - yc * J.wd;
+    int x = 2 * xc, y = 2 * yc;
+    const T w5[5] = {T(1) / 16, T(4) / 16, T(6) / 16, T(4) / 16, T(1) / 16};
+    int cols[5], rows[5];
+#pragma unroll
+    for (int a = 0; a < 5; a++) {
+        cols[a] = reflect101(x + a - 2, J.ws);
+        rows[a] = reflect101(y + a - 2, J.hs);
+    }
+#pragma unroll
+    for (int img = 0; img < 2; img++) {
+        const void *src = img ? J.src_r : J.src_l;
+        T acc = 0;
+#pragma unroll
+        for (int a = 0; a < 5; a++) {
+            size_t r0 = (size_t)rows[a] * J.src_pitch;
+            T h = 0;
+#pragma unroll
+            for (int b = 0; b < 5; b++) h += w5[b] * pixv<T, U8>(src, r0 + cols[b]);
+            acc += w5[a] * h;
+        }
+        bool ok = true;
+#pragma unroll
+        for (int dy = 0; dy < 2; dy++)
+#pragma unroll
+            for (int dx = 0; dx < 2; dx++) {
+                int yy = y + dy, xx = x + dx;
+                if (yy < J.hs && xx < J.ws) {
+                    bool v;
+                    (void)pix<T, U8>(src, (size_t)yy * J.src_pitch + xx, kp, v);
+                    ok = ok && v;
+                }
+            }
+        T *dst = static_cast<T *>(img ? J.dst_r : J.dst_l);
+        dst[i] = ok ? acc : -acc;  // -0 keeps the invalid flag for a zero value
+    }
+}
+
+// ---------------------------------------------------------------- LK + posterior
+
+enum { ST_KEPT = 0, ST_DEGENERATE = 1, ST_DIVERGED = 2, ST_GATED = 3 };
+
+// One patch per segment of SEG lanes, one patch row per lane (lanes >= P of a
+// 16-lane segment idle).  Per lane: the template row, the mean-normalised
+// template gradient J (the inverse-compositional Jacobian, computed once on
+// the left patch, Sec. 2.1), then K Gauss-Newton steps u <- u - sum(J e)/H
+// sampling the right row at the current shift.  Because sum J = 0 over the
+// left-valid pixels, sum J e equals sum J d without subtracting the residual
+// mean.  A patch is kept only if the iteration converged (last step within
+// conv_tol, shift within a patch side of its start).  Then the window
+// energies E_i = sum (d - mean d)^2 at u + (i - c) step and the posterior
+// p = 1 / sum_i exp(-(E_i - E_c) / tau), and the gamma gate.
+template <typename T, int P, bool U8>
+__global__ __launch_bounds__(kBlock) void k_lk(const LkJob *jobs, int njobs, KParams kp) {
+    constexpr int SEG = P <= 8 ? 8 : 16;
+    constexpr int PPB = kBlock / SEG;
+    const LkJob &J = jobs[find_job(jobs, njobs, (int)blockIdx.x)];
+    const int np = J.nx * J.ny;
+    const int slot = (int)threadIdx.x / SEG, r = (int)threadIdx.x % SEG;
+    const int k_raw = ((int)blockIdx.x - J.block0) * PPB + slot;
+    const bool live = k_raw < np;
+    const int k = live ? k_raw : np - 1;  // idle segments shadow the last patch
+    const int jy = k / J.nx, jx = k - jy * J.nx;
+    const int x0 = grid_pos(jx, J.W, P, J.stride), y0 = grid_pos(jy, J.H, P, J.stride);
+    const bool row_on = r < P;
+    const int y = y0 + (row_on ? r : 0);
+    const int W = J.W;
+    const size_t row0 = (size_t)y * J.pitch;
+
+    // initial shift: twice the coarse field at the patch centre (Sec. 2.1)
+    T u0 = 0;
+    if (J.Uc) {
+        T cx = (T)x0 + T(0.5) * (T)(P - 1), cy = (T)y0 + T(0.5) * (T)(P - 1);
+        u0 = T(2) * bilinear<T>(static_cast<const T *>(J.Uc), J.Wc, J.Hc, T(0.5) * cx, T(0.5) * cy);
+    }
+
+    // template row, gradient, validity
+    T Tv[P], Jg[P];
+    uint32_t vmask = 0;
+    T gsum = 0;
+    int nloc = 0;
+#pragma unroll
+    for (int c = 0; c < P; c++) {
+        int x = x0 + c;
+        bool v;
+        Tv[c] = pix<T, U8>(J.L, row0 + x, kp, v);
+        T gp = pixv<T, U8>(J.L, row0 + min(x + 1, W - 1));
+        T gm = pixv<T, U8>(J.L, row0 + max(x - 1, 0));
+        Jg[c] = T(0.5) * (gp - gm);
+        v = v && row_on;
+        vmask |= (uint32_t)v << c;
+        if (v) { gsum += Jg[c]; nloc++; }
+    }
+    const int n = seg_sum_i<SEG>(nloc);
+    gsum = seg_sum<SEG>(gsum);
+    const T gmean = n > 0 ? gsum / (T)n : T(0);
+    T hloc = 0;
+#pragma unroll
+    for (int c = 0; c < P; c++) {
+        Jg[c] = ((vmask >> c) & 1u) ? Jg[c] - gmean : T(0);
+        hloc += Jg[c] * Jg[c];
+    }
+    const T Hs = seg_sum<SEG>(hloc);
+
+    int status = ST_KEPT;
+    T u = u0, post = 0;
+    if (n == 0 || !(Hs > (T)kp.eps_h * (T)n)) {
+        status = ST_DEGENERATE;
+    } else {
+        const T ulo = -(T)(W + P + 2), uhi = (T)(W + 2);
+        T step = 0;
+        for (int t = 0; t < kp.iters; t++) {
+            T uc = fmin(fmax(u, ulo), uhi);
+            T ui = floor(uc), uf = uc - ui;
+            int xi0 = x0 + (int)ui;
+            T s = 0;
+#pragma unroll
+            for (int c = 0; c < P; c++) {
+                T I = sample_row<T, U8>(J.R, row0, W, xi0 + c, uf);
+                s += Jg[c] * (I - Tv[c]);
+            }
+            T b = seg_sum<SEG>(s);
+            step = b / Hs;
+            u = u - step;
+        }
+        const bool unconverged = kp.conv_tol > 0 && kp.iters > 0 && !(fabs(step) <= (T)kp.conv_tol);
+        if (kp.fusion == 1) {
+            if (!isfinite(u)) status = ST_DIVERGED;
+            else post = 1;
+        } else if (!isfinite(u) || fabs(u - u0) > (T)P || unconverged) {
+            status = ST_DIVERGED;
+        } else {
+            // eqs. (3)-(4): energies over the window, centre first
+            const int cw = (kp.window - 1) / 2;
+            auto energy = [&](T ud) -> T {
+                T uc = fmin(fmax(ud, ulo), uhi);
+                T ui = floor(uc), uf = uc - ui;
+                int xi0 = x0 + (int)ui;
+                T d[P];
+                T ds = 0;
+#pragma unroll
+                for (int c = 0; c < P; c++) {
+                    d[c] = sample_row<T, U8>(J.R, row0, W, xi0 + c, uf) - Tv[c];
+                    if ((vmask >> c) & 1u) ds += d[c];
+                }
+                T mean = seg_sum<SEG>(ds) / (T)n;
+                T e = 0;
+#pragma unroll
+                for (int c = 0; c < P; c++) {
+                    T q = d[c] - mean;
+                    if ((vmask >> c) & 1u) e += q * q;
+                }
+                return seg_sum<SEG>(e);
+            };
+            const T Ec = energy(u);
+            T z = 0;
+            for (int i = 0; i < kp.window; i++) {
+                if (i == cw) { z += T(1); continue; }
+                T Ei = energy(u + (T)(i - cw) * (T)kp.window_step);
+                z += exp(-(Ei - Ec) / (T)kp.tau);
+            }
+            post = T(1) / z;
+            // gamma gate at the final shift: left valid, sample inside the
+            // row, both right taps valid (Sec. 3, Sec. 3.2)
+            T uc = fmin(fmax(u, ulo), uhi);
+            T ui = floor(uc), uf = uc - ui;
+            int xi0 = x0 + (int)ui;
+            int cnt = 0;
+#pragma unroll
+            for (int c = 0; c < P; c++) {
+                int xi = xi0 + c;
+                bool inb = xi >= 0 && (xi < W - 1 || (xi == W - 1 && uf == T(0)));
+                if (((vmask >> c) & 1u) && inb) {
+                    int m = min(xi, W - 2);
+                    bool a, b;
+                    (void)pix<T, U8>(J.R, row0 + m, kp, a);
+                    (void)pix<T, U8>(J.R, row0 + m + 1, kp, b);
+                    cnt += (a && b) ? 1 : 0;
+                }
+            }
+            cnt = seg_sum_i<SEG>(cnt);
+            if (cnt < kp.min_valid) {
+                status = ST_GATED;
+                post = 0;
+            }
+        }
+    }
+    if (live && r == 0) {
+        static_cast<T *>(J.rec_u)[k] = u;
+        static_cast<T *>(J.rec_w)[k] = status == ST_KEPT ? post : T(0);
+        J.rec_st[k] = (int8_t)status;
+        static_cast<T *>(J.rec_u0)[k] = u0;
+    }
+}
+
+// ---------------------------------------------------------------- densify
+
+// One pixel: kept covering patches in (row, column) order, weight = patch
+// posterior x spatial Gaussian at the pixel's offset in the patch (Bayesian)
+// or 1 / max(residual^2, 1) (DIS eq. (2)); U = sum(w u) / sum(w).  Uncovered:
+// NaN at level 0, zero at the coarsest level, else twice the coarse field.
+template <typename T, bool U8>
+__global__ __launch_bounds__(kBlock) void k_dense(const DenseJob *jobs, int njobs, KParams kp) {
+    const DenseJob &J = jobs[find_job(jobs, njobs, (int)blockIdx.x)];
+    int i = ((int)blockIdx.x - J.block0) * kBlock + (int)threadIdx.x;
+    if (i >= J.W * J.H) return;
+    const int y = i / J.W, x = i - y * J.W;
+    const int P = J.patch, st = J.stride;
+    const T *rec_u = static_cast<const T *>(J.rec_u);
+    const T *rec_w = static_cast<const T *>(J.rec_w);
+    const T *gtab = static_cast<const T *>(J.gtab);
+    auto range = [&](int v, int n, int cnt, int &lo, int &hi, int &extra) {
+        int t = v - P + 1;
+        lo = t > 0 ? (t + st - 1) / st : 0;
+        hi = min(cnt - 1, v / st);
+        extra = (hi < cnt - 1 && v >= n - P) ? cnt - 1 : -1;
+    };
+    int xlo, xhi, xex, ylo, yhi, yex;
+    range(x, J.W, J.nx, xlo, xhi, xex);
+    range(y, J.H, J.ny, ylo, yhi, yex);
+    T A = 0, B = 0;
+    for (int jy = ylo; jy <= (yex >= 0 ? yex : yhi); jy++) {
+        if (jy > yhi && jy != yex) continue;
+        int py = grid_pos(jy, J.H, P, st);
+        if (y < py || y >= py + P) continue;
+        for (int jx = xlo; jx <= (xex >= 0 ? xex : xhi); jx++) {
+            if (jx > xhi && jx != xex) continue;
+            int px = grid_pos(jx, J.W, P, st);
+            if (x < px || x >= px + P) continue;
+            int k = jy * J.nx + jx;
+            T wk = rec_w[k];
+            if (!(wk > T(0))) continue;
+            T uk = rec_u[k];
+            T w;
+            if (kp.fusion == 1) {
+                size_t row0 = (size_t)y * J.pitch;
+                T uc = fmin(fmax(uk, -(T)(J.W + 2)), (T)(J.W + 2));
+                T ui = floor(uc), uf = uc - ui;
+                T res = sample_row<T, U8>(J.R, row0, J.W, x + (int)ui, uf) - pixv<T, U8>(J.L, row0 + x);
+                T q = res * res;
+                w = T(1) / (q > T(1) ? q : T(1));
+            } else {
+                w = wk * gtab[(y - py) * P + (x - px)];
+            }
+            A += w;
+            B += w * uk;
+        }
+    }
+    T U;
+    if (A > T(0)) U = B / A;
+    else if (J.mode == 2) U = (T)__builtin_nan("");
+    else if (J.mode == 1) U = 0;
+    else U = T(2) * bilinear<T>(static_cast<const T *>(J.Uc), J.Wc, J.Hc, T(0.5) * (T)x, T(0.5) * (T)y);
+    if (J.out) J.out[(size_t)y * J.out_pitch + x] = (float)(-U);
+    if (J.U) static_cast<T *>(J.U)[i] = U;
+}
+
+}  // namespace bdis

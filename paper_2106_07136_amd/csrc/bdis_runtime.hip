@@ -1,0 +1,730 @@
+// bdis_runtime.hip -- host side of the BDIS stereo library: parameter checks,
+// plans, device workspace, job tables, kernel launches and the C ABI declared
+// in include/bdis.h.  Paper: arXiv 2106.07136.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "bdis.h"
+#include "bdis_kernels.hpp"
+
+using namespace bdis;
+
+namespace {
+
+constexpr int kMaxLevels = 12;
+constexpr int kSupportedPatch[] = {4, 6, 8, 10, 12, 16};
+constexpr int kMaxTuning = 8;
+
+thread_local char g_thread_err[512] = "";
+
+void set_err(char *buf, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, 512, fmt, ap);
+    va_end(ap);
+}
+
+bool patch_supported(int p) {
+    for (int s : kSupportedPatch)
+        if (s == p) return true;
+    return false;
+}
+
+int gtab_offset(int p) {  // offset of patch p's spatial table in the packed table
+    int off = 0;
+    for (int s : kSupportedPatch) {
+        if (s == p) return off;
+        off += s * s;
+    }
+    return -1;
+}
+constexpr int kGtabFloats = 16 + 36 + 64 + 100 + 144 + 256;
+
+bdis_status check_params(const bdis_params *p, char *err) {
+    if (!p) { set_err(err, "params is NULL"); return BDIS_E_INVALID_ARG; }
+    if (p->struct_size != sizeof(bdis_params)) {
+        set_err(err, "params.struct_size %u != %zu", p->struct_size, sizeof(bdis_params));
+        return BDIS_E_INVALID_ARG;
+    }
+    if (p->patch < 2 || p->patch > 64) { set_err(err, "patch %d outside [2, 64]", p->patch); return BDIS_E_INVALID_ARG; }
+    if (p->stride < 1 || p->stride > p->patch) { set_err(err, "stride %d outside [1, patch]", p->stride); return BDIS_E_INVALID_ARG; }
+    if (p->iters < 0 || p->iters > 1000) { set_err(err, "iters %d outside [0, 1000]", p->iters); return BDIS_E_INVALID_ARG; }
+    if (!(p->sigma_r > 0.f) || !(p->sigma_s > 0.f) || !std::isfinite(p->sigma_r) || !std::isfinite(p->sigma_s)) {
+        set_err(err, "sigma_r and sigma_s must be positive and finite"); return BDIS_E_INVALID_ARG;
+    }
+    if (p->window < 1 || p->window > 15 || (p->window % 2) == 0) { set_err(err, "window %d must be odd in [1, 15]", p->window); return BDIS_E_INVALID_ARG; }
+    if (!(p->window_step >= 0.f) || !std::isfinite(p->window_step)) { set_err(err, "window_step must be >= 0"); return BDIS_E_INVALID_ARG; }
+    if (!(p->gamma >= 0.f && p->gamma <= 1.f)) { set_err(err, "gamma must be in [0, 1]"); return BDIS_E_INVALID_ARG; }
+    if (p->s_mode != 0 && p->s_mode != 1) { set_err(err, "s_mode must be 0 or 1"); return BDIS_E_INVALID_ARG; }
+    if (p->fusion != BDIS_FUSION_BAYES && p->fusion != BDIS_FUSION_DIS) { set_err(err, "fusion must be 0 or 1"); return BDIS_E_INVALID_ARG; }
+    if (p->valid_lo < 0 || p->valid_hi > 255 || p->valid_lo > p->valid_hi) { set_err(err, "need 0 <= valid_lo <= valid_hi <= 255"); return BDIS_E_INVALID_ARG; }
+    if (!(p->eps_h >= 0.f) || !std::isfinite(p->eps_h)) { set_err(err, "eps_h must be >= 0"); return BDIS_E_INVALID_ARG; }
+    if (!std::isfinite(p->conv_tol)) { set_err(err, "conv_tol must be finite"); return BDIS_E_INVALID_ARG; }
+    if (p->precision != 0 && p->precision != 1) { set_err(err, "precision must be 0 (FP64) or 1 (FP32)"); return BDIS_E_INVALID_ARG; }
+    if (p->levels < 0 || p->levels > kMaxLevels) { set_err(err, "levels %d outside [0, %d]", p->levels, kMaxLevels); return BDIS_E_INVALID_ARG; }
+    if (p->levels == 0 && !(p->max_disparity > 0.f && std::isfinite(p->max_disparity))) {
+        set_err(err, "levels = 0 (auto) needs max_disparity > 0"); return BDIS_E_INVALID_ARG;
+    }
+    if (p->init != BDIS_INIT_ZERO && p->init != BDIS_INIT_LEARNED) { set_err(err, "init must be 0 or 1"); return BDIS_E_INVALID_ARG; }
+    if (p->autotune != 0 && p->autotune != 1) { set_err(err, "autotune must be 0 or 1"); return BDIS_E_INVALID_ARG; }
+    if (!patch_supported(p->patch)) { set_err(err, "patch %d not built (4, 6, 8, 10, 12, 16)", p->patch); return BDIS_E_UNSUPPORTED; }
+    if (p->init == BDIS_INIT_LEARNED) { set_err(err, "learned init is not available in this build"); return BDIS_E_UNSUPPORTED; }
+    return BDIS_OK;
+}
+
+int requested_levels(const bdis_params &p) {
+    if (p.levels > 0) return p.levels;
+    double r = p.max_disparity / 4.0;
+    int L = 1 + (r > 1.0 ? (int)std::ceil(std::log2(r) - 1e-12) : 0);
+    return std::min(L, kMaxLevels);
+}
+
+// Geometry of one pair under (patch, stride).
+struct Geo {
+    int L;
+    int W[kMaxLevels], H[kMaxLevels], nx[kMaxLevels], ny[kMaxLevels];
+    long long patches;
+};
+
+int grid_count(int n, int p, int st) { return n < p ? 0 : (n - p + st - 1) / st + 1; }
+
+bool make_geo(int W, int H, int patch, int stride, int Lreq, Geo &g) {
+    if (W < patch || H < patch) return false;
+    g.L = 0;
+    g.patches = 0;
+    int w = W, h = H;
+    for (int l = 0; l < Lreq && l < kMaxLevels; l++) {
+        if (w < patch || h < patch) break;
+        g.W[l] = w; g.H[l] = h;
+        g.nx[l] = grid_count(w, patch, stride);
+        g.ny[l] = grid_count(h, patch, stride);
+        g.patches += (long long)g.nx[l] * g.ny[l];
+        g.L = l + 1;
+        w = (w + 1) / 2;
+        h = (h + 1) / 2;
+    }
+    return g.L >= 1;
+}
+
+size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
+
+// Workspace of one pair, elements of the arithmetic type (esz bytes):
+// pyramid levels >= 1 (2 images), fields U_l for l >= 1, and per-level patch
+// records (u, w, u0 + a status byte).
+struct PairWs {
+    void *pyr_l[kMaxLevels], *pyr_r[kMaxLevels], *U[kMaxLevels];
+    void *rec_u[kMaxLevels], *rec_w[kMaxLevels], *rec_u0[kMaxLevels];
+    int8_t *rec_st[kMaxLevels];
+};
+
+size_t pair_ws_bytes(const Geo &g, size_t esz) {
+    size_t b = 0;
+    for (int l = 0; l < g.L; l++) {
+        size_t px = (size_t)g.W[l] * g.H[l], np = (size_t)g.nx[l] * g.ny[l];
+        if (l >= 1) b += 3 * align_up(px * esz);
+        b += 3 * align_up(np * esz) + align_up(np);
+    }
+    return b;
+}
+
+void carve(char *base, const Geo &g, size_t esz, PairWs &w) {
+    memset(&w, 0, sizeof w);
+    size_t off = 0;
+    auto take = [&](size_t bytes) { char *p = base + off; off += align_up(bytes); return (void *)p; };
+    for (int l = 0; l < g.L; l++) {
+        size_t px = (size_t)g.W[l] * g.H[l], np = (size_t)g.nx[l] * g.ny[l];
+        if (l >= 1) {
+            w.pyr_l[l] = take(px * esz);
+            w.pyr_r[l] = take(px * esz);
+            w.U[l] = take(px * esz);
+        }
+        w.rec_u[l] = take(np * esz);
+        w.rec_w[l] = take(np * esz);
+        w.rec_u0[l] = take(np * esz);
+        w.rec_st[l] = (int8_t *)take(np);
+    }
+}
+
+struct PairIn {
+    const uint8_t *left, *right;
+    float *disp;
+    int W, H, pitch, dpitch;
+    int patch, stride;
+    Geo g;
+    PairWs ws;
+};
+
+}  // namespace
+
+struct bdis_ctx {
+    bdis_params prm;
+    int device = 0;
+    char err[512] = "";
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    char *djobs = nullptr;
+    size_t djobs_bytes = 0;
+    char *hjobs = nullptr;  // pinned staging
+    size_t hjobs_bytes = 0;
+    std::vector<char> last_upload;
+    hipEvent_t upload_ev = nullptr;
+    bool upload_pending = false;
+    double *gtab_d = nullptr;  // spatial Gaussian tables, one per precision
+    float *gtab_f = nullptr;
+    // last single-pair run, for bdis_debug_stage
+    bool have_last = false;
+    PairIn last;
+    hipStream_t last_stream = nullptr;
+    // autotuner table
+    int ntune = 0;
+    int tune_w[kMaxTuning], tune_p[kMaxTuning], tune_s[kMaxTuning];
+};
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+#define HIPCHK(h, call)                                                              \
+    do {                                                                             \
+        hipError_t e_ = (call);                                                      \
+        if (e_ != hipSuccess) {                                                      \
+            set_err((h)->err, "%s failed: %s", #call, hipGetErrorString(e_));       \
+            return BDIS_E_HIP;                                                       \
+        }                                                                            \
+    } while (0)
+
+size_t esize(const bdis_params &p) { return p.precision == 0 ? sizeof(double) : sizeof(float); }
+
+bdis_status fill_gtab(bdis_t *h) {
+    std::vector<double> t(kGtabFloats);
+    for (int p : kSupportedPatch) {
+        int off = gtab_offset(p);
+        double c = 0.5 * (p - 1), s = h->prm.sigma_s;
+        for (int r = 0; r < p; r++)
+            for (int q = 0; q < p; q++) {
+                double d2 = (r - c) * (r - c) + (q - c) * (q - c);
+                t[off + r * p + q] = std::exp(-d2 / (2.0 * s * s));
+            }
+    }
+    std::vector<float> tf(t.begin(), t.end());
+    HIPCHK(h, hipMemcpy(h->gtab_d, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(h, hipMemcpy(h->gtab_f, tf.data(), tf.size() * sizeof(float), hipMemcpyHostToDevice));
+    return BDIS_OK;
+}
+
+KParams make_kparams(const bdis_params &p, int patch) {
+    KParams k;
+    k.iters = p.iters;
+    k.window = p.window;
+    k.window_step = p.window_step;
+    double s = p.s_mode == 0 ? (double)p.window : (double)patch;
+    k.tau = 2.0 * (double)p.sigma_r * (double)p.sigma_r * s * s;
+    // kept iff count / p^2 >= gamma, decided on integers
+    int need = 0;
+    while (need <= patch * patch && (double)need / ((double)patch * patch) < (double)p.gamma) need++;
+    k.min_valid = need;
+    k.fusion = p.fusion;
+    k.vlo = p.valid_lo;
+    k.vhi = p.valid_hi;
+    k.eps_h = p.eps_h;
+    k.conv_tol = p.conv_tol;
+    return k;
+}
+
+bdis_status ensure_ws(bdis_t *h, size_t bytes) {
+    if (bytes <= h->ws_bytes) return BDIS_OK;
+    if (h->ws) {
+        HIPCHK(h, hipDeviceSynchronize());
+        (void)hipFree(h->ws);
+        h->ws = nullptr;
+        h->ws_bytes = 0;
+    }
+    size_t want = align_up(bytes, 1 << 20);
+    if (hipMalloc(&h->ws, want) != hipSuccess) {
+        (void)hipGetLastError();
+        h->ws = nullptr;
+        set_err(h->err, "workspace allocation of %zu bytes failed", want);
+        return BDIS_E_OOM;
+    }
+    h->ws_bytes = want;
+    return BDIS_OK;
+}
+
+bdis_status ensure_jobs(bdis_t *h, size_t bytes) {
+    if (bytes <= h->djobs_bytes) return BDIS_OK;
+    size_t want = align_up(std::max(bytes, (size_t)16384), 4096);
+    if (h->upload_pending) {
+        HIPCHK(h, hipEventSynchronize(h->upload_ev));
+        h->upload_pending = false;
+    }
+    if (h->djobs) { HIPCHK(h, hipDeviceSynchronize()); (void)hipFree(h->djobs); h->djobs = nullptr; h->djobs_bytes = 0; }
+    if (h->hjobs) { (void)hipHostFree(h->hjobs); h->hjobs = nullptr; h->hjobs_bytes = 0; }
+    if (hipMalloc(&h->djobs, want) != hipSuccess || hipHostMalloc(&h->hjobs, want, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        set_err(h->err, "job table allocation failed");
+        return BDIS_E_OOM;
+    }
+    h->djobs_bytes = h->hjobs_bytes = want;
+    h->last_upload.clear();
+    return BDIS_OK;
+}
+
+// A launch: kernel kind, template selectors, byte offset of its jobs in the
+// table, job count and total blocks.
+enum Kind { K_PYR, K_LK, K_DENSE };
+struct Launch {
+    Kind kind;
+    int patch;
+    bool u8;
+    bool f64;
+    size_t off;
+    int njobs;
+    int blocks;
+    KParams kp;
+};
+
+template <typename Job>
+void append(std::vector<char> &tab, std::vector<Launch> &ls, Kind kind, int patch, bool u8, bool f64,
+            const std::vector<Job> &jobs, int blocks, const KParams &kp) {
+    if (jobs.empty() || blocks == 0) return;
+    size_t off = align_up(tab.size(), 64);
+    tab.resize(off + jobs.size() * sizeof(Job));
+    memcpy(tab.data() + off, jobs.data(), jobs.size() * sizeof(Job));
+    ls.push_back(Launch{kind, patch, u8, f64, off, (int)jobs.size(), blocks, kp});
+}
+
+// Build every launch for a set of pairs: pyramid levels 1..Lmax-1, then for
+// each level from the coarsest down, LK (one launch per patch size) and the
+// densification.
+void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<char> &tab, std::vector<Launch> &ls) {
+    int Lmax = 0;
+    const bool f64 = h->prm.precision == 0;
+    for (auto &p : pairs) Lmax = std::max(Lmax, p.g.L);
+    KParams kp0 = make_kparams(h->prm, h->prm.patch);
+    for (int l = 1; l < Lmax; l++) {
+        std::vector<PyrJob> jobs;
+        int blocks = 0;
+        for (auto &p : pairs) {
+            if (p.g.L <= l) continue;
+            PyrJob j;
+            j.src_l = l == 1 ? (const void *)p.left : p.ws.pyr_l[l - 1];
+            j.src_r = l == 1 ? (const void *)p.right : p.ws.pyr_r[l - 1];
+            j.src_pitch = l == 1 ? p.pitch : p.g.W[l - 1];
+            j.ws = p.g.W[l - 1]; j.hs = p.g.H[l - 1];
+            j.dst_l = p.ws.pyr_l[l]; j.dst_r = p.ws.pyr_r[l];
+            j.wd = p.g.W[l]; j.hd = p.g.H[l];
+            j.block0 = blocks;
+            blocks += (j.wd * j.hd + kBlock - 1) / kBlock;
+            jobs.push_back(j);
+        }
+        append(tab, ls, K_PYR, 0, l == 1, f64, jobs, blocks, kp0);
+    }
+    for (int l = Lmax - 1; l >= 0; l--) {
+        for (int P : kSupportedPatch) {
+            std::vector<LkJob> jobs;
+            int blocks = 0;
+            int ppb = kBlock / (P <= 8 ? 8 : 16);
+            for (auto &p : pairs) {
+                if (p.g.L <= l || p.patch != P) continue;
+                LkJob j;
+                j.L = l == 0 ? (const void *)p.left : p.ws.pyr_l[l];
+                j.R = l == 0 ? (const void *)p.right : p.ws.pyr_r[l];
+                j.pitch = l == 0 ? p.pitch : p.g.W[l];
+                j.W = p.g.W[l]; j.H = p.g.H[l];
+                bool coarsest = l == p.g.L - 1;
+                j.Uc = coarsest ? nullptr : p.ws.U[l + 1];
+                j.Wc = coarsest ? 0 : p.g.W[l + 1];
+                j.Hc = coarsest ? 0 : p.g.H[l + 1];
+                j.nx = p.g.nx[l]; j.ny = p.g.ny[l]; j.stride = p.stride;
+                j.rec_u = p.ws.rec_u[l]; j.rec_w = p.ws.rec_w[l];
+                j.rec_u0 = p.ws.rec_u0[l]; j.rec_st = p.ws.rec_st[l];
+                j.block0 = blocks;
+                blocks += (j.nx * j.ny + ppb - 1) / ppb;
+                jobs.push_back(j);
+            }
+            append(tab, ls, K_LK, P, l == 0, f64, jobs, blocks, make_kparams(h->prm, P));
+        }
+        std::vector<DenseJob> jobs;
+        int blocks = 0;
+        for (auto &p : pairs) {
+            if (p.g.L <= l) continue;
+            DenseJob j;
+            j.L = l == 0 ? (const void *)p.left : p.ws.pyr_l[l];
+            j.R = l == 0 ? (const void *)p.right : p.ws.pyr_r[l];
+            j.pitch = l == 0 ? p.pitch : p.g.W[l];
+            j.W = p.g.W[l]; j.H = p.g.H[l];
+            j.patch = p.patch; j.stride = p.stride;
+            j.nx = p.g.nx[l]; j.ny = p.g.ny[l];
+            j.rec_u = p.ws.rec_u[l]; j.rec_w = p.ws.rec_w[l];
+            j.gtab = f64 ? (const void *)(h->gtab_d + gtab_offset(p.patch))
+                         : (const void *)(h->gtab_f + gtab_offset(p.patch));
+            bool coarsest = l == p.g.L - 1;
+            j.Uc = coarsest ? nullptr : p.ws.U[l + 1];
+            j.Wc = coarsest ? 0 : p.g.W[l + 1];
+            j.Hc = coarsest ? 0 : p.g.H[l + 1];
+            j.mode = l == 0 ? 2 : (coarsest ? 1 : 0);
+            j.U = l == 0 ? nullptr : p.ws.U[l];
+            j.out = l == 0 ? p.disp : nullptr;
+            j.out_pitch = p.dpitch;
+            j.block0 = blocks;
+            blocks += (j.W * j.H + kBlock - 1) / kBlock;
+            jobs.push_back(j);
+        }
+        append(tab, ls, K_DENSE, 0, l == 0, f64, jobs, blocks, kp0);
+    }
+}
+
+template <typename T, int P>
+void launch_lk(const Launch &L, const char *base, hipStream_t s) {
+    const LkJob *j = (const LkJob *)(base + L.off);
+    if (L.u8) hipLaunchKernelGGL((k_lk<T, P, true>), dim3(L.blocks), dim3(kBlock), 0, s, j, L.njobs, L.kp);
+    else hipLaunchKernelGGL((k_lk<T, P, false>), dim3(L.blocks), dim3(kBlock), 0, s, j, L.njobs, L.kp);
+}
+
+template <typename T>
+void launch_one(const Launch &L, const char *base, hipStream_t s) {
+    switch (L.kind) {
+    case K_PYR: {
+        const PyrJob *j = (const PyrJob *)(base + L.off);
+        if (L.u8) hipLaunchKernelGGL((k_pyr<T, true>), dim3(L.blocks), dim3(kBlock), 0, s, j, L.njobs, L.kp);
+        else hipLaunchKernelGGL((k_pyr<T, false>), dim3(L.blocks), dim3(kBlock), 0, s, j, L.njobs, L.kp);
+        break;
+    }
+    case K_LK:
+        switch (L.patch) {
+        case 4: launch_lk<T, 4>(L, base, s); break;
+        case 6: launch_lk<T, 6>(L, base, s); break;
+        case 8: launch_lk<T, 8>(L, base, s); break;
+        case 10: launch_lk<T, 10>(L, base, s); break;
+        case 12: launch_lk<T, 12>(L, base, s); break;
+        case 16: launch_lk<T, 16>(L, base, s); break;
+        }
+        break;
+    case K_DENSE: {
+        const DenseJob *j = (const DenseJob *)(base + L.off);
+        if (L.u8) hipLaunchKernelGGL((k_dense<T, true>), dim3(L.blocks), dim3(kBlock), 0, s, j, L.njobs, L.kp);
+        else hipLaunchKernelGGL((k_dense<T, false>), dim3(L.blocks), dim3(kBlock), 0, s, j, L.njobs, L.kp);
+        break;
+    }
+    }
+}
+
+void launch_all(const std::vector<Launch> &ls, const char *base, hipStream_t s) {
+    for (const Launch &L : ls) {
+        if (L.f64) launch_one<double>(L, base, s);
+        else launch_one<float>(L, base, s);
+    }
+}
+
+void pick_tuning(const bdis_t *h, int W, int &patch, int &stride) {
+    patch = h->prm.patch;
+    stride = h->prm.stride;
+    if (!h->prm.autotune) return;
+    for (int i = 0; i < h->ntune; i++)
+        if (W <= h->tune_w[i]) { patch = h->tune_p[i]; stride = h->tune_s[i]; return; }
+}
+
+bdis_status check_pair(bdis_t *h, const uint8_t *L, const uint8_t *R, int W, int H, int pitch,
+                       float *disp, int dpitch, int patch) {
+    if (!L || !R || !disp) { set_err(h->err, "NULL image or output pointer"); return BDIS_E_INVALID_ARG; }
+    if (W < patch || H < patch) { set_err(h->err, "image %dx%d smaller than the patch %d", W, H, patch); return BDIS_E_INVALID_ARG; }
+    if (W > 65536 || H > 65536) { set_err(h->err, "image %dx%d too large", W, H); return BDIS_E_INVALID_ARG; }
+    if (pitch < W || dpitch < W) { set_err(h->err, "pitch smaller than width"); return BDIS_E_INVALID_ARG; }
+    return BDIS_OK;
+}
+
+// Shared body of bdis_compute and bdis_compute_batch.
+bdis_status run(bdis_t *h, std::vector<PairIn> &pairs, hipStream_t s) {
+    DeviceGuard dg(h->device);
+    int Lreq = requested_levels(h->prm);
+    const size_t esz = esize(h->prm);
+    size_t total = 0;
+    for (auto &p : pairs) {
+        if (!make_geo(p.W, p.H, p.patch, p.stride, Lreq, p.g)) {
+            set_err(h->err, "image %dx%d smaller than patch %d", p.W, p.H, p.patch);
+            return BDIS_E_INVALID_ARG;
+        }
+        total += align_up(pair_ws_bytes(p.g, esz));
+    }
+    bdis_status st = ensure_ws(h, total);
+    if (st != BDIS_OK) return st;
+    size_t off = 0;
+    for (auto &p : pairs) {
+        carve(h->ws + off, p.g, esz, p.ws);
+        off += align_up(pair_ws_bytes(p.g, esz));
+    }
+    std::vector<char> tab;
+    std::vector<Launch> ls;
+    plan_launches(h, pairs, tab, ls);
+    st = ensure_jobs(h, tab.size());
+    if (st != BDIS_OK) return st;
+    if (tab != h->last_upload) {
+        if (h->upload_pending) {
+            HIPCHK(h, hipEventSynchronize(h->upload_ev));
+            h->upload_pending = false;
+        }
+        memcpy(h->hjobs, tab.data(), tab.size());
+        HIPCHK(h, hipMemcpyAsync(h->djobs, h->hjobs, tab.size(), hipMemcpyHostToDevice, s));
+        HIPCHK(h, hipEventRecord(h->upload_ev, s));
+        h->upload_pending = true;
+        h->last_upload = tab;
+    }
+    launch_all(ls, h->djobs, s);
+    HIPCHK(h, hipGetLastError());
+    return BDIS_OK;
+}
+
+}  // namespace
+
+// ============================================================== C ABI
+
+extern "C" {
+
+void bdis_default_params(bdis_params *p) {
+    if (!p) return;
+    memset(p, 0, sizeof *p);
+    p->struct_size = sizeof(bdis_params);
+    p->levels = 5;
+    p->max_disparity = 64.f;
+    p->patch = 8;
+    p->stride = 4;
+    p->iters = 12;
+    p->sigma_r = 4.f;
+    p->sigma_s = 4.f;
+    p->window = 5;
+    p->window_step = 0.5f;
+    p->gamma = 0.75f;
+    p->s_mode = 0;
+    p->fusion = BDIS_FUSION_BAYES;
+    p->valid_lo = 1;
+    p->valid_hi = 254;
+    p->eps_h = 1e-6f;
+    p->conv_tol = 0.05f;
+    p->precision = 0;
+    p->init = BDIS_INIT_ZERO;
+    p->conf_threshold = 0.5f;
+    p->learned_fine_levels = 2;
+    p->learned_iters = 12;
+    p->autotune = 0;
+}
+
+bdis_status bdis_plan(const bdis_params *p, int32_t width, int32_t height, bdis_plan_info *out) {
+    bdis_status st = check_params(p, g_thread_err);
+    if (st != BDIS_OK) return st;
+    if (!out) { set_err(g_thread_err, "out is NULL"); return BDIS_E_INVALID_ARG; }
+    Geo g;
+    if (!make_geo(width, height, p->patch, p->stride, requested_levels(*p), g)) {
+        set_err(g_thread_err, "image %dx%d smaller than patch %d", width, height, p->patch);
+        return BDIS_E_INVALID_ARG;
+    }
+    memset(out, 0, sizeof *out);
+    out->levels = g.L;
+    for (int l = 0; l < g.L; l++) {
+        out->width[l] = g.W[l]; out->height[l] = g.H[l];
+        out->nx[l] = g.nx[l]; out->ny[l] = g.ny[l];
+    }
+    out->patches = g.patches;
+    out->workspace_bytes = (int64_t)align_up(pair_ws_bytes(g, esize(*p)));
+    return BDIS_OK;
+}
+
+bdis_status bdis_create(const bdis_params *p, int device, bdis_t **out) {
+    if (!out) { set_err(g_thread_err, "out is NULL"); return BDIS_E_INVALID_ARG; }
+    *out = nullptr;
+    bdis_params def;
+    bdis_default_params(&def);
+    if (!p) p = &def;
+    bdis_status st = check_params(p, g_thread_err);
+    if (st != BDIS_OK) return st;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
+        (void)hipGetLastError();
+        set_err(g_thread_err, "no HIP device");
+        return BDIS_E_NO_DEVICE;
+    }
+    if (device < 0 || device >= n) { set_err(g_thread_err, "device %d out of range (%d devices)", device, n); return BDIS_E_NO_DEVICE; }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) { set_err(g_thread_err, "hipGetDeviceProperties failed"); return BDIS_E_NO_DEVICE; }
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+        set_err(g_thread_err, "device %d is %s, this library is built for gfx950", device, prop.gcnArchName);
+        return BDIS_E_NO_DEVICE;
+    }
+    bdis_t *h = new (std::nothrow) bdis_t();
+    if (!h) { set_err(g_thread_err, "host allocation failed"); return BDIS_E_OOM; }
+    h->prm = *p;
+    h->device = device;
+    DeviceGuard dg(device);
+    if (hipMalloc(&h->gtab_d, kGtabFloats * sizeof(double)) != hipSuccess ||
+        hipMalloc(&h->gtab_f, kGtabFloats * sizeof(float)) != hipSuccess ||
+        hipEventCreateWithFlags(&h->upload_ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        set_err(g_thread_err, "device setup failed");
+        bdis_destroy(h);
+        return BDIS_E_HIP;
+    }
+    st = fill_gtab(h);
+    if (st != BDIS_OK) {
+        set_err(g_thread_err, "%s", h->err);
+        bdis_destroy(h);
+        return st;
+    }
+    *out = h;
+    return BDIS_OK;
+}
+
+bdis_status bdis_set_params(bdis_t *h, const bdis_params *p) {
+    if (!h) { set_err(g_thread_err, "handle is NULL"); return BDIS_E_INVALID_ARG; }
+    bdis_status st = check_params(p, h->err);
+    if (st != BDIS_OK) return st;
+    DeviceGuard dg(h->device);
+    HIPCHK(h, hipDeviceSynchronize());
+    h->prm = *p;
+    h->last_upload.clear();
+    return fill_gtab(h);
+}
+
+bdis_status bdis_reserve(bdis_t *h, int32_t width, int32_t height, int32_t n_pairs) {
+    if (!h) { set_err(g_thread_err, "handle is NULL"); return BDIS_E_INVALID_ARG; }
+    if (width < h->prm.patch || height < h->prm.patch || n_pairs < 1) {
+        set_err(h->err, "bad reserve size"); return BDIS_E_INVALID_ARG;
+    }
+    Geo g;
+    size_t worst = 0;
+    int Lreq = requested_levels(h->prm);
+    for (int p : kSupportedPatch)
+        for (int s = 1; s <= p; s++)
+            if (make_geo(width, height, p, s, Lreq, g)) worst = std::max(worst, align_up(pair_ws_bytes(g, sizeof(double))));
+    DeviceGuard dg(h->device);
+    return ensure_ws(h, worst * (size_t)n_pairs);
+}
+
+bdis_status bdis_compute(bdis_t *h, const uint8_t *left, const uint8_t *right, int32_t width,
+                         int32_t height, int32_t pitch_bytes, float *disp, int32_t disp_pitch_elems,
+                         void *stream) {
+    if (!h) { set_err(g_thread_err, "handle is NULL"); return BDIS_E_INVALID_ARG; }
+    bdis_status st = check_pair(h, left, right, width, height, pitch_bytes, disp, disp_pitch_elems, h->prm.patch);
+    if (st != BDIS_OK) return st;
+    std::vector<PairIn> pairs(1);
+    PairIn &p = pairs[0];
+    p.left = left; p.right = right; p.disp = disp;
+    p.W = width; p.H = height; p.pitch = pitch_bytes; p.dpitch = disp_pitch_elems;
+    p.patch = h->prm.patch; p.stride = h->prm.stride;
+    hipStream_t s = (hipStream_t)stream;
+    st = run(h, pairs, s);
+    if (st != BDIS_OK) return st;
+    h->have_last = true;
+    h->last = pairs[0];
+    h->last_stream = s;
+    return BDIS_OK;
+}
+
+bdis_status bdis_compute_batch(bdis_t *h, const bdis_pair *pairs, int32_t n, void *stream) {
+    if (!h) { set_err(g_thread_err, "handle is NULL"); return BDIS_E_INVALID_ARG; }
+    if (!pairs || n < 1 || n > 4096) { set_err(h->err, "need 1 <= n <= 4096 pairs"); return BDIS_E_INVALID_ARG; }
+    std::vector<PairIn> ps(n);
+    for (int i = 0; i < n; i++) {
+        const bdis_pair &q = pairs[i];
+        PairIn &p = ps[i];
+        pick_tuning(h, q.width, p.patch, p.stride);
+        bdis_status st = check_pair(h, q.left, q.right, q.width, q.height, q.pitch_bytes, q.disp,
+                                    q.disp_pitch_elems, p.patch);
+        if (st != BDIS_OK) return st;
+        p.left = q.left; p.right = q.right; p.disp = q.disp;
+        p.W = q.width; p.H = q.height; p.pitch = q.pitch_bytes; p.dpitch = q.disp_pitch_elems;
+    }
+    h->have_last = false;
+    return run(h, ps, (hipStream_t)stream);
+}
+
+bdis_status bdis_set_tuning(bdis_t *h, int32_t n, const int32_t *max_width, const int32_t *patch,
+                            const int32_t *stride) {
+    if (!h) { set_err(g_thread_err, "handle is NULL"); return BDIS_E_INVALID_ARG; }
+    if (n < 0 || n > kMaxTuning || (n > 0 && (!max_width || !patch || !stride))) {
+        set_err(h->err, "bad tuning table"); return BDIS_E_INVALID_ARG;
+    }
+    for (int i = 0; i < n; i++) {
+        if (!patch_supported(patch[i]) || stride[i] < 1 || stride[i] > patch[i] || max_width[i] < 1 ||
+            (i > 0 && max_width[i] <= max_width[i - 1])) {
+            set_err(h->err, "bad tuning entry %d", i); return BDIS_E_INVALID_ARG;
+        }
+    }
+    h->ntune = n;
+    for (int i = 0; i < n; i++) { h->tune_w[i] = max_width[i]; h->tune_p[i] = patch[i]; h->tune_s[i] = stride[i]; }
+    return BDIS_OK;
+}
+
+bdis_status bdis_debug_stage(bdis_t *h, int32_t stage, int32_t level, void *dst, size_t bytes) {
+    if (!h) { set_err(g_thread_err, "handle is NULL"); return BDIS_E_INVALID_ARG; }
+    if (!h->have_last) { set_err(h->err, "no single-pair compute to inspect"); return BDIS_E_STATE; }
+    const PairIn &p = h->last;
+    if (!dst || level < 0 || level >= p.g.L) { set_err(h->err, "bad level or dst"); return BDIS_E_INVALID_ARG; }
+    const size_t esz = esize(h->prm);
+    size_t px = (size_t)p.g.W[level] * p.g.H[level] * esz, np = (size_t)p.g.nx[level] * p.g.ny[level];
+    const void *src = nullptr;
+    size_t need = 0;
+    switch (stage) {
+    case 0: src = p.ws.pyr_l[level]; need = px; break;
+    case 1: src = p.ws.pyr_r[level]; need = px; break;
+    case 2: src = p.ws.rec_u[level]; need = np * esz; break;
+    case 3: src = p.ws.rec_w[level]; need = np * esz; break;
+    case 4: src = p.ws.rec_st[level]; need = np; break;
+    case 5: src = p.ws.U[level]; need = px; break;
+    case 6: src = p.ws.rec_u0[level]; need = np * esz; break;
+    default: set_err(h->err, "unknown stage %d", stage); return BDIS_E_INVALID_ARG;
+    }
+    if (!src) { set_err(h->err, "stage %d has no level %d", stage, level); return BDIS_E_INVALID_ARG; }
+    if (bytes < need) { set_err(h->err, "dst holds %zu bytes, need %zu", bytes, need); return BDIS_E_INVALID_ARG; }
+    DeviceGuard dg(h->device);
+    HIPCHK(h, hipStreamSynchronize(h->last_stream));
+    HIPCHK(h, hipMemcpy(dst, src, need, hipMemcpyDeviceToHost));
+    return BDIS_OK;
+}
+
+void bdis_destroy(bdis_t *h) {
+    if (!h) return;
+    {
+        DeviceGuard dg(h->device);
+        (void)hipDeviceSynchronize();
+        if (h->ws) (void)hipFree(h->ws);
+        if (h->djobs) (void)hipFree(h->djobs);
+        if (h->hjobs) (void)hipHostFree(h->hjobs);
+        if (h->gtab_d) (void)hipFree(h->gtab_d);
+        if (h->gtab_f) (void)hipFree(h->gtab_f);
+        if (h->upload_ev) (void)hipEventDestroy(h->upload_ev);
+    }
+    delete h;
+}
+
+const char *bdis_status_string(bdis_status s) {
+    switch (s) {
+    case BDIS_OK: return "ok";
+    case BDIS_E_INVALID_ARG: return "invalid argument";
+    case BDIS_E_NO_DEVICE: return "no usable gfx950 device";
+    case BDIS_E_OOM: return "out of device memory";
+    case BDIS_E_HIP: return "HIP runtime error";
+    case BDIS_E_UNSUPPORTED: return "unsupported request";
+    case BDIS_E_STATE: return "call out of order";
+    }
+    return "unknown status";
+}
+
+const char *bdis_last_error(const bdis_t *h) { return h ? h->err : g_thread_err; }
+
+}  // extern "C"

@@ -1,0 +1,111 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/bdis.h declares, validates parameters, plans the
+pyramid and patch grids, and reports a missing device as an error."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2106_07136_amd import bdis
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "bdis.h")).read()
+    return sorted(set(re.findall(r"BDIS_API[^;(]*?\b(bdis_\w+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol():
+    names = _declared()
+    assert len(names) >= 12
+    L = C.CDLL(bdis.LIB_PATH)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_default_params_follow_paper():
+    p = bdis.default_params()
+    assert (p.sigma_r, p.sigma_s, p.window, p.window_step, p.gamma) == (4.0, 4.0, 5, 0.5, 0.75)
+    assert (p.patch, p.stride, p.iters, p.levels) == (8, 4, 12, 5)
+    assert p == bdis.Params(eps_h=p.eps_h, conv_tol=p.conv_tol)
+    assert abs(p.conv_tol - 0.05) < 1e-7 and p.precision == 0
+
+
+@pytest.mark.parametrize("W,H,levels,patches", [(640, 480, 5, 25042), (160, 120, 3, 1460)])
+def test_plan_patch_counts(W, H, levels, patches, ref):
+    info = bdis.plan(bdis.Params(levels=levels), W, H)
+    assert info["levels"] == levels and info["patches"] == patches
+    # the oracle derives the same grid independently
+    tot = 0
+    for l in range(levels):
+        w, h = ref.level_dims(W, H, l)
+        assert (info["width"][l], info["height"][l]) == (w, h)
+        assert info["nx"][l] == ref.grid_count(w, 8, 4) and info["ny"][l] == ref.grid_count(h, 8, 4)
+        tot += info["nx"][l] * info["ny"][l]
+    assert tot == patches
+
+
+@pytest.mark.parametrize("W,H,dmax,L", [(640, 480, 64, 5), (160, 120, 16, 3), (320, 240, 32, 4),
+                                        (1280, 720, 128, 6), (1920, 1080, 192, 7), (64, 64, 3, 1)])
+def test_auto_levels(W, H, dmax, L):
+    assert bdis.plan(bdis.Params(levels=0, max_disparity=dmax), W, H)["levels"] == L
+
+
+def test_levels_capped_by_size():
+    info = bdis.plan(bdis.Params(levels=12), 100, 40)
+    # 100x40 -> 50x20 -> 25x10 -> 13x5 (too short for an 8x8 patch)
+    assert info["levels"] == 3 and info["height"] == [40, 20, 10]
+    assert bdis.plan(bdis.Params(levels=3), 8, 8)["patches"] == 1
+
+
+@pytest.mark.parametrize("bad", [dict(patch=1), dict(stride=0), dict(stride=9), dict(iters=-1),
+                                 dict(sigma_r=0.0), dict(window=4), dict(window=17), dict(gamma=1.5),
+                                 dict(s_mode=2), dict(fusion=3), dict(valid_lo=10, valid_hi=5),
+                                 dict(levels=13), dict(levels=0, max_disparity=0.0), dict(eps_h=-1.0)])
+def test_plan_rejects_bad_params(bad):
+    with pytest.raises(bdis.BdisError) as e:
+        bdis.plan(bdis.Params(**bad), 64, 64)
+    assert e.value.status == bdis.E_INVALID_ARG
+    assert bdis.lib().bdis_last_error(None)
+
+
+def test_plan_unsupported_patch_and_small_image():
+    with pytest.raises(bdis.BdisError) as e:
+        bdis.plan(bdis.Params(patch=9, stride=4), 64, 64)
+    assert e.value.status == bdis.E_UNSUPPORTED
+    with pytest.raises(bdis.BdisError) as e:
+        bdis.plan(bdis.Params(), 7, 64)
+    assert e.value.status == bdis.E_INVALID_ARG
+
+
+def test_struct_size_checked():
+    c = bdis.Params().to_c()
+    c.struct_size = 4
+    info = bdis.CPlan()
+    assert bdis.lib().bdis_plan(C.byref(c), 64, 64, C.byref(info)) == bdis.E_INVALID_ARG
+
+
+def test_status_strings_and_null_safety():
+    L = bdis.lib()
+    for s in range(-6, 1):
+        assert L.bdis_status_string(s)
+    L.bdis_destroy(None)  # NULL-safe
+    h = C.c_void_p()
+    assert L.bdis_create(None, 0, None) == bdis.E_INVALID_ARG
+    assert L.bdis_compute(None, None, None, 8, 8, 8, None, 8, None) == bdis.E_INVALID_ARG
+    assert L.bdis_debug_stage(None, 0, 0, None, 0) == bdis.E_INVALID_ARG
+
+
+def test_create_without_gpu_reports_no_device():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(bdis.BdisError) as e:
+        bdis.Bdis()
+    assert e.value.status == bdis.E_NO_DEVICE
+    # parameter errors are found before the device is touched
+    with pytest.raises(bdis.BdisError) as e:
+        bdis.Bdis(bdis.Params(window=2))
+    assert e.value.status == bdis.E_INVALID_ARG

@@ -1,0 +1,229 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on
+the same seeded synthetic pairs, stage by stage and end to end.  Needs an
+MI355X; every test is marked gpu."""
+import numpy as np
+import pytest
+
+from paper_2106_07136_amd import synth
+from tests.parity_util import assert_parity, oracle_params, parity
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _run(torch, params, left, right, pitch_pad=0, out_pad=0):
+    from paper_2106_07136_amd import bdis
+    h = bdis.Bdis(params)
+    H, W = left.shape
+    if pitch_pad:
+        Lb = torch.zeros((H, W + pitch_pad), dtype=torch.uint8, device="cuda")
+        Rb = torch.zeros((H, W + pitch_pad), dtype=torch.uint8, device="cuda")
+        Lb[:, :W] = torch.from_numpy(left).cuda()
+        Rb[:, :W] = torch.from_numpy(right).cuda()
+        L, R = Lb[:, :W], Rb[:, :W]
+    else:
+        L = torch.from_numpy(np.ascontiguousarray(left)).cuda()
+        R = torch.from_numpy(np.ascontiguousarray(right)).cuda()
+    ob = torch.full((H, W + out_pad), 7.0, dtype=torch.float32, device="cuda")
+    out = ob[:, :W]
+    h.compute(L, R, out)
+    torch.cuda.synchronize()
+    if out_pad:
+        assert torch.all(ob[:, W:] == 7.0).item(), "wrote outside the output rows"
+    return h, out.cpu().numpy()
+
+
+CONFIGS = {
+    # one 160x120 pair, d 0-16, 3 levels, 8 iterations
+    "160x120": (160, 120, 16.0, 1, dict(levels=3, iters=8)),
+    # one 640x480 pair, d 0-64, 5 levels, 12 iterations
+    "640x480": (640, 480, 64.0, 2, dict(levels=5, iters=12)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CONFIGS))
+def test_e2e_parity_configs(torch_cuda, ref, name):
+    from paper_2106_07136_amd import bdis
+    W, H, dmax, seed, kw = CONFIGS[name]
+    print(f"case {name} seed {seed}", flush=True)
+    pair = synth.make_pair(W, H, dmax, seed)
+    gp = bdis.Params(**kw)
+    _, gpu = _run(torch_cuda, gp, pair.left, pair.right)
+    exp = ref.compute(pair.left, pair.right, oracle_params(ref, gp))
+    assert_parity(gpu, exp, name)
+
+
+@pytest.mark.parametrize("W,H,dmax,seed,levels", [(1280, 720, 128.0, 3001, 6), (1920, 1080, 192.0, 50000, 7)])
+def test_e2e_parity_large(torch_cuda, ref, W, H, dmax, seed, levels):
+    from paper_2106_07136_amd import bdis
+    print(f"case {W}x{H} seed {seed}", flush=True)
+    pair = synth.make_pair(W, H, dmax, seed)
+    gp = bdis.Params(levels=levels, iters=12)
+    _, gpu = _run(torch_cuda, gp, pair.left, pair.right)
+    exp = ref.compute(pair.left, pair.right, oracle_params(ref, gp))
+    assert_parity(gpu, exp, f"{W}x{H}")
+
+
+def test_stage_parity_small(torch_cuda, ref):
+    """Per level: pyramid values and validity, initial and final patch
+    shifts, posteriors, patch outcomes and dense fields."""
+    from paper_2106_07136_amd import bdis
+    pair = synth.make_pair(160, 120, 16.0, 1)
+    gp = bdis.Params(levels=3, iters=8)
+    h, gpu = _run(torch_cuda, gp, pair.left, pair.right)
+    exp, tr = ref.compute(pair.left, pair.right, oracle_params(ref, gp), trace=True)
+    for l in range(3):
+        t = tr[l]
+        if l >= 1:
+            for stage, key, mkey in ((bdis.STAGE_PYR_L, "pyr_l", "mask_l"), (bdis.STAGE_PYR_R, "pyr_r", "mask_r")):
+                g = h.debug_stage(stage, l)
+                np.testing.assert_allclose(np.abs(g), t[key], atol=1e-3, rtol=0)
+                np.testing.assert_array_equal(~np.signbit(g), t[mkey].astype(bool))
+            np.testing.assert_allclose(h.debug_stage(bdis.STAGE_FIELD, l), t["field"], atol=1e-3, rtol=0)
+        st = h.debug_stage(bdis.STAGE_STATUS, l)
+        same = st == t["status"]
+        assert same.mean() >= 0.999, (l, same.mean())
+        u0 = h.debug_stage(bdis.STAGE_U0, l)
+        u = h.debug_stage(bdis.STAGE_U, l)
+        w = h.debug_stage(bdis.STAGE_W, l)
+        assert (np.abs(u0 - t["u_init"]) <= 1e-3).mean() >= 0.999
+        kept = same & (st == 0)
+        assert (np.abs(u - t["u_final"])[kept] <= 1e-3).mean() >= 0.999
+        assert np.abs(w - t["post"])[kept].max() <= 1e-4
+
+
+@pytest.mark.parametrize("s", [2, 7])
+def test_integer_shift_recovered(torch_cuda, s):
+    from paper_2106_07136_amd import bdis
+    pair = synth.integer_shift_pair(160, 96, s, seed=s)
+    _, gpu = _run(torch_cuda, bdis.Params(levels=3, iters=12), pair.left, pair.right)
+    inner = gpu[8:-8, s + 8:-8]
+    assert np.isfinite(inner).mean() > 0.99
+    assert np.nanmax(np.abs(inner - s)) <= 1e-3
+
+
+EDGE = {
+    "odd_97x61": (97, 61, dict(levels=2, iters=6)),
+    "min_8x8": (8, 8, dict(levels=3)),
+    "one_wider_9x8": (9, 8, dict(levels=1)),
+    "single_level": (96, 64, dict(levels=1)),
+    "dis_fusion": (128, 96, dict(levels=3, fusion=1)),
+    "s_is_patch": (128, 96, dict(levels=3, s_mode=1)),
+    "window3": (128, 96, dict(levels=2, window=3, window_step=1.0)),
+    "window7": (128, 96, dict(levels=2, window=7, window_step=0.25)),
+    "patch12_st3": (160, 120, dict(levels=3, patch=12, stride=3)),
+    "patch16_st6": (160, 120, dict(levels=2, patch=16, stride=6)),
+    "patch4_st2": (96, 64, dict(levels=3, patch=4, stride=2)),
+    "patch6_st6": (96, 64, dict(levels=3, patch=6, stride=6)),
+    "patch10_st5": (120, 80, dict(levels=2, patch=10, stride=5)),
+    "gamma_025": (160, 120, dict(levels=3, gamma=0.25)),
+    "no_iters": (96, 64, dict(levels=2, iters=0)),
+    "valid_band": (128, 96, dict(levels=2, valid_lo=90, valid_hi=160)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(EDGE))
+def test_edge_cases(torch_cuda, ref, name):
+    from paper_2106_07136_amd import bdis
+    W, H, kw = EDGE[name]
+    print(f"edge {name}", flush=True)
+    pair = synth.make_pair(W, H, max(2.0, W / 10), seed=W * 7 + H)
+    gp = bdis.Params(**kw)
+    _, gpu = _run(torch_cuda, gp, pair.left, pair.right)
+    exp = ref.compute(pair.left, pair.right, oracle_params(ref, gp))
+    assert_parity(gpu, exp, name)
+
+
+def test_padded_pitches(torch_cuda, ref):
+    from paper_2106_07136_amd import bdis
+    pair = synth.make_pair(150, 100, 12.0, seed=77)
+    gp = bdis.Params(levels=3, iters=8)
+    _, gpu = _run(torch_cuda, gp, pair.left, pair.right, pitch_pad=37, out_pad=5)
+    exp = ref.compute(pair.left, pair.right, oracle_params(ref, gp))
+    assert_parity(gpu, exp, "padded")
+
+
+def test_constant_image_all_unestimated(torch_cuda):
+    from paper_2106_07136_amd import bdis
+    c = np.full((48, 64), 120, np.uint8)
+    _, gpu = _run(torch_cuda, bdis.Params(levels=3), c, c)
+    assert np.isnan(gpu).all()
+
+
+def test_deterministic(torch_cuda):
+    from paper_2106_07136_amd import bdis
+    pair = synth.make_pair(320, 240, 32.0, seed=5)
+    h = bdis.Bdis(bdis.Params(levels=4))
+    L = torch_cuda.from_numpy(pair.left).cuda()
+    R = torch_cuda.from_numpy(pair.right).cuda()
+    outs = [h.compute(L, R).cpu().numpy() for _ in range(5)]
+    for o in outs[1:]:
+        np.testing.assert_array_equal(o.view(np.uint32), outs[0].view(np.uint32))
+
+
+def test_side_stream(torch_cuda, ref):
+    from paper_2106_07136_amd import bdis
+    torch = torch_cuda
+    pair = synth.make_pair(160, 120, 16.0, seed=9)
+    h = bdis.Bdis(bdis.Params(levels=3, iters=8))
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        L = torch.from_numpy(pair.left).cuda()
+        R = torch.from_numpy(pair.right).cuda()
+        out = h.compute(L, R, stream=s)
+    s.synchronize()
+    exp = ref.compute(pair.left, pair.right, ref.Params(levels=3, iters=8))
+    assert_parity(out.cpu().numpy(), exp, "side stream")
+
+
+def test_invalid_args_leave_output_untouched(torch_cuda):
+    from paper_2106_07136_amd import bdis
+    torch = torch_cuda
+    h = bdis.Bdis(bdis.Params(levels=2))
+    L = torch.zeros((16, 16), dtype=torch.uint8, device="cuda")
+    out = torch.full((16, 16), 3.0, device="cuda")
+    lib = bdis.lib()
+    # width below the patch side
+    assert lib.bdis_compute(h._h, L.data_ptr(), L.data_ptr(), 7, 16, 16, out.data_ptr(), 16, None) == bdis.E_INVALID_ARG
+    # pitch below the width
+    assert lib.bdis_compute(h._h, L.data_ptr(), L.data_ptr(), 16, 16, 8, out.data_ptr(), 16, None) == bdis.E_INVALID_ARG
+    # NULL output
+    assert lib.bdis_compute(h._h, L.data_ptr(), L.data_ptr(), 16, 16, 16, None, 16, None) == bdis.E_INVALID_ARG
+    torch.cuda.synchronize()
+    assert torch.all(out == 3.0).item()
+    assert b"pitch" in lib.bdis_last_error(h._h) or lib.bdis_last_error(h._h)
+
+
+def test_parity_without_convergence_test(torch_cuda, ref):
+    """conv_tol = 0 keeps non-converged patches (only the patch-side bound
+    remains).  Their final shift is sensitive to rounding, so this is the
+    hardest case for agreement; FP64 on both sides keeps it in tolerance."""
+    from paper_2106_07136_amd import bdis
+    pair = synth.make_pair(320, 240, 32.0, seed=11)
+    gp = bdis.Params(levels=4, iters=12, conv_tol=0.0)
+    _, gpu = _run(torch_cuda, gp, pair.left, pair.right)
+    exp = ref.compute(pair.left, pair.right, oracle_params(ref, gp))
+    assert_parity(gpu, exp, "conv_tol=0")
+
+
+@pytest.mark.parametrize("name", sorted(CONFIGS))
+def test_fp32_option(torch_cuda, ref, name):
+    """precision = 1 runs the same kernels in FP32.  FP32 rounding flips a
+    few discrete patch decisions, so only the per-pixel agreement is held to
+    the bar here; the RMS over a few flipped pixels is reported."""
+    from paper_2106_07136_amd import bdis
+    W, H, dmax, seed, kw = CONFIGS[name]
+    pair = synth.make_pair(W, H, dmax, seed)
+    gp = bdis.Params(precision=1, **kw)
+    _, gpu = _run(torch_cuda, gp, pair.left, pair.right)
+    exp = ref.compute(pair.left, pair.right, oracle_params(ref, gp))
+    m = parity(gpu, exp)
+    print(f"fp32 {name}: {m}", flush=True)
+    assert m["agree"] >= 0.998 and m["frac"] >= 0.998

@@ -38,6 +38,8 @@ MUTATIONS = {
                      "if (y < H && x < W && m[(size_t)y * W + x])\n                        ok = 2;"),
     "dis_weight_inverse": ("w = 1.0 / (q > 1.0 ? q : 1.0);", "w = (q > 1.0 ? q : 1.0);"),
     "uncovered_zero": ("v = NAN; /* Sec. 3.2", "v = 0.0; /* Sec. 3.2"),
+    "convergence_test_off": ("(P->conv_tol > 0 && P->iters > 0 &&", "(0 && P->iters > 0 &&"),
+    "divergence_bound_off": ("fabs(o->u - u0) > (double)p ||", "0 ||"),
 }
 
 

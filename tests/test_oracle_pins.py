@@ -406,6 +406,39 @@ def test_e2e_integer_shift_recovered(ref, W, H, s, levels):
     assert np.nanmax(np.abs(inner - s)) <= 1e-3
 
 
+def test_e2e_unconverged_patches_discarded(ref):
+    """Sec. 3.2 discards patches that do not converge.  One LK step from zero
+    toward a 2 px shift moves about 2 px, far above the 0.05 px tolerance:
+    every patch is discarded.  Thirty steps converge: every patch is kept.
+    With the test off, the single-step patches are kept."""
+    P = synth.integer_shift_pair(64, 32, 2, seed=13)
+    d1 = ref.compute(P.left, P.right, ref.Params(levels=1, iters=1))
+    assert np.isnan(d1).all()
+    d30 = ref.compute(P.left, P.right, ref.Params(levels=1, iters=30))
+    assert np.isfinite(d30[:, 10:]).all()
+    assert np.nanmax(np.abs(d30[4:-4, 12:-8] - 2)) < 1e-6
+    d1off = ref.compute(P.left, P.right, ref.Params(levels=1, iters=1, conv_tol=0.0))
+    assert np.isfinite(d1off[:, 10:]).all()
+
+
+def test_e2e_far_converged_patches_discarded(ref):
+    """A long-period sinusoid shifted by 10 px: LK from zero converges to the
+    true shift, 10 px from its start.  That is more than an 8 px patch side,
+    so every 8x8 patch is discarded; 12x12 patches (bound 12) are kept."""
+    W, H = 96, 16
+    x = np.arange(W)
+    row = np.clip(np.rint(128 + 90 * np.sin(2 * np.pi * x / 64.0)), 0, 255)
+    L = np.tile(row, (H, 1)).astype(np.uint8)
+    R = L[:, np.clip(x + 10, 0, W - 1)].copy()
+    st, u, *_ = ref.patch_lk(L.astype(float), R.astype(float), np.ones_like(L), 40, 4, 8, 60, 0.0)
+    assert st == 0 and abs(u + 10) < 1e-9
+    d8 = ref.compute(L, R, ref.Params(levels=1, patch=8, stride=4, iters=60))
+    assert np.isnan(d8).all()
+    d12 = ref.compute(L, R, ref.Params(levels=1, patch=12, stride=4, iters=60))
+    inner = d12[:, 12:W - 24]
+    assert np.isfinite(inner).all() and np.abs(inner - 10).max() < 1e-6
+
+
 def test_e2e_constant_image_is_unestimated(ref):
     c = np.full((40, 48), 100, np.uint8)
     d = ref.compute(c, c, ref.Params(levels=2))
