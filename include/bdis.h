@@ -168,6 +168,26 @@ BDIS_API bdis_status bdis_set_tuning(bdis_t *h, int32_t n, const int32_t *max_wi
  * Errors: BDIS_E_STATE (no single-pair compute yet), BDIS_E_INVALID_ARG. */
 BDIS_API bdis_status bdis_debug_stage(bdis_t *h, int32_t stage, int32_t level, void *dst, size_t bytes);
 
+/* Per-kernel timing of the handle's launches, for measurement tools.  With
+ * profiling on, every kernel launch is bracketed by HIP events recorded on
+ * the launch stream (this adds a small gap between launches).  Entries are
+ * keyed by kernel and pyramid level, e.g. "lk_f64_p8_l0", "dense_f64_l0",
+ * "pyr_f64_l1". */
+typedef struct {
+    char name[48];
+    int32_t launches;
+    double total_ms;          /* sum of event-to-event durations            */
+} bdis_kernel_time;
+
+/* on = 1 starts recording (and clears earlier records), 0 stops. */
+BDIS_API bdis_status bdis_set_profiling(bdis_t *h, int32_t on);
+
+/* Waits for the recorded launches, then writes up to cap entries to the HOST
+ * array out (one per kernel name, in first-launch order) and sets *count to
+ * the number of entries available.  Records stay until the next
+ * bdis_set_profiling(h, 1). */
+BDIS_API bdis_status bdis_get_profile(bdis_t *h, bdis_kernel_time *out, int32_t cap, int32_t *count);
+
 /* Frees the handle and its workspace; NULL is allowed. */
 BDIS_API void bdis_destroy(bdis_t *h);
 

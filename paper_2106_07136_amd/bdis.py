@@ -42,6 +42,10 @@ class CPair(C.Structure):
                 ("disp_pitch_elems", C.c_int32)]
 
 
+class CKernelTime(C.Structure):
+    _fields_ = [("name", C.c_char * 48), ("launches", C.c_int32), ("total_ms", C.c_double)]
+
+
 class CPlan(C.Structure):
     _fields_ = [("levels", C.c_int32), ("width", C.c_int32 * 16), ("height", C.c_int32 * 16),
                 ("nx", C.c_int32 * 16), ("ny", C.c_int32 * 16), ("patches", C.c_int64),
@@ -102,6 +106,8 @@ def lib():
         L.bdis_compute_batch.argtypes = [vp, C.POINTER(CPair), i32, vp]
         L.bdis_set_tuning.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
         L.bdis_debug_stage.argtypes = [vp, i32, i32, vp, C.c_size_t]
+        L.bdis_set_profiling.argtypes = [vp, i32]
+        L.bdis_get_profile.argtypes = [vp, C.POINTER(CKernelTime), i32, C.POINTER(i32)]
         L.bdis_destroy.argtypes = [vp]
         L.bdis_destroy.restype = None
         L.bdis_status_string.argtypes = [C.c_int]
@@ -109,7 +115,8 @@ def lib():
         L.bdis_last_error.argtypes = [vp]
         L.bdis_last_error.restype = C.c_char_p
         for name in ("bdis_plan", "bdis_create", "bdis_set_params", "bdis_reserve", "bdis_compute",
-                     "bdis_compute_batch", "bdis_set_tuning", "bdis_debug_stage"):
+                     "bdis_compute_batch", "bdis_set_tuning", "bdis_debug_stage",
+                     "bdis_set_profiling", "bdis_get_profile"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -226,3 +233,14 @@ class Bdis:
         a = np.empty(shape, dt)
         _check(lib().bdis_debug_stage(self._h, stage, level, a.ctypes.data, a.nbytes), self._h)
         return a
+
+    def set_profiling(self, on: bool):
+        _check(lib().bdis_set_profiling(self._h, 1 if on else 0), self._h)
+
+    def profile(self) -> dict:
+        """{kernel name: (launches, total ms)} of the recorded launches."""
+        cnt = C.c_int32()
+        _check(lib().bdis_get_profile(self._h, None, 0, C.byref(cnt)), self._h)
+        arr = (CKernelTime * max(cnt.value, 1))()
+        _check(lib().bdis_get_profile(self._h, arr, cnt.value, C.byref(cnt)), self._h)
+        return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms) for i in range(cnt.value)}

@@ -21,6 +21,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <climits>
+#include <type_traits>
 
 namespace bdis {
 
@@ -122,18 +124,44 @@ __device__ __forceinline__ T pixv(const void *img, size_t idx) {
     else return fabs(static_cast<const T *>(img)[idx]);
 }
 
-// Sum over aligned segments of SEG lanes; every lane of a segment receives
-// the bitwise-same total (the butterfly adds commuting pairs).
+// Lane swizzles inside a row of 16 lanes (DPP): swap neighbours, swap pairs,
+// mirror each half-row of 8, mirror the row of 16.
+constexpr int kDppXor1 = 0xB1;    // quad_perm [1, 0, 3, 2]
+constexpr int kDppXor2 = 0x4E;    // quad_perm [2, 3, 0, 1]
+constexpr int kDppHalfMirror = 0x141;
+constexpr int kDppMirror = 0x140;
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_v(float v) {
+    return __int_as_float(dpp_i<CTRL>(__float_as_int(v)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_v(double v) {
+    int lo = dpp_i<CTRL>(__double2loint(v)), hi = dpp_i<CTRL>(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over aligned segments of SEG (8 or 16) lanes.  Every lane of a segment
+// receives the bitwise-same total: each step adds a commuting pair.  All
+// lanes of a segment must be active.
 template <int SEG, typename T>
 __device__ __forceinline__ T seg_sum(T v) {
-#pragma unroll
-    for (int m = SEG / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, SEG);
+    v += dpp_v<kDppXor1>(v);
+    v += dpp_v<kDppXor2>(v);
+    v += dpp_v<kDppHalfMirror>(v);
+    if constexpr (SEG == 16) v += dpp_v<kDppMirror>(v);
     return v;
 }
 template <int SEG>
 __device__ __forceinline__ int seg_sum_i(int v) {
-#pragma unroll
-    for (int m = SEG / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, SEG);
+    v += dpp_i<kDppXor1>(v);
+    v += dpp_i<kDppXor2>(v);
+    v += dpp_i<kDppHalfMirror>(v);
+    if constexpr (SEG == 16) v += dpp_i<kDppMirror>(v);
     return v;
 }
 
@@ -216,6 +244,25 @@ __global__ __launch_bounds__(kBlock) void k_pyr(const PyrJob *jobs, int njobs, K
 
 enum { ST_KEPT = 0, ST_DEGENERATE = 1, ST_DIVERGED = 2, ST_GATED = 3 };
 
+// Patches per block and the widest span of right-image columns a block stages.
+template <int P> struct LkShape {
+    static constexpr int SEG = P <= 8 ? 8 : 16;  // lanes per patch (one per patch row)
+    static constexpr int PPB = kBlock / SEG;     // patches per block, one patch row
+    static constexpr int NCMAX = 320;            // staged columns per image row
+};
+
+template <int P>
+__host__ __device__ constexpr int lk_blocks_per_row(int nx) {
+    return (nx + LkShape<P>::PPB - 1) / LkShape<P>::PPB;
+}
+
+// A block takes up to PPB consecutive patches of one patch row.  It stages
+// the P right-image rows of those patches in LDS over the columns their
+// initial shifts reach, plus a margin of P + 2 (a kept patch ends within P
+// of its start; the window adds 1), so every LK iteration and window sample
+// reads LDS; an iterate outside the staged span reads global memory instead,
+// with the same values.
+//
 // One patch per segment of SEG lanes, one patch row per lane (lanes >= P of a
 // 16-lane segment idle).  Per lane: the template row, the mean-normalised
 // template gradient J (the inverse-compositional Jacobian, computed once on
@@ -224,37 +271,36 @@ enum { ST_KEPT = 0, ST_DEGENERATE = 1, ST_DIVERGED = 2, ST_GATED = 3 };
 // left-valid pixels, sum J e equals sum J d without subtracting the residual
 // mean.  A patch is kept only if the iteration converged (last step within
 // conv_tol, shift within a patch side of its start).  Then the window
-// energies E_i = sum (d - mean d)^2 at u + (i - c) step and the posterior
-// p = 1 / sum_i exp(-(E_i - E_c) / tau), and the gamma gate.
+// energies E_i = sum (d - mean d)^2 at u + (i - c) step, the posterior
+// p = 1 / sum_i exp(-(E_i - E_c) / tau) (eqs. (3)-(4)) and the gamma gate.
 template <typename T, int P, bool U8>
 __global__ __launch_bounds__(kBlock) void k_lk(const LkJob *jobs, int njobs, KParams kp) {
-    constexpr int SEG = P <= 8 ? 8 : 16;
-    constexpr int PPB = kBlock / SEG;
+    using S = LkShape<P>;
+    constexpr int SEG = S::SEG, PPB = S::PPB, NCMAX = S::NCMAX;
+    constexpr int NCPAD = NCMAX + 1;
+    __shared__ T Rs[P * NCPAD];
+    __shared__ int s_umin, s_umax;
+
     const LkJob &J = jobs[find_job(jobs, njobs, (int)blockIdx.x)];
-    const int np = J.nx * J.ny;
+    const int W = J.W;
+    const int bpr = lk_blocks_per_row<P>(J.nx);
+    const int lb = (int)blockIdx.x - J.block0;
+    const int jy = lb / bpr, jx0 = (lb - jy * bpr) * PPB;
     const int slot = (int)threadIdx.x / SEG, r = (int)threadIdx.x % SEG;
-    const int k_raw = ((int)blockIdx.x - J.block0) * PPB + slot;
-    const bool live = k_raw < np;
-    const int k = live ? k_raw : np - 1;  // idle segments shadow the last patch
-    const int jy = k / J.nx, jx = k - jy * J.nx;
-    const int x0 = grid_pos(jx, J.W, P, J.stride), y0 = grid_pos(jy, J.H, P, J.stride);
+    const int jx_raw = jx0 + slot;
+    const bool live = jx_raw < J.nx;
+    const int jx = live ? jx_raw : J.nx - 1;  // idle segments shadow the row's last patch
+    const int k = jy * J.nx + jx;
+    const int x0 = grid_pos(jx, W, P, J.stride), y0 = grid_pos(jy, J.H, P, J.stride);
     const bool row_on = r < P;
     const int y = y0 + (row_on ? r : 0);
-    const int W = J.W;
     const size_t row0 = (size_t)y * J.pitch;
 
-    // initial shift: twice the coarse field at the patch centre (Sec. 2.1)
-    T u0 = 0;
-    if (J.Uc) {
-        T cx = (T)x0 + T(0.5) * (T)(P - 1), cy = (T)y0 + T(0.5) * (T)(P - 1);
-        u0 = T(2) * bilinear<T>(static_cast<const T *>(J.Uc), J.Wc, J.Hc, T(0.5) * cx, T(0.5) * cy);
-    }
+    if (threadIdx.x == 0) { s_umin = INT_MAX; s_umax = INT_MIN; }
 
-    // template row, gradient, validity
+    // template row and gradient (independent of the shift: issued first)
     T Tv[P], Jg[P];
     uint32_t vmask = 0;
-    T gsum = 0;
-    int nloc = 0;
 #pragma unroll
     for (int c = 0; c < P; c++) {
         int x = x0 + c;
@@ -265,8 +311,81 @@ __global__ __launch_bounds__(kBlock) void k_lk(const LkJob *jobs, int njobs, KPa
         Jg[c] = T(0.5) * (gp - gm);
         v = v && row_on;
         vmask |= (uint32_t)v << c;
-        if (v) { gsum += Jg[c]; nloc++; }
     }
+
+    // initial shift: twice the coarse field at the patch centre (Sec. 2.1)
+    T u0 = 0;
+    if (J.Uc) {
+        T cx = (T)x0 + T(0.5) * (T)(P - 1), cy = (T)y0 + T(0.5) * (T)(P - 1);
+        u0 = T(2) * bilinear<T>(static_cast<const T *>(J.Uc), J.Wc, J.Hc, T(0.5) * cx, T(0.5) * cy);
+    }
+    const T ulo = -(T)(W + P + 2), uhi = (T)(W + 2);
+    const int iu0 = (int)floor(fmin(fmax(u0, ulo), uhi));
+    __syncthreads();
+    if (r == 0 && live) {
+        atomicMin(&s_umin, x0 + iu0);
+        atomicMax(&s_umax, x0 + iu0);
+    }
+    __syncthreads();
+    int col_lo = max(0, s_umin - (P + 2));
+    int col_hi = min(W - 1, s_umax + P + (P + 2));
+    if (col_hi - col_lo + 1 > NCMAX) {  // wide disparity spread: keep a centred span
+        int mid = (s_umin + s_umax + P) / 2;
+        col_lo = max(0, min(mid - NCMAX / 2, W - NCMAX));
+        col_hi = min(W - 1, col_lo + NCMAX - 1);
+    }
+    const int nc = col_hi - col_lo + 1;
+    for (int e = (int)threadIdx.x; e < P * nc; e += kBlock) {
+        int rr = e / nc, cc = e - rr * nc;
+        size_t g = (size_t)(y0 + rr) * J.pitch + (size_t)(col_lo + cc);
+        if constexpr (U8) Rs[rr * NCPAD + cc] = (T) static_cast<const uint8_t *>(J.R)[g];
+        else Rs[rr * NCPAD + cc] = static_cast<const T *>(J.R)[g];
+    }
+    __syncthreads();
+
+    // LDS index of column c of this lane's staged row is rbase + c, which is
+    // >= 0 exactly for the staged columns c >= col_lo (the array is only ever
+    // indexed, never offset before its start)
+    const int rbase = (row_on ? r : 0) * NCPAD - col_lo;
+    // raw right values (sign = validity above level 0) of columns
+    // clamp(c0 + c, 0, W-1), c = 0..N-1: all reads issued back to back, from
+    // LDS when the whole span is staged, else from global memory
+    auto fetch = [&](int c0, T *v, auto N_) {
+        constexpr int N = decltype(N_)::value;
+        const bool staged = max(c0, 0) >= col_lo && min(c0 + N - 1, W - 1) <= col_hi;
+        if (staged) {
+#pragma unroll
+            for (int c = 0; c < N; c++) v[c] = Rs[rbase + min(max(c0 + c, 0), W - 1)];
+        } else {
+#pragma unroll
+            for (int c = 0; c < N; c++) {
+                size_t g = row0 + (size_t)min(max(c0 + c, 0), W - 1);
+                if constexpr (U8) v[c] = (T) static_cast<const uint8_t *>(J.R)[g];
+                else v[c] = static_cast<const T *>(J.R)[g];
+            }
+        }
+    };
+    // I_r at x0 + c + shift for the patch row, shift = xi0 - x0 + uf with
+    // 0 <= uf < 1, coordinate clamped to [0, W-1]: left of the row f = 0,
+    // right of it f = 1, inside (1 - f) R[m] + f R[m + 1]
+    auto sample = [&](int xi0, T uf, T *out) {
+        T v[P + 1];
+        fetch(xi0, v, std::integral_constant<int, P + 1>());
+#pragma unroll
+        for (int c = 0; c <= P; c++) if constexpr (!U8) v[c] = fabs(v[c]);
+#pragma unroll
+        for (int c = 0; c < P; c++) {
+            int xi = xi0 + c;
+            T f = xi < 0 ? T(0) : (xi >= W - 1 ? T(1) : uf);
+            out[c] = (T(1) - f) * v[c] + f * v[c + 1];
+        }
+    };
+
+    int nloc = 0;
+    T gsum = 0;
+#pragma unroll
+    for (int c = 0; c < P; c++)
+        if ((vmask >> c) & 1u) { gsum += Jg[c]; nloc++; }
     const int n = seg_sum_i<SEG>(nloc);
     gsum = seg_sum<SEG>(gsum);
     const T gmean = n > 0 ? gsum / (T)n : T(0);
@@ -283,18 +402,15 @@ __global__ __launch_bounds__(kBlock) void k_lk(const LkJob *jobs, int njobs, KPa
     if (n == 0 || !(Hs > (T)kp.eps_h * (T)n)) {
         status = ST_DEGENERATE;
     } else {
-        const T ulo = -(T)(W + P + 2), uhi = (T)(W + 2);
         T step = 0;
         for (int t = 0; t < kp.iters; t++) {
             T uc = fmin(fmax(u, ulo), uhi);
             T ui = floor(uc), uf = uc - ui;
-            int xi0 = x0 + (int)ui;
+            T I[P];
+            sample(x0 + (int)ui, uf, I);
             T s = 0;
 #pragma unroll
-            for (int c = 0; c < P; c++) {
-                T I = sample_row<T, U8>(J.R, row0, W, xi0 + c, uf);
-                s += Jg[c] * (I - Tv[c]);
-            }
+            for (int c = 0; c < P; c++) s += Jg[c] * (I[c] - Tv[c]);
             T b = seg_sum<SEG>(s);
             step = b / Hs;
             u = u - step;
@@ -311,12 +427,12 @@ __global__ __launch_bounds__(kBlock) void k_lk(const LkJob *jobs, int njobs, KPa
             auto energy = [&](T ud) -> T {
                 T uc = fmin(fmax(ud, ulo), uhi);
                 T ui = floor(uc), uf = uc - ui;
-                int xi0 = x0 + (int)ui;
                 T d[P];
+                sample(x0 + (int)ui, uf, d);
                 T ds = 0;
 #pragma unroll
                 for (int c = 0; c < P; c++) {
-                    d[c] = sample_row<T, U8>(J.R, row0, W, xi0 + c, uf) - Tv[c];
+                    d[c] -= Tv[c];
                     if ((vmask >> c) & 1u) ds += d[c];
                 }
                 T mean = seg_sum<SEG>(ds) / (T)n;
@@ -341,18 +457,26 @@ __global__ __launch_bounds__(kBlock) void k_lk(const LkJob *jobs, int njobs, KPa
             T uc = fmin(fmax(u, ulo), uhi);
             T ui = floor(uc), uf = uc - ui;
             int xi0 = x0 + (int)ui;
+            // taps m = min(xi, W-2) and m + 1 for xi = xi0 .. xi0+P-1
+            int m0 = min(max(xi0, 0), W - 2);
+            T v[P + 2];
+            fetch(m0, v, std::integral_constant<int, P + 2>());
             int cnt = 0;
 #pragma unroll
             for (int c = 0; c < P; c++) {
                 int xi = xi0 + c;
                 bool inb = xi >= 0 && (xi < W - 1 || (xi == W - 1 && uf == T(0)));
-                if (((vmask >> c) & 1u) && inb) {
-                    int m = min(xi, W - 2);
-                    bool a, b;
-                    (void)pix<T, U8>(J.R, row0 + m, kp, a);
-                    (void)pix<T, U8>(J.R, row0 + m + 1, kp, b);
-                    cnt += (a && b) ? 1 : 0;
+                int m = min(max(xi, 0), W - 2) - m0;  // 0 <= m <= P
+                T a = v[m], b = v[m + 1];
+                bool va, vb;
+                if constexpr (U8) {
+                    va = a >= (T)kp.vlo && a <= (T)kp.vhi;
+                    vb = b >= (T)kp.vlo && b <= (T)kp.vhi;
+                } else {
+                    va = !signbit(a);
+                    vb = !signbit(b);
                 }
+                cnt += (((vmask >> c) & 1u) && inb && va && vb) ? 1 : 0;
             }
             cnt = seg_sum_i<SEG>(cnt);
             if (cnt < kp.min_valid) {

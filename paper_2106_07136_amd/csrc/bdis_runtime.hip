@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "bdis.h"
@@ -182,6 +183,14 @@ struct bdis_ctx {
     bool have_last = false;
     PairIn last;
     hipStream_t last_stream = nullptr;
+    // profiling: events around each launch, resolved in bdis_get_profile
+    bool profiling = false;
+    struct Rec { std::string name; hipEvent_t a, b; };
+    std::vector<Rec> pending;
+    std::vector<hipEvent_t> spare;
+    std::vector<std::string> prof_names;
+    std::vector<int> prof_count;
+    std::vector<double> prof_ms;
     // autotuner table
     int ntune = 0;
     int tune_w[kMaxTuning], tune_p[kMaxTuning], tune_s[kMaxTuning];
@@ -291,6 +300,7 @@ bdis_status ensure_jobs(bdis_t *h, size_t bytes) {
 enum Kind { K_PYR, K_LK, K_DENSE };
 struct Launch {
     Kind kind;
+    int level;
     int patch;
     bool u8;
     bool f64;
@@ -301,13 +311,24 @@ struct Launch {
 };
 
 template <typename Job>
-void append(std::vector<char> &tab, std::vector<Launch> &ls, Kind kind, int patch, bool u8, bool f64,
+void append(std::vector<char> &tab, std::vector<Launch> &ls, Kind kind, int level, int patch, bool u8, bool f64,
             const std::vector<Job> &jobs, int blocks, const KParams &kp) {
     if (jobs.empty() || blocks == 0) return;
     size_t off = align_up(tab.size(), 64);
     tab.resize(off + jobs.size() * sizeof(Job));
     memcpy(tab.data() + off, jobs.data(), jobs.size() * sizeof(Job));
-    ls.push_back(Launch{kind, patch, u8, f64, off, (int)jobs.size(), blocks, kp});
+    ls.push_back(Launch{kind, level, patch, u8, f64, off, (int)jobs.size(), blocks, kp});
+}
+
+int lk_bpr(int P, int nx) {
+    switch (P) {
+    case 4: return lk_blocks_per_row<4>(nx);
+    case 6: return lk_blocks_per_row<6>(nx);
+    case 8: return lk_blocks_per_row<8>(nx);
+    case 10: return lk_blocks_per_row<10>(nx);
+    case 12: return lk_blocks_per_row<12>(nx);
+    default: return lk_blocks_per_row<16>(nx);
+    }
 }
 
 // Build every launch for a set of pairs: pyramid levels 1..Lmax-1, then for
@@ -334,13 +355,12 @@ void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<char> &tab
             blocks += (j.wd * j.hd + kBlock - 1) / kBlock;
             jobs.push_back(j);
         }
-        append(tab, ls, K_PYR, 0, l == 1, f64, jobs, blocks, kp0);
+        append(tab, ls, K_PYR, l, 0, l == 1, f64, jobs, blocks, kp0);
     }
     for (int l = Lmax - 1; l >= 0; l--) {
         for (int P : kSupportedPatch) {
             std::vector<LkJob> jobs;
             int blocks = 0;
-            int ppb = kBlock / (P <= 8 ? 8 : 16);
             for (auto &p : pairs) {
                 if (p.g.L <= l || p.patch != P) continue;
                 LkJob j;
@@ -356,10 +376,10 @@ void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<char> &tab
                 j.rec_u = p.ws.rec_u[l]; j.rec_w = p.ws.rec_w[l];
                 j.rec_u0 = p.ws.rec_u0[l]; j.rec_st = p.ws.rec_st[l];
                 j.block0 = blocks;
-                blocks += (j.nx * j.ny + ppb - 1) / ppb;
+                blocks += j.ny * lk_bpr(P, j.nx);
                 jobs.push_back(j);
             }
-            append(tab, ls, K_LK, P, l == 0, f64, jobs, blocks, make_kparams(h->prm, P));
+            append(tab, ls, K_LK, l, P, l == 0, f64, jobs, blocks, make_kparams(h->prm, P));
         }
         std::vector<DenseJob> jobs;
         int blocks = 0;
@@ -387,7 +407,7 @@ void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<char> &tab
             blocks += (j.W * j.H + kBlock - 1) / kBlock;
             jobs.push_back(j);
         }
-        append(tab, ls, K_DENSE, 0, l == 0, f64, jobs, blocks, kp0);
+        append(tab, ls, K_DENSE, l, 0, l == 0, f64, jobs, blocks, kp0);
     }
 }
 
@@ -426,10 +446,44 @@ void launch_one(const Launch &L, const char *base, hipStream_t s) {
     }
 }
 
-void launch_all(const std::vector<Launch> &ls, const char *base, hipStream_t s) {
+std::string launch_name(const Launch &L) {
+    char buf[48];
+    const char *t = L.f64 ? "f64" : "f32";
+    switch (L.kind) {
+    case K_PYR: snprintf(buf, sizeof buf, "pyr_%s_l%d", t, L.level); break;
+    case K_LK: snprintf(buf, sizeof buf, "lk_%s_p%d_l%d", t, L.patch, L.level); break;
+    default: snprintf(buf, sizeof buf, "dense_%s_l%d", t, L.level); break;
+    }
+    return buf;
+}
+
+void launch_all(bdis_t *h, const std::vector<Launch> &ls, const char *base, hipStream_t s);
+
+hipEvent_t take_event(bdis_t *h) {
+    if (!h->spare.empty()) {
+        hipEvent_t e = h->spare.back();
+        h->spare.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+void launch_all(bdis_t *h, const std::vector<Launch> &ls, const char *base, hipStream_t s) {
     for (const Launch &L : ls) {
+        hipEvent_t a = nullptr, b = nullptr;
+        if (h->profiling) {
+            a = take_event(h);
+            b = take_event(h);
+            if (a && b) (void)hipEventRecord(a, s);
+        }
         if (L.f64) launch_one<double>(L, base, s);
         else launch_one<float>(L, base, s);
+        if (h->profiling && a && b) {
+            (void)hipEventRecord(b, s);
+            h->pending.push_back({launch_name(L), a, b});
+        }
     }
 }
 
@@ -486,7 +540,7 @@ bdis_status run(bdis_t *h, std::vector<PairIn> &pairs, hipStream_t s) {
         h->upload_pending = true;
         h->last_upload = tab;
     }
-    launch_all(ls, h->djobs, s);
+    launch_all(h, ls, h->djobs, s);
     HIPCHK(h, hipGetLastError());
     return BDIS_OK;
 }
@@ -697,6 +751,52 @@ bdis_status bdis_debug_stage(bdis_t *h, int32_t stage, int32_t level, void *dst,
     return BDIS_OK;
 }
 
+bdis_status bdis_set_profiling(bdis_t *h, int32_t on) {
+    if (!h) { set_err(g_thread_err, "handle is NULL"); return BDIS_E_INVALID_ARG; }
+    DeviceGuard dg(h->device);
+    if (on) {
+        HIPCHK(h, hipDeviceSynchronize());
+        for (auto &r : h->pending) { h->spare.push_back(r.a); h->spare.push_back(r.b); }
+        h->pending.clear();
+        h->prof_names.clear();
+        h->prof_count.clear();
+        h->prof_ms.clear();
+    }
+    h->profiling = on != 0;
+    return BDIS_OK;
+}
+
+bdis_status bdis_get_profile(bdis_t *h, bdis_kernel_time *out, int32_t cap, int32_t *count) {
+    if (!h) { set_err(g_thread_err, "handle is NULL"); return BDIS_E_INVALID_ARG; }
+    if (!count || cap < 0 || (cap > 0 && !out)) { set_err(h->err, "bad output arguments"); return BDIS_E_INVALID_ARG; }
+    DeviceGuard dg(h->device);
+    for (auto &r : h->pending) {
+        HIPCHK(h, hipEventSynchronize(r.b));
+        float ms = 0.f;
+        HIPCHK(h, hipEventElapsedTime(&ms, r.a, r.b));
+        size_t i = 0;
+        while (i < h->prof_names.size() && h->prof_names[i] != r.name) i++;
+        if (i == h->prof_names.size()) {
+            h->prof_names.push_back(r.name);
+            h->prof_count.push_back(0);
+            h->prof_ms.push_back(0.0);
+        }
+        h->prof_count[i]++;
+        h->prof_ms[i] += ms;
+        h->spare.push_back(r.a);
+        h->spare.push_back(r.b);
+    }
+    h->pending.clear();
+    *count = (int32_t)h->prof_names.size();
+    for (int32_t i = 0; i < cap && i < *count; i++) {
+        memset(&out[i], 0, sizeof out[i]);
+        snprintf(out[i].name, sizeof out[i].name, "%s", h->prof_names[i].c_str());
+        out[i].launches = h->prof_count[i];
+        out[i].total_ms = h->prof_ms[i];
+    }
+    return BDIS_OK;
+}
+
 void bdis_destroy(bdis_t *h) {
     if (!h) return;
     {
@@ -708,6 +808,8 @@ void bdis_destroy(bdis_t *h) {
         if (h->gtab_d) (void)hipFree(h->gtab_d);
         if (h->gtab_f) (void)hipFree(h->gtab_f);
         if (h->upload_ev) (void)hipEventDestroy(h->upload_ev);
+        for (auto &r : h->pending) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+        for (auto e : h->spare) (void)hipEventDestroy(e);
     }
     delete h;
 }
