@@ -70,7 +70,7 @@ typedef struct {
     int32_t iters;            /* K, LK iterations per level (no early exit)  */
     float sigma_r;            /* eq. (4) brightness spread, gray levels      */
     float sigma_s;            /* eq. (5) spatial spread, level pixels        */
-    int32_t window;           /* samples in the posterior window (odd, <=15) */
+    int32_t window;           /* samples in the posterior window (odd, <= 9) */
     float window_step;        /* spacing of the window samples, level px     */
     float gamma;              /* valid-pixel ratio below which a patch is
                                  discarded, in [0, 1]                         */

@@ -57,6 +57,8 @@ struct LkJob {
     const void *Uc;        // coarse field (level + 1), pitch Wc; null at coarsest
     int Wc, Hc;
     int nx, ny, stride;
+    int reach;             // staged span reaches this many columns left of a
+                           // patch (the level's largest expected disparity)
     void *rec_u, *rec_w, *rec_u0;  // arithmetic type
     int8_t *rec_st;
     int block0;
@@ -79,12 +81,22 @@ struct DenseJob {
 
 // ---------------------------------------------------------------- helpers
 
+// Jobs of one launch, passed by value as the kernel argument (read through
+// the scalar path from the kernel-argument segment: no dependent load of a
+// table).  A launch carries at most kMaxJobs jobs; larger sets are split.
+constexpr int kMaxJobs = 24;
 template <typename Job>
-__device__ __forceinline__ int find_job(const Job *jobs, int njobs, int b) {
-    int lo = 0, hi = njobs - 1;
+struct JobPack {
+    int n;
+    Job j[kMaxJobs];
+};
+
+template <typename Job>
+__device__ __forceinline__ int find_job(const JobPack<Job> &pk, int b) {
+    int lo = 0, hi = pk.n - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
-        if (jobs[mid].block0 <= b) lo = mid; else hi = mid - 1;
+        if (pk.j[mid].block0 <= b) lo = mid; else hi = mid - 1;
     }
     return lo;
 }
@@ -156,6 +168,21 @@ __device__ __forceinline__ T seg_sum(T v) {
     if constexpr (SEG == 16) v += dpp_v<kDppMirror>(v);
     return v;
 }
+// seg_sum on N independent values at once (the DPP chains interleave)
+template <int SEG, int N, typename T>
+__device__ __forceinline__ void seg_sum_n(T *v) {
+#pragma unroll
+    for (int i = 0; i < N; i++) v[i] += dpp_v<kDppXor1>(v[i]);
+#pragma unroll
+    for (int i = 0; i < N; i++) v[i] += dpp_v<kDppXor2>(v[i]);
+#pragma unroll
+    for (int i = 0; i < N; i++) v[i] += dpp_v<kDppHalfMirror>(v[i]);
+    if constexpr (SEG == 16) {
+#pragma unroll
+        for (int i = 0; i < N; i++) v[i] += dpp_v<kDppMirror>(v[i]);
+    }
+}
+
 template <int SEG>
 __device__ __forceinline__ int seg_sum_i(int v) {
     v += dpp_i<kDppXor1>(v);
@@ -198,8 +225,8 @@ __device__ __forceinline__ T sample_row(const void *img, size_t row0, int W, int
 // existing 2x2 fine children are valid.  In double precision every level up
 // to the fifth is exact (dyadic sums of 8-bit values).
 template <typename T, bool U8>
-__global__ __launch_bounds__(kBlock) void k_pyr(const PyrJob *jobs, int njobs, KParams kp) {
-    const PyrJob &J = jobs[find_job(jobs, njobs, (int)blockIdx.x)];
+__global__ __launch_bounds__(kBlock) void k_pyr(const JobPack<PyrJob> pk, KParams kp) {
+    const PyrJob &J = pk.j[find_job(pk, (int)blockIdx.x)];
     int i = ((int)blockIdx.x - J.block0) * kBlock + (int)threadIdx.x;
     if (i >= J.wd * J.hd) return;
     int yc = i / J.wd, xc = i - yc * J.wd;
@@ -248,7 +275,7 @@ enum { ST_KEPT = 0, ST_DEGENERATE = 1, ST_DIVERGED = 2, ST_GATED = 3 };
 template <int P> struct LkShape {
     static constexpr int SEG = P <= 8 ? 8 : 16;  // lanes per patch (one per patch row)
     static constexpr int PPB = kBlock / SEG;     // patches per block, one patch row
-    static constexpr int NCMAX = 320;            // staged columns per image row
+    static constexpr int NCMAX = 384;            // staged columns per image row
 };
 
 template <int P>
@@ -274,14 +301,13 @@ __host__ __device__ constexpr int lk_blocks_per_row(int nx) {
 // energies E_i = sum (d - mean d)^2 at u + (i - c) step, the posterior
 // p = 1 / sum_i exp(-(E_i - E_c) / tau) (eqs. (3)-(4)) and the gamma gate.
 template <typename T, int P, bool U8>
-__global__ __launch_bounds__(kBlock) void k_lk(const LkJob *jobs, int njobs, KParams kp) {
+__global__ __launch_bounds__(kBlock) void k_lk(const JobPack<LkJob> pk, KParams kp) {
     using S = LkShape<P>;
     constexpr int SEG = S::SEG, PPB = S::PPB, NCMAX = S::NCMAX;
     constexpr int NCPAD = NCMAX + 1;
     __shared__ T Rs[P * NCPAD];
-    __shared__ int s_umin, s_umax;
 
-    const LkJob &J = jobs[find_job(jobs, njobs, (int)blockIdx.x)];
+    const LkJob &J = pk.j[find_job(pk, (int)blockIdx.x)];
     const int W = J.W;
     const int bpr = lk_blocks_per_row<P>(J.nx);
     const int lb = (int)blockIdx.x - J.block0;
@@ -295,8 +321,6 @@ __global__ __launch_bounds__(kBlock) void k_lk(const LkJob *jobs, int njobs, KPa
     const bool row_on = r < P;
     const int y = y0 + (row_on ? r : 0);
     const size_t row0 = (size_t)y * J.pitch;
-
-    if (threadIdx.x == 0) { s_umin = INT_MAX; s_umax = INT_MIN; }
 
     // template row and gradient (independent of the shift: issued first)
     T Tv[P], Jg[P];
@@ -320,26 +344,42 @@ __global__ __launch_bounds__(kBlock) void k_lk(const LkJob *jobs, int njobs, KPa
         u0 = T(2) * bilinear<T>(static_cast<const T *>(J.Uc), J.Wc, J.Hc, T(0.5) * cx, T(0.5) * cy);
     }
     const T ulo = -(T)(W + P + 2), uhi = (T)(W + 2);
-    const int iu0 = (int)floor(fmin(fmax(u0, ulo), uhi));
-    __syncthreads();
-    if (r == 0 && live) {
-        atomicMin(&s_umin, x0 + iu0);
-        atomicMax(&s_umax, x0 + iu0);
-    }
-    __syncthreads();
-    int col_lo = max(0, s_umin - (P + 2));
-    int col_hi = min(W - 1, s_umax + P + (P + 2));
-    if (col_hi - col_lo + 1 > NCMAX) {  // wide disparity spread: keep a centred span
-        int mid = (s_umin + s_umax + P) / 2;
-        col_lo = max(0, min(mid - NCMAX / 2, W - NCMAX));
-        col_hi = min(W - 1, col_lo + NCMAX - 1);
-    }
+
+    // Staged span of the block's right rows, from static bounds so the loads
+    // go out with the template and init loads: disparities d >= 0 shift the
+    // right sample left (u = -d), so the span reaches `reach` columns left of
+    // the first patch and a margin of P + 2 on both sides.
+    const int xf = grid_pos(jx0, W, P, J.stride);
+    const int xl = grid_pos(min(jx0 + PPB, J.nx) - 1, W, P, J.stride);
+    int col_hi = min(W - 1, xl + P + (P + 2));
+    int col_lo = max(0, xf - J.reach - (P + 2));
+    col_lo = max(col_lo, col_hi - NCMAX + 1);
     const int nc = col_hi - col_lo + 1;
-    for (int e = (int)threadIdx.x; e < P * nc; e += kBlock) {
-        int rr = e / nc, cc = e - rr * nc;
-        size_t g = (size_t)(y0 + rr) * J.pitch + (size_t)(col_lo + cc);
-        if constexpr (U8) Rs[rr * NCPAD + cc] = (T) static_cast<const uint8_t *>(J.R)[g];
-        else Rs[rr * NCPAD + cc] = static_cast<const T *>(J.R)[g];
+    // rows in passes of up to 8, columns in chunks of kBlock: every load of a
+    // pass is issued before the LDS writes (one memory round trip per pass)
+    constexpr int CH = (NCMAX + kBlock - 1) / kBlock;
+#pragma unroll
+    for (int r0 = 0; r0 < P; r0 += 8) {
+        T buf[8][CH];
+#pragma unroll
+        for (int rr = 0; rr < 8; rr++)
+#pragma unroll
+            for (int q = 0; q < CH; q++) {
+                int cc = (int)threadIdx.x + q * kBlock;
+                buf[rr][q] = T(0);
+                if (r0 + rr < P && cc < nc) {
+                    size_t g = (size_t)(y0 + r0 + rr) * J.pitch + (size_t)(col_lo + cc);
+                    if constexpr (U8) buf[rr][q] = (T) static_cast<const uint8_t *>(J.R)[g];
+                    else buf[rr][q] = static_cast<const T *>(J.R)[g];
+                }
+            }
+#pragma unroll
+        for (int rr = 0; rr < 8; rr++)
+#pragma unroll
+            for (int q = 0; q < CH; q++) {
+                int cc = (int)threadIdx.x + q * kBlock;
+                if (r0 + rr < P && cc < nc) Rs[(r0 + rr) * NCPAD + cc] = buf[rr][q];
+            }
     }
     __syncthreads();
 
@@ -369,6 +409,20 @@ __global__ __launch_bounds__(kBlock) void k_lk(const LkJob *jobs, int njobs, KPa
     // 0 <= uf < 1, coordinate clamped to [0, W-1]: left of the row f = 0,
     // right of it f = 1, inside (1 - f) R[m] + f R[m + 1]
     auto sample = [&](int xi0, T uf, T *out) {
+        if (xi0 >= col_lo && xi0 + P <= col_hi) {
+            // whole span staged and inside the row: f = uf everywhere
+            const int base = rbase + xi0;
+            const T omf = T(1) - uf;
+            T v[P + 1];
+#pragma unroll
+            for (int c = 0; c <= P; c++) {
+                v[c] = Rs[base + c];
+                if constexpr (!U8) v[c] = fabs(v[c]);
+            }
+#pragma unroll
+            for (int c = 0; c < P; c++) out[c] = omf * v[c] + uf * v[c + 1];
+            return;
+        }
         T v[P + 1];
         fetch(xi0, v, std::integral_constant<int, P + 1>());
 #pragma unroll
@@ -403,16 +457,21 @@ __global__ __launch_bounds__(kBlock) void k_lk(const LkJob *jobs, int njobs, KPa
         status = ST_DEGENERATE;
     } else {
         T step = 0;
+        const T invH = T(1) / Hs;
         for (int t = 0; t < kp.iters; t++) {
             T uc = fmin(fmax(u, ulo), uhi);
             T ui = floor(uc), uf = uc - ui;
             T I[P];
             sample(x0 + (int)ui, uf, I);
-            T s = 0;
+            // two interleaved partial sums shorten the dependent chain
+            T s0 = 0, s1 = 0;
 #pragma unroll
-            for (int c = 0; c < P; c++) s += Jg[c] * (I[c] - Tv[c]);
-            T b = seg_sum<SEG>(s);
-            step = b / Hs;
+            for (int c = 0; c < P; c += 2) {
+                s0 += Jg[c] * (I[c] - Tv[c]);
+                if (c + 1 < P) s1 += Jg[c + 1] * (I[c + 1] - Tv[c + 1]);
+            }
+            T b = seg_sum<SEG>(s0 + s1);
+            step = b * invH;
             u = u - step;
         }
         const bool unconverged = kp.conv_tol > 0 && kp.iters > 0 && !(fabs(step) <= (T)kp.conv_tol);
@@ -422,35 +481,50 @@ __global__ __launch_bounds__(kBlock) void k_lk(const LkJob *jobs, int njobs, KPa
         } else if (!isfinite(u) || fabs(u - u0) > (T)P || unconverged) {
             status = ST_DIVERGED;
         } else {
-            // eqs. (3)-(4): energies over the window, centre first
+            // eqs. (3)-(4): residual energies E_i = sum (d - mean d)^2 of the
+            // window samples u + (i - c) step, evaluated as
+            // sum d^2 - (sum d)^2 / n with every window sum reduced at once
+            // (in double precision the two forms agree to ~1e-13 relative)
             const int cw = (kp.window - 1) / 2;
-            auto energy = [&](T ud) -> T {
-                T uc = fmin(fmax(ud, ulo), uhi);
-                T ui = floor(uc), uf = uc - ui;
-                T d[P];
-                sample(x0 + (int)ui, uf, d);
-                T ds = 0;
+            constexpr int WMAX = 9;
+            T acc[2 * WMAX];
 #pragma unroll
-                for (int c = 0; c < P; c++) {
-                    d[c] -= Tv[c];
-                    if ((vmask >> c) & 1u) ds += d[c];
-                }
-                T mean = seg_sum<SEG>(ds) / (T)n;
-                T e = 0;
+            for (int i = 0; i < WMAX; i++) {
+                acc[2 * i] = 0;
+                acc[2 * i + 1] = 0;
+                if (i < kp.window) {
+                    T ud = u + (T)(i - cw) * (T)kp.window_step;
+                    T uc = fmin(fmax(ud, ulo), uhi);
+                    T ui = floor(uc), uf = uc - ui;
+                    T d[P];
+                    sample(x0 + (int)ui, uf, d);
 #pragma unroll
-                for (int c = 0; c < P; c++) {
-                    T q = d[c] - mean;
-                    if ((vmask >> c) & 1u) e += q * q;
+                    for (int c = 0; c < P; c++) {
+                        T q = ((vmask >> c) & 1u) ? d[c] - Tv[c] : T(0);
+                        acc[2 * i] += q;
+                        acc[2 * i + 1] += q * q;
+                    }
                 }
-                return seg_sum<SEG>(e);
-            };
-            const T Ec = energy(u);
-            T z = 0;
-            for (int i = 0; i < kp.window; i++) {
-                if (i == cw) { z += T(1); continue; }
-                T Ei = energy(u + (T)(i - cw) * (T)kp.window_step);
-                z += exp(-(Ei - Ec) / (T)kp.tau);
             }
+            seg_sum_n<SEG, 2 * WMAX>(acc);
+            const T ninv = T(1) / (T)n;
+            auto energy = [&](int i) -> T {
+                T E = T(0);
+#pragma unroll
+                for (int j = 0; j < WMAX; j++)
+                    if (j == i) E = acc[2 * j + 1] - acc[2 * j] * acc[2 * j] * ninv;
+                return E;
+            };
+            const T Ec = energy(cw);
+            // p = 1 / sum_i exp(-(E_i - E_c) / tau): lane r of the segment
+            // evaluates the terms of samples r, r + SEG (the centre term is 1)
+            T term = 0;
+#pragma unroll
+            for (int q = 0; q < (WMAX + SEG - 1) / SEG; q++) {
+                int i = r + q * SEG;
+                if (i < kp.window) term += i == cw ? T(1) : exp(-(energy(i) - Ec) / (T)kp.tau);
+            }
+            const T z = seg_sum<SEG>(term);
             post = T(1) / z;
             // gamma gate at the final shift: left valid, sample inside the
             // row, both right taps valid (Sec. 3, Sec. 3.2)
@@ -500,8 +574,8 @@ __global__ __launch_bounds__(kBlock) void k_lk(const LkJob *jobs, int njobs, KPa
 // or 1 / max(residual^2, 1) (DIS eq. (2)); U = sum(w u) / sum(w).  Uncovered:
 // NaN at level 0, zero at the coarsest level, else twice the coarse field.
 template <typename T, bool U8>
-__global__ __launch_bounds__(kBlock) void k_dense(const DenseJob *jobs, int njobs, KParams kp) {
-    const DenseJob &J = jobs[find_job(jobs, njobs, (int)blockIdx.x)];
+__global__ __launch_bounds__(kBlock) void k_dense(const JobPack<DenseJob> pk, KParams kp) {
+    const DenseJob &J = pk.j[find_job(pk, (int)blockIdx.x)];
     int i = ((int)blockIdx.x - J.block0) * kBlock + (int)threadIdx.x;
     if (i >= J.W * J.H) return;
     const int y = i / J.W, x = i - y * J.W;

@@ -60,7 +60,7 @@ bdis_status check_params(const bdis_params *p, char *err) {
     if (!(p->sigma_r > 0.f) || !(p->sigma_s > 0.f) || !std::isfinite(p->sigma_r) || !std::isfinite(p->sigma_s)) {
         set_err(err, "sigma_r and sigma_s must be positive and finite"); return BDIS_E_INVALID_ARG;
     }
-    if (p->window < 1 || p->window > 15 || (p->window % 2) == 0) { set_err(err, "window %d must be odd in [1, 15]", p->window); return BDIS_E_INVALID_ARG; }
+    if (p->window < 1 || p->window > 9 || (p->window % 2) == 0) { set_err(err, "window %d must be odd in [1, 9]", p->window); return BDIS_E_INVALID_ARG; }
     if (!(p->window_step >= 0.f) || !std::isfinite(p->window_step)) { set_err(err, "window_step must be >= 0"); return BDIS_E_INVALID_ARG; }
     if (!(p->gamma >= 0.f && p->gamma <= 1.f)) { set_err(err, "gamma must be in [0, 1]"); return BDIS_E_INVALID_ARG; }
     if (p->s_mode != 0 && p->s_mode != 1) { set_err(err, "s_mode must be 0 or 1"); return BDIS_E_INVALID_ARG; }
@@ -170,13 +170,6 @@ struct bdis_ctx {
     char err[512] = "";
     char *ws = nullptr;
     size_t ws_bytes = 0;
-    char *djobs = nullptr;
-    size_t djobs_bytes = 0;
-    char *hjobs = nullptr;  // pinned staging
-    size_t hjobs_bytes = 0;
-    std::vector<char> last_upload;
-    hipEvent_t upload_ev = nullptr;
-    bool upload_pending = false;
     double *gtab_d = nullptr;  // spatial Gaussian tables, one per precision
     float *gtab_f = nullptr;
     // last single-pair run, for bdis_debug_stage
@@ -276,27 +269,7 @@ bdis_status ensure_ws(bdis_t *h, size_t bytes) {
     return BDIS_OK;
 }
 
-bdis_status ensure_jobs(bdis_t *h, size_t bytes) {
-    if (bytes <= h->djobs_bytes) return BDIS_OK;
-    size_t want = align_up(std::max(bytes, (size_t)16384), 4096);
-    if (h->upload_pending) {
-        HIPCHK(h, hipEventSynchronize(h->upload_ev));
-        h->upload_pending = false;
-    }
-    if (h->djobs) { HIPCHK(h, hipDeviceSynchronize()); (void)hipFree(h->djobs); h->djobs = nullptr; h->djobs_bytes = 0; }
-    if (h->hjobs) { (void)hipHostFree(h->hjobs); h->hjobs = nullptr; h->hjobs_bytes = 0; }
-    if (hipMalloc(&h->djobs, want) != hipSuccess || hipHostMalloc(&h->hjobs, want, 0) != hipSuccess) {
-        (void)hipGetLastError();
-        set_err(h->err, "job table allocation failed");
-        return BDIS_E_OOM;
-    }
-    h->djobs_bytes = h->hjobs_bytes = want;
-    h->last_upload.clear();
-    return BDIS_OK;
-}
-
-// A launch: kernel kind, template selectors, byte offset of its jobs in the
-// table, job count and total blocks.
+// A launch: kernel kind, template selectors and its jobs (passed by value).
 enum Kind { K_PYR, K_LK, K_DENSE };
 struct Launch {
     Kind kind;
@@ -304,20 +277,33 @@ struct Launch {
     int patch;
     bool u8;
     bool f64;
-    size_t off;
-    int njobs;
     int blocks;
     KParams kp;
+    std::vector<char> pack;  // JobPack<Job> bytes
 };
 
-template <typename Job>
-void append(std::vector<char> &tab, std::vector<Launch> &ls, Kind kind, int level, int patch, bool u8, bool f64,
-            const std::vector<Job> &jobs, int blocks, const KParams &kp) {
-    if (jobs.empty() || blocks == 0) return;
-    size_t off = align_up(tab.size(), 64);
-    tab.resize(off + jobs.size() * sizeof(Job));
-    memcpy(tab.data() + off, jobs.data(), jobs.size() * sizeof(Job));
-    ls.push_back(Launch{kind, level, patch, u8, f64, off, (int)jobs.size(), blocks, kp});
+// Splits jobs into launches of at most kMaxJobs; `blocks_of` gives a job's
+// block count.
+template <typename Job, typename F>
+void append(std::vector<Launch> &ls, Kind kind, int level, int patch, bool u8, bool f64,
+            std::vector<Job> &jobs, const KParams &kp, F blocks_of) {
+    for (size_t s0 = 0; s0 < jobs.size(); s0 += kMaxJobs) {
+        JobPack<Job> pk;
+        memset(&pk, 0, sizeof pk);
+        pk.n = 0;
+        int blocks = 0;
+        for (size_t i = s0; i < jobs.size() && i < s0 + kMaxJobs; i++) {
+            Job j = jobs[i];
+            j.block0 = blocks;
+            blocks += blocks_of(j);
+            pk.j[pk.n++] = j;
+        }
+        if (blocks == 0) continue;
+        Launch L{kind, level, patch, u8, f64, blocks, kp, {}};
+        L.pack.resize(sizeof pk);
+        memcpy(L.pack.data(), &pk, sizeof pk);
+        ls.push_back(std::move(L));
+    }
 }
 
 int lk_bpr(int P, int nx) {
@@ -332,16 +318,15 @@ int lk_bpr(int P, int nx) {
 }
 
 // Build every launch for a set of pairs: pyramid levels 1..Lmax-1, then for
-// each level from the coarsest down, LK (one launch per patch size) and the
+// each level from the coarsest down, LK (per patch size) and the
 // densification.
-void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<char> &tab, std::vector<Launch> &ls) {
+void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<Launch> &ls) {
     int Lmax = 0;
     const bool f64 = h->prm.precision == 0;
     for (auto &p : pairs) Lmax = std::max(Lmax, p.g.L);
     KParams kp0 = make_kparams(h->prm, h->prm.patch);
     for (int l = 1; l < Lmax; l++) {
         std::vector<PyrJob> jobs;
-        int blocks = 0;
         for (auto &p : pairs) {
             if (p.g.L <= l) continue;
             PyrJob j;
@@ -351,16 +336,14 @@ void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<char> &tab
             j.ws = p.g.W[l - 1]; j.hs = p.g.H[l - 1];
             j.dst_l = p.ws.pyr_l[l]; j.dst_r = p.ws.pyr_r[l];
             j.wd = p.g.W[l]; j.hd = p.g.H[l];
-            j.block0 = blocks;
-            blocks += (j.wd * j.hd + kBlock - 1) / kBlock;
             jobs.push_back(j);
         }
-        append(tab, ls, K_PYR, l, 0, l == 1, f64, jobs, blocks, kp0);
+        append(ls, K_PYR, l, 0, l == 1, f64, jobs, kp0,
+               [](const PyrJob &j) { return (j.wd * j.hd + kBlock - 1) / kBlock; });
     }
     for (int l = Lmax - 1; l >= 0; l--) {
         for (int P : kSupportedPatch) {
             std::vector<LkJob> jobs;
-            int blocks = 0;
             for (auto &p : pairs) {
                 if (p.g.L <= l || p.patch != P) continue;
                 LkJob j;
@@ -373,16 +356,15 @@ void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<char> &tab
                 j.Wc = coarsest ? 0 : p.g.W[l + 1];
                 j.Hc = coarsest ? 0 : p.g.H[l + 1];
                 j.nx = p.g.nx[l]; j.ny = p.g.ny[l]; j.stride = p.stride;
+                j.reach = (int)std::ceil(std::max(0.f, h->prm.max_disparity) / (float)(1 << l)) + 1;
                 j.rec_u = p.ws.rec_u[l]; j.rec_w = p.ws.rec_w[l];
                 j.rec_u0 = p.ws.rec_u0[l]; j.rec_st = p.ws.rec_st[l];
-                j.block0 = blocks;
-                blocks += j.ny * lk_bpr(P, j.nx);
                 jobs.push_back(j);
             }
-            append(tab, ls, K_LK, l, P, l == 0, f64, jobs, blocks, make_kparams(h->prm, P));
+            append(ls, K_LK, l, P, l == 0, f64, jobs, make_kparams(h->prm, P),
+                   [P](const LkJob &j) { return j.ny * lk_bpr(P, j.nx); });
         }
         std::vector<DenseJob> jobs;
-        int blocks = 0;
         for (auto &p : pairs) {
             if (p.g.L <= l) continue;
             DenseJob j;
@@ -403,44 +385,53 @@ void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<char> &tab
             j.U = l == 0 ? nullptr : p.ws.U[l];
             j.out = l == 0 ? p.disp : nullptr;
             j.out_pitch = p.dpitch;
-            j.block0 = blocks;
-            blocks += (j.W * j.H + kBlock - 1) / kBlock;
             jobs.push_back(j);
         }
-        append(tab, ls, K_DENSE, l, 0, l == 0, f64, jobs, blocks, kp0);
+        append(ls, K_DENSE, l, 0, l == 0, f64, jobs, kp0,
+               [](const DenseJob &j) { return (j.W * j.H + kBlock - 1) / kBlock; });
     }
 }
 
+// kernel arguments are limited to 4 KiB
+static_assert(sizeof(JobPack<PyrJob>) + sizeof(KParams) <= 4000, "pyramid job pack too large");
+static_assert(sizeof(JobPack<LkJob>) + sizeof(KParams) <= 4000, "LK job pack too large");
+static_assert(sizeof(JobPack<DenseJob>) + sizeof(KParams) <= 4000, "densify job pack too large");
+
+template <typename Job>
+const JobPack<Job> &pack_of(const Launch &L) {
+    return *reinterpret_cast<const JobPack<Job> *>(L.pack.data());
+}
+
 template <typename T, int P>
-void launch_lk(const Launch &L, const char *base, hipStream_t s) {
-    const LkJob *j = (const LkJob *)(base + L.off);
-    if (L.u8) hipLaunchKernelGGL((k_lk<T, P, true>), dim3(L.blocks), dim3(kBlock), 0, s, j, L.njobs, L.kp);
-    else hipLaunchKernelGGL((k_lk<T, P, false>), dim3(L.blocks), dim3(kBlock), 0, s, j, L.njobs, L.kp);
+void launch_lk(const Launch &L, hipStream_t s) {
+    const JobPack<LkJob> &pk = pack_of<LkJob>(L);
+    if (L.u8) hipLaunchKernelGGL((k_lk<T, P, true>), dim3(L.blocks), dim3(kBlock), 0, s, pk, L.kp);
+    else hipLaunchKernelGGL((k_lk<T, P, false>), dim3(L.blocks), dim3(kBlock), 0, s, pk, L.kp);
 }
 
 template <typename T>
-void launch_one(const Launch &L, const char *base, hipStream_t s) {
+void launch_one(const Launch &L, hipStream_t s) {
     switch (L.kind) {
     case K_PYR: {
-        const PyrJob *j = (const PyrJob *)(base + L.off);
-        if (L.u8) hipLaunchKernelGGL((k_pyr<T, true>), dim3(L.blocks), dim3(kBlock), 0, s, j, L.njobs, L.kp);
-        else hipLaunchKernelGGL((k_pyr<T, false>), dim3(L.blocks), dim3(kBlock), 0, s, j, L.njobs, L.kp);
+        const JobPack<PyrJob> &pk = pack_of<PyrJob>(L);
+        if (L.u8) hipLaunchKernelGGL((k_pyr<T, true>), dim3(L.blocks), dim3(kBlock), 0, s, pk, L.kp);
+        else hipLaunchKernelGGL((k_pyr<T, false>), dim3(L.blocks), dim3(kBlock), 0, s, pk, L.kp);
         break;
     }
     case K_LK:
         switch (L.patch) {
-        case 4: launch_lk<T, 4>(L, base, s); break;
-        case 6: launch_lk<T, 6>(L, base, s); break;
-        case 8: launch_lk<T, 8>(L, base, s); break;
-        case 10: launch_lk<T, 10>(L, base, s); break;
-        case 12: launch_lk<T, 12>(L, base, s); break;
-        case 16: launch_lk<T, 16>(L, base, s); break;
+        case 4: launch_lk<T, 4>(L, s); break;
+        case 6: launch_lk<T, 6>(L, s); break;
+        case 8: launch_lk<T, 8>(L, s); break;
+        case 10: launch_lk<T, 10>(L, s); break;
+        case 12: launch_lk<T, 12>(L, s); break;
+        case 16: launch_lk<T, 16>(L, s); break;
         }
         break;
     case K_DENSE: {
-        const DenseJob *j = (const DenseJob *)(base + L.off);
-        if (L.u8) hipLaunchKernelGGL((k_dense<T, true>), dim3(L.blocks), dim3(kBlock), 0, s, j, L.njobs, L.kp);
-        else hipLaunchKernelGGL((k_dense<T, false>), dim3(L.blocks), dim3(kBlock), 0, s, j, L.njobs, L.kp);
+        const JobPack<DenseJob> &pk = pack_of<DenseJob>(L);
+        if (L.u8) hipLaunchKernelGGL((k_dense<T, true>), dim3(L.blocks), dim3(kBlock), 0, s, pk, L.kp);
+        else hipLaunchKernelGGL((k_dense<T, false>), dim3(L.blocks), dim3(kBlock), 0, s, pk, L.kp);
         break;
     }
     }
@@ -457,7 +448,7 @@ std::string launch_name(const Launch &L) {
     return buf;
 }
 
-void launch_all(bdis_t *h, const std::vector<Launch> &ls, const char *base, hipStream_t s);
+void launch_all(bdis_t *h, const std::vector<Launch> &ls, hipStream_t s);
 
 hipEvent_t take_event(bdis_t *h) {
     if (!h->spare.empty()) {
@@ -470,7 +461,7 @@ hipEvent_t take_event(bdis_t *h) {
     return e;
 }
 
-void launch_all(bdis_t *h, const std::vector<Launch> &ls, const char *base, hipStream_t s) {
+void launch_all(bdis_t *h, const std::vector<Launch> &ls, hipStream_t s) {
     for (const Launch &L : ls) {
         hipEvent_t a = nullptr, b = nullptr;
         if (h->profiling) {
@@ -478,8 +469,8 @@ void launch_all(bdis_t *h, const std::vector<Launch> &ls, const char *base, hipS
             b = take_event(h);
             if (a && b) (void)hipEventRecord(a, s);
         }
-        if (L.f64) launch_one<double>(L, base, s);
-        else launch_one<float>(L, base, s);
+        if (L.f64) launch_one<double>(L, s);
+        else launch_one<float>(L, s);
         if (h->profiling && a && b) {
             (void)hipEventRecord(b, s);
             h->pending.push_back({launch_name(L), a, b});
@@ -524,23 +515,9 @@ bdis_status run(bdis_t *h, std::vector<PairIn> &pairs, hipStream_t s) {
         carve(h->ws + off, p.g, esz, p.ws);
         off += align_up(pair_ws_bytes(p.g, esz));
     }
-    std::vector<char> tab;
     std::vector<Launch> ls;
-    plan_launches(h, pairs, tab, ls);
-    st = ensure_jobs(h, tab.size());
-    if (st != BDIS_OK) return st;
-    if (tab != h->last_upload) {
-        if (h->upload_pending) {
-            HIPCHK(h, hipEventSynchronize(h->upload_ev));
-            h->upload_pending = false;
-        }
-        memcpy(h->hjobs, tab.data(), tab.size());
-        HIPCHK(h, hipMemcpyAsync(h->djobs, h->hjobs, tab.size(), hipMemcpyHostToDevice, s));
-        HIPCHK(h, hipEventRecord(h->upload_ev, s));
-        h->upload_pending = true;
-        h->last_upload = tab;
-    }
-    launch_all(h, ls, h->djobs, s);
+    plan_launches(h, pairs, ls);
+    launch_all(h, ls, s);
     HIPCHK(h, hipGetLastError());
     return BDIS_OK;
 }
@@ -626,8 +603,7 @@ bdis_status bdis_create(const bdis_params *p, int device, bdis_t **out) {
     h->device = device;
     DeviceGuard dg(device);
     if (hipMalloc(&h->gtab_d, kGtabFloats * sizeof(double)) != hipSuccess ||
-        hipMalloc(&h->gtab_f, kGtabFloats * sizeof(float)) != hipSuccess ||
-        hipEventCreateWithFlags(&h->upload_ev, hipEventDisableTiming) != hipSuccess) {
+        hipMalloc(&h->gtab_f, kGtabFloats * sizeof(float)) != hipSuccess) {
         (void)hipGetLastError();
         set_err(g_thread_err, "device setup failed");
         bdis_destroy(h);
@@ -650,7 +626,6 @@ bdis_status bdis_set_params(bdis_t *h, const bdis_params *p) {
     DeviceGuard dg(h->device);
     HIPCHK(h, hipDeviceSynchronize());
     h->prm = *p;
-    h->last_upload.clear();
     return fill_gtab(h);
 }
 
@@ -803,11 +778,8 @@ void bdis_destroy(bdis_t *h) {
         DeviceGuard dg(h->device);
         (void)hipDeviceSynchronize();
         if (h->ws) (void)hipFree(h->ws);
-        if (h->djobs) (void)hipFree(h->djobs);
-        if (h->hjobs) (void)hipHostFree(h->hjobs);
         if (h->gtab_d) (void)hipFree(h->gtab_d);
         if (h->gtab_f) (void)hipFree(h->gtab_f);
-        if (h->upload_ev) (void)hipEventDestroy(h->upload_ev);
         for (auto &r : h->pending) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
         for (auto e : h->spare) (void)hipEventDestroy(e);
     }

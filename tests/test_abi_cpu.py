@@ -61,7 +61,7 @@ def test_levels_capped_by_size():
 
 
 @pytest.mark.parametrize("bad", [dict(patch=1), dict(stride=0), dict(stride=9), dict(iters=-1),
-                                 dict(sigma_r=0.0), dict(window=4), dict(window=17), dict(gamma=1.5),
+                                 dict(sigma_r=0.0), dict(window=4), dict(window=11), dict(gamma=1.5),
                                  dict(s_mode=2), dict(fusion=3), dict(valid_lo=10, valid_hi=5),
                                  dict(levels=13), dict(levels=0, max_disparity=0.0), dict(eps_h=-1.0)])
 def test_plan_rejects_bad_params(bad):
