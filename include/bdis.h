@@ -95,12 +95,15 @@ typedef struct {
 
 typedef struct bdis_ctx bdis_t;
 
-/* One stereo pair for bdis_compute_batch (device pointers, caller-owned). */
+/* One stereo pair for bdis_compute_batch (device pointers, caller-owned).
+ * max_disparity > 0 overrides the handle's for this pair (automatic level
+ * count when params.levels == 0, and the staged search span). */
 typedef struct {
     const uint8_t *left;
     const uint8_t *right;
     float *disp;
     int32_t width, height, pitch_bytes, disp_pitch_elems;
+    float max_disparity;
 } bdis_pair;
 
 /* Sizes the library derives for one image under given parameters. */
@@ -147,6 +150,23 @@ BDIS_API bdis_status bdis_compute(bdis_t *h, const uint8_t *left, const uint8_t 
  * (bit for bit).  With params.autotune = 1, each pair uses the (patch,
  * stride) that bdis_set_tuning recorded for its size class. */
 BDIS_API bdis_status bdis_compute_batch(bdis_t *h, const bdis_pair *pairs, int32_t n, void *stream);
+
+/* How bdis_compute_batch runs a batch.
+ *   mode 0 (default): one persistent kernel over a task list of every block
+ *     of every pair and level, dependencies tracked by per-job completion
+ *     counters, captured with a counter-reset kernel in a hipGraph that is
+ *     replayed while the batch layout stays the same (new buffer pointers
+ *     only re-upload the task tables).  Patch sides 8 and 12 only.
+ *   mode 1: one launch per kernel kind and level over all pairs.
+ * wgs_per_cu: persistent workgroups per compute unit (0 = as many as fit).
+ * Results are the same in both modes, bit for bit. */
+BDIS_API bdis_status bdis_set_batch_mode(bdis_t *h, int32_t mode, int32_t wgs_per_cu);
+
+/* Waits for the last bdis_compute_batch and reports whether the persistent
+ * kernel had to give up a dependency wait (*flag = 1: that batch's results are
+ * not valid; it cannot happen when the kernel owns the GPU).  *flag = 0 in
+ * mode 1. */
+BDIS_API bdis_status bdis_batch_error(bdis_t *h, int32_t *flag);
 
 /* Autotuner table: for images whose width is <= max_width[i] (ascending),
  * use patch[i] and stride[i].  n <= 8.  n = 0 clears it. */

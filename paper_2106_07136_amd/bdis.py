@@ -39,7 +39,7 @@ class CParams(C.Structure):
 class CPair(C.Structure):
     _fields_ = [("left", C.c_void_p), ("right", C.c_void_p), ("disp", C.c_void_p),
                 ("width", C.c_int32), ("height", C.c_int32), ("pitch_bytes", C.c_int32),
-                ("disp_pitch_elems", C.c_int32)]
+                ("disp_pitch_elems", C.c_int32), ("max_disparity", C.c_float)]
 
 
 class CKernelTime(C.Structure):
@@ -106,6 +106,8 @@ def lib():
         L.bdis_compute_batch.argtypes = [vp, C.POINTER(CPair), i32, vp]
         L.bdis_set_tuning.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
         L.bdis_debug_stage.argtypes = [vp, i32, i32, vp, C.c_size_t]
+        L.bdis_set_batch_mode.argtypes = [vp, i32, i32]
+        L.bdis_batch_error.argtypes = [vp, C.POINTER(i32)]
         L.bdis_set_profiling.argtypes = [vp, i32]
         L.bdis_get_profile.argtypes = [vp, C.POINTER(CKernelTime), i32, C.POINTER(i32)]
         L.bdis_destroy.argtypes = [vp]
@@ -116,7 +118,8 @@ def lib():
         L.bdis_last_error.restype = C.c_char_p
         for name in ("bdis_plan", "bdis_create", "bdis_set_params", "bdis_reserve", "bdis_compute",
                      "bdis_compute_batch", "bdis_set_tuning", "bdis_debug_stage",
-                     "bdis_set_profiling", "bdis_get_profile"):
+                     "bdis_set_profiling", "bdis_get_profile", "bdis_set_batch_mode",
+                     "bdis_batch_error"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -205,7 +208,17 @@ class Bdis:
         self._last_shape = (W, H)
         return out
 
-    def compute_batch(self, lefts, rights, outs=None, stream=None):
+    def set_batch_mode(self, mode: int, wgs_per_cu: int = 0):
+        """0: one persistent launch in a hipGraph; 1: one launch per level."""
+        _check(lib().bdis_set_batch_mode(self._h, mode, wgs_per_cu), self._h)
+
+    def batch_error(self) -> int:
+        f = C.c_int32()
+        _check(lib().bdis_batch_error(self._h, C.byref(f)), self._h)
+        return f.value
+
+    def compute_batch(self, lefts, rights, outs=None, stream=None, max_disparity=None):
+        """max_disparity: optional per-pair list (0 = the handle's)."""
         import torch
         n = len(lefts)
         if outs is None:
@@ -216,8 +229,9 @@ class Bdis:
                 raise ValueError(f"pair {i}: uint8 tensors of equal shape required")
             if l.stride(1) != 1 or l.stride(0) != r.stride(0) or o.stride(1) != 1:
                 raise ValueError(f"pair {i}: rows must be contiguous with equal pitch")
+            dm = 0.0 if max_disparity is None else float(max_disparity[i])
             arr[i] = CPair(l.data_ptr(), r.data_ptr(), o.data_ptr(), l.shape[1], l.shape[0],
-                           l.stride(0), o.stride(0))
+                           l.stride(0), o.stride(0), dm)
         _check(lib().bdis_compute_batch(self._h, arr, n, _stream_ptr(stream)), self._h)
         return outs
 

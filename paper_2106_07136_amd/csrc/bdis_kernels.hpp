@@ -225,10 +225,7 @@ __device__ __forceinline__ T sample_row(const void *img, size_t row0, int W, int
 // existing 2x2 fine children are valid.  In double precision every level up
 // to the fifth is exact (dyadic sums of 8-bit values).
 template <typename T, bool U8>
-__global__ __launch_bounds__(kBlock) void k_pyr(const JobPack<PyrJob> pk, KParams kp) {
-    const PyrJob &J = pk.j[find_job(pk, (int)blockIdx.x)];
-    int i = ((int)blockIdx.x - J.block0) * kBlock + (int)threadIdx.x;
-    if (i >= J.wd * J.hd) return;
+__device__ __forceinline__ void pyr_pixel(const PyrJob &J, int i, const KParams &kp) {
     int yc = i / J.wd, xc = i - yc * J.wd;
     int x = 2 * xc, y = 2 * yc;
     const T w5[5] = {T(1) / 16, T(4) / 16, T(6) / 16, T(4) / 16, T(1) / 16};
@@ -267,6 +264,28 @@ __global__ __launch_bounds__(kBlock) void k_pyr(const JobPack<PyrJob> pk, KParam
     }
 }
 
+// Block lb of a pyramid job: kPixPerThread coarse pixels per thread.
+constexpr int kPixPerThread = 4;
+__host__ __device__ constexpr int pyr_blocks(int wd, int hd) {
+    return (wd * hd + kBlock * kPixPerThread - 1) / (kBlock * kPixPerThread);
+}
+
+template <typename T, bool U8>
+__device__ __forceinline__ void pyr_block(const PyrJob &J, int lb, const KParams &kp) {
+    const int n = J.wd * J.hd;
+#pragma unroll
+    for (int q = 0; q < kPixPerThread; q++) {
+        int i = (lb * kPixPerThread + q) * kBlock + (int)threadIdx.x;
+        if (i < n) pyr_pixel<T, U8>(J, i, kp);
+    }
+}
+
+template <typename T, bool U8>
+__global__ __launch_bounds__(kBlock) void k_pyr(const JobPack<PyrJob> pk, KParams kp) {
+    const PyrJob &J = pk.j[find_job(pk, (int)blockIdx.x)];
+    pyr_block<T, U8>(J, (int)blockIdx.x - J.block0, kp);
+}
+
 // ---------------------------------------------------------------- LK + posterior
 
 enum { ST_KEPT = 0, ST_DEGENERATE = 1, ST_DIVERGED = 2, ST_GATED = 3 };
@@ -300,17 +319,19 @@ __host__ __device__ constexpr int lk_blocks_per_row(int nx) {
 // conv_tol, shift within a patch side of its start).  Then the window
 // energies E_i = sum (d - mean d)^2 at u + (i - c) step, the posterior
 // p = 1 / sum_i exp(-(E_i - E_c) / tau) (eqs. (3)-(4)) and the gamma gate.
+template <typename T, int P>
+__host__ __device__ constexpr int lk_lds_bytes() { return P * (LkShape<P>::NCMAX + 1) * (int)sizeof(T); }
+
+// Block lb of an LK job; Rs is the block's LDS staging area of
+// lk_lds_bytes<T, P>() bytes.
 template <typename T, int P, bool U8>
-__global__ __launch_bounds__(kBlock) void k_lk(const JobPack<LkJob> pk, KParams kp) {
+__device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KParams &kp, T *__restrict__ Rs) {
     using S = LkShape<P>;
     constexpr int SEG = S::SEG, PPB = S::PPB, NCMAX = S::NCMAX;
     constexpr int NCPAD = NCMAX + 1;
-    __shared__ T Rs[P * NCPAD];
 
-    const LkJob &J = pk.j[find_job(pk, (int)blockIdx.x)];
     const int W = J.W;
     const int bpr = lk_blocks_per_row<P>(J.nx);
-    const int lb = (int)blockIdx.x - J.block0;
     const int jy = lb / bpr, jx0 = (lb - jy * bpr) * PPB;
     const int slot = (int)threadIdx.x / SEG, r = (int)threadIdx.x % SEG;
     const int jx_raw = jx0 + slot;
@@ -567,6 +588,13 @@ __global__ __launch_bounds__(kBlock) void k_lk(const JobPack<LkJob> pk, KParams 
     }
 }
 
+template <typename T, int P, bool U8>
+__global__ __launch_bounds__(kBlock) void k_lk(const JobPack<LkJob> pk, KParams kp) {
+    __shared__ T Rs[lk_lds_bytes<T, P>() / sizeof(T)];
+    const LkJob &J = pk.j[find_job(pk, (int)blockIdx.x)];
+    lk_block<T, P, U8>(J, (int)blockIdx.x - J.block0, kp, Rs);
+}
+
 // ---------------------------------------------------------------- densify
 
 // One pixel: kept covering patches in (row, column) order, weight = patch
@@ -574,10 +602,7 @@ __global__ __launch_bounds__(kBlock) void k_lk(const JobPack<LkJob> pk, KParams 
 // or 1 / max(residual^2, 1) (DIS eq. (2)); U = sum(w u) / sum(w).  Uncovered:
 // NaN at level 0, zero at the coarsest level, else twice the coarse field.
 template <typename T, bool U8>
-__global__ __launch_bounds__(kBlock) void k_dense(const JobPack<DenseJob> pk, KParams kp) {
-    const DenseJob &J = pk.j[find_job(pk, (int)blockIdx.x)];
-    int i = ((int)blockIdx.x - J.block0) * kBlock + (int)threadIdx.x;
-    if (i >= J.W * J.H) return;
+__device__ __forceinline__ void dense_pixel(const DenseJob &J, const int i, const KParams &kp) {
     const int y = i / J.W, x = i - y * J.W;
     const int P = J.patch, st = J.stride;
     const T *rec_u = static_cast<const T *>(J.rec_u);
@@ -627,6 +652,26 @@ __global__ __launch_bounds__(kBlock) void k_dense(const JobPack<DenseJob> pk, KP
     else U = T(2) * bilinear<T>(static_cast<const T *>(J.Uc), J.Wc, J.Hc, T(0.5) * (T)x, T(0.5) * (T)y);
     if (J.out) J.out[(size_t)y * J.out_pitch + x] = (float)(-U);
     if (J.U) static_cast<T *>(J.U)[i] = U;
+}
+
+__host__ __device__ constexpr int dense_blocks(int w, int h) {
+    return (w * h + kBlock * kPixPerThread - 1) / (kBlock * kPixPerThread);
+}
+
+template <typename T, bool U8>
+__device__ __forceinline__ void dense_block(const DenseJob &J, int lb, const KParams &kp) {
+    const int n = J.W * J.H;
+#pragma unroll
+    for (int q = 0; q < kPixPerThread; q++) {
+        int i = (lb * kPixPerThread + q) * kBlock + (int)threadIdx.x;
+        if (i < n) dense_pixel<T, U8>(J, i, kp);
+    }
+}
+
+template <typename T, bool U8>
+__global__ __launch_bounds__(kBlock) void k_dense(const JobPack<DenseJob> pk, KParams kp) {
+    const DenseJob &J = pk.j[find_job(pk, (int)blockIdx.x)];
+    dense_block<T, U8>(J, (int)blockIdx.x - J.block0, kp);
 }
 
 }  // namespace bdis

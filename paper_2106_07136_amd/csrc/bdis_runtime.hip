@@ -14,6 +14,7 @@
 
 #include "bdis.h"
 #include "bdis_kernels.hpp"
+#include "bdis_persist.hpp"
 
 using namespace bdis;
 
@@ -80,9 +81,9 @@ bdis_status check_params(const bdis_params *p, char *err) {
     return BDIS_OK;
 }
 
-int requested_levels(const bdis_params &p) {
+int requested_levels(const bdis_params &p, float dmax) {
     if (p.levels > 0) return p.levels;
-    double r = p.max_disparity / 4.0;
+    double r = dmax / 4.0;
     int L = 1 + (r > 1.0 ? (int)std::ceil(std::log2(r) - 1e-12) : 0);
     return std::min(L, kMaxLevels);
 }
@@ -158,6 +159,7 @@ struct PairIn {
     float *disp;
     int W, H, pitch, dpitch;
     int patch, stride;
+    float dmax;  // largest expected disparity, level-0 pixels
     Geo g;
     PairWs ws;
 };
@@ -184,6 +186,24 @@ struct bdis_ctx {
     std::vector<std::string> prof_names;
     std::vector<int> prof_count;
     std::vector<double> prof_ms;
+    // batch execution
+    int batch_mode = 0;
+    int wgs_per_cu = 0;
+    hipStream_t cap_stream = nullptr;
+    char *p_dev = nullptr;        // tasks | jobs | kparams | counters (+ error flag)
+    size_t p_dev_bytes = 0;
+    char *p_host = nullptr;       // pinned staging of the tables
+    size_t p_host_bytes = 0;
+    hipEvent_t p_upload_ev = nullptr;
+    bool p_upload_pending = false;
+    std::vector<char> p_last;     // last uploaded table bytes
+    std::vector<char> p_key;      // batch description the tables were built for
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    std::vector<long long> graph_key;
+    int *p_err = nullptr;         // device error flag of the last persistent run
+    hipStream_t last_batch_stream = nullptr;
+    int n_cu = 0;
     // autotuner table
     int ntune = 0;
     int tune_w[kMaxTuning], tune_p[kMaxTuning], tune_s[kMaxTuning];
@@ -339,7 +359,7 @@ void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<Launch> &l
             jobs.push_back(j);
         }
         append(ls, K_PYR, l, 0, l == 1, f64, jobs, kp0,
-               [](const PyrJob &j) { return (j.wd * j.hd + kBlock - 1) / kBlock; });
+               [](const PyrJob &j) { return pyr_blocks(j.wd, j.hd); });
     }
     for (int l = Lmax - 1; l >= 0; l--) {
         for (int P : kSupportedPatch) {
@@ -356,7 +376,7 @@ void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<Launch> &l
                 j.Wc = coarsest ? 0 : p.g.W[l + 1];
                 j.Hc = coarsest ? 0 : p.g.H[l + 1];
                 j.nx = p.g.nx[l]; j.ny = p.g.ny[l]; j.stride = p.stride;
-                j.reach = (int)std::ceil(std::max(0.f, h->prm.max_disparity) / (float)(1 << l)) + 1;
+                j.reach = (int)std::ceil(std::max(0.f, p.dmax) / (float)(1 << l)) + 1;
                 j.rec_u = p.ws.rec_u[l]; j.rec_w = p.ws.rec_w[l];
                 j.rec_u0 = p.ws.rec_u0[l]; j.rec_st = p.ws.rec_st[l];
                 jobs.push_back(j);
@@ -388,7 +408,7 @@ void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<Launch> &l
             jobs.push_back(j);
         }
         append(ls, K_DENSE, l, 0, l == 0, f64, jobs, kp0,
-               [](const DenseJob &j) { return (j.W * j.H + kBlock - 1) / kBlock; });
+               [](const DenseJob &j) { return dense_blocks(j.W, j.H); });
     }
 }
 
@@ -495,14 +515,224 @@ bdis_status check_pair(bdis_t *h, const uint8_t *L, const uint8_t *R, int W, int
     return BDIS_OK;
 }
 
+// ---------------------------------------------------------------- persistent batch
+
+struct PTables {
+    std::vector<PTask> tasks;
+    std::vector<PJob> jobs;
+    std::vector<KParams> kps;
+    int lds = 0;
+};
+
+// Task list of a batch in dependency order; counters live at `ctr` (device).
+void build_ptables(bdis_t *h, std::vector<PairIn> &pairs, int *ctr, PTables &t) {
+    const bool f64 = h->prm.precision == 0;
+    const size_t esz = f64 ? sizeof(double) : sizeof(float);
+    int Lmax = 0;
+    for (auto &p : pairs) Lmax = std::max(Lmax, p.g.L);
+    t.kps.push_back(make_kparams(h->prm, h->prm.patch));  // 0: pyramid / densify
+    t.kps.push_back(make_kparams(h->prm, 8));              // 1: LK p = 8
+    t.kps.push_back(make_kparams(h->prm, 12));             // 2: LK p = 12
+    const int np = (int)pairs.size();
+    // job index of (pair, level, kind), -1 if absent
+    std::vector<int> idx((size_t)np * kMaxLevels * 3, -1);
+    auto at = [&](int p, int l, int k) -> int & { return idx[((size_t)p * kMaxLevels + l) * 3 + k]; };
+    auto blocks_of = [&](const PJob &j) {
+        if (j.kind == PK_PYR) return pyr_blocks(j.pyr.wd, j.pyr.hd);
+        if (j.kind == PK_LK) return j.lk.ny * lk_bpr(j.patch, j.lk.nx);
+        return dense_blocks(j.dense.W, j.dense.H);
+    };
+    // jobs name their dependencies by job id while the list is built; the
+    // counters' device addresses are bound at the end
+    std::vector<int> dep_ids;  // two per job, -1 = none
+    auto add_job = [&](PJob j, int p, int l, int d0, int d1) {
+        int id = (int)t.jobs.size();
+        j.need0 = d0 < 0 ? 0 : blocks_of(t.jobs[d0]);
+        j.need1 = d1 < 0 ? 0 : blocks_of(t.jobs[d1]);
+        t.jobs.push_back(j);
+        dep_ids.push_back(d0);
+        dep_ids.push_back(d1);
+        at(p, l, j.kind) = id;
+        int nb = blocks_of(j);
+        for (int b = 0; b < nb; b++) t.tasks.push_back(PTask{id, b});
+    };
+    for (int l = 1; l < Lmax; l++)
+        for (int p = 0; p < np; p++) {
+            PairIn &q = pairs[p];
+            if (q.g.L <= l) continue;
+            PJob j;
+            memset(&j, 0, sizeof j);
+            j.kind = PK_PYR; j.u8 = l == 1; j.kp = 0;
+            PyrJob &y = j.pyr;
+            y.src_l = l == 1 ? (const void *)q.left : q.ws.pyr_l[l - 1];
+            y.src_r = l == 1 ? (const void *)q.right : q.ws.pyr_r[l - 1];
+            y.src_pitch = l == 1 ? q.pitch : q.g.W[l - 1];
+            y.ws = q.g.W[l - 1]; y.hs = q.g.H[l - 1];
+            y.dst_l = q.ws.pyr_l[l]; y.dst_r = q.ws.pyr_r[l];
+            y.wd = q.g.W[l]; y.hd = q.g.H[l];
+            add_job(j, p, l, l >= 2 ? at(p, l - 1, PK_PYR) : -1, -1);
+        }
+    for (int l = Lmax - 1; l >= 0; l--) {
+        for (int p = 0; p < np; p++) {
+            PairIn &q = pairs[p];
+            if (q.g.L <= l) continue;
+            PJob j;
+            memset(&j, 0, sizeof j);
+            j.kind = PK_LK; j.patch = q.patch; j.u8 = l == 0; j.kp = q.patch == 8 ? 1 : 2;
+            LkJob &k = j.lk;
+            k.L = l == 0 ? (const void *)q.left : q.ws.pyr_l[l];
+            k.R = l == 0 ? (const void *)q.right : q.ws.pyr_r[l];
+            k.pitch = l == 0 ? q.pitch : q.g.W[l];
+            k.W = q.g.W[l]; k.H = q.g.H[l];
+            bool coarsest = l == q.g.L - 1;
+            k.Uc = coarsest ? nullptr : q.ws.U[l + 1];
+            k.Wc = coarsest ? 0 : q.g.W[l + 1];
+            k.Hc = coarsest ? 0 : q.g.H[l + 1];
+            k.nx = q.g.nx[l]; k.ny = q.g.ny[l]; k.stride = q.stride;
+            k.reach = (int)std::ceil(std::max(0.f, q.dmax) / (float)(1 << l)) + 1;
+            k.rec_u = q.ws.rec_u[l]; k.rec_w = q.ws.rec_w[l];
+            k.rec_u0 = q.ws.rec_u0[l]; k.rec_st = q.ws.rec_st[l];
+            const int d0 = l >= 1 ? at(p, l, PK_PYR) : -1;
+            const int d1 = coarsest ? -1 : at(p, l + 1, PK_DENSE);
+            int lds = q.patch == 8 ? (f64 ? lk_lds_bytes<double, 8>() : lk_lds_bytes<float, 8>())
+                                   : (f64 ? lk_lds_bytes<double, 12>() : lk_lds_bytes<float, 12>());
+            t.lds = std::max(t.lds, lds);
+            add_job(j, p, l, d0, d1);
+        }
+        for (int p = 0; p < np; p++) {
+            PairIn &q = pairs[p];
+            if (q.g.L <= l) continue;
+            PJob j;
+            memset(&j, 0, sizeof j);
+            j.kind = PK_DENSE; j.u8 = l == 0; j.kp = 0;
+            DenseJob &d = j.dense;
+            d.L = l == 0 ? (const void *)q.left : q.ws.pyr_l[l];
+            d.R = l == 0 ? (const void *)q.right : q.ws.pyr_r[l];
+            d.pitch = l == 0 ? q.pitch : q.g.W[l];
+            d.W = q.g.W[l]; d.H = q.g.H[l];
+            d.patch = q.patch; d.stride = q.stride;
+            d.nx = q.g.nx[l]; d.ny = q.g.ny[l];
+            d.rec_u = q.ws.rec_u[l]; d.rec_w = q.ws.rec_w[l];
+            d.gtab = f64 ? (const void *)(h->gtab_d + gtab_offset(q.patch))
+                         : (const void *)(h->gtab_f + gtab_offset(q.patch));
+            bool coarsest = l == q.g.L - 1;
+            d.Uc = coarsest ? nullptr : q.ws.U[l + 1];
+            d.Wc = coarsest ? 0 : q.g.W[l + 1];
+            d.Hc = coarsest ? 0 : q.g.H[l + 1];
+            d.mode = l == 0 ? 2 : (coarsest ? 1 : 0);
+            d.U = l == 0 ? nullptr : q.ws.U[l];
+            d.out = l == 0 ? q.disp : nullptr;
+            d.out_pitch = q.dpitch;
+            add_job(j, p, l, at(p, l, PK_LK), -1);
+        }
+    }
+    if (ctr)
+        for (size_t i = 0; i < t.jobs.size(); i++) {
+            PJob &j = t.jobs[i];
+            j.done = ctr + i;
+            j.dep0 = dep_ids[2 * i] >= 0 ? ctr + dep_ids[2 * i] : nullptr;
+            j.dep1 = dep_ids[2 * i + 1] >= 0 ? ctr + dep_ids[2 * i + 1] : nullptr;
+        }
+}
+
+template <typename T>
+int persist_occupancy(int lds) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persist<T>, kBlock, lds) != hipSuccess) {
+        (void)hipGetLastError();
+        return 1;
+    }
+    return std::max(nb, 1);
+}
+
+bdis_status run_persistent(bdis_t *h, std::vector<PairIn> &pairs, hipStream_t s) {
+    for (auto &p : pairs)
+        if (!persist_patch_ok(p.patch)) {
+            set_err(h->err, "the persistent batch kernel supports patch 8 and 12 (got %d)", p.patch);
+            return BDIS_E_UNSUPPORTED;
+        }
+    const bool f64 = h->prm.precision == 0;
+    // size the device area first (counter addresses go into the tables)
+    PTables t;
+    build_ptables(h, pairs, nullptr, t);
+    const size_t njobs = t.jobs.size(), ntasks = t.tasks.size();
+    const size_t o_jobs = align_up(ntasks * sizeof(PTask));
+    const size_t o_kps = o_jobs + align_up(njobs * sizeof(PJob));
+    const size_t o_ctr = o_kps + align_up(t.kps.size() * sizeof(KParams));
+    const size_t total = o_ctr + align_up((njobs + 1) * sizeof(int));
+    if (total > h->p_dev_bytes) {
+        if (h->p_upload_pending) { HIPCHK(h, hipEventSynchronize(h->p_upload_ev)); h->p_upload_pending = false; }
+        HIPCHK(h, hipDeviceSynchronize());
+        if (h->p_dev) (void)hipFree(h->p_dev);
+        if (h->p_host) (void)hipHostFree(h->p_host);
+        h->p_dev = h->p_host = nullptr;
+        h->p_dev_bytes = h->p_host_bytes = 0;
+        size_t want = align_up(total + total / 4, 1 << 16);
+        if (hipMalloc(&h->p_dev, want) != hipSuccess || hipHostMalloc(&h->p_host, want, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            set_err(h->err, "task table allocation failed");
+            return BDIS_E_OOM;
+        }
+        h->p_dev_bytes = h->p_host_bytes = want;
+        h->p_last.clear();
+        h->graph_key.clear();
+    }
+    int *ctr = (int *)(h->p_dev + o_ctr);
+    h->p_err = ctr + njobs;
+    PTables t2;
+    build_ptables(h, pairs, ctr, t2);
+    std::vector<char> bytes(o_ctr);
+    memcpy(bytes.data(), t2.tasks.data(), ntasks * sizeof(PTask));
+    memcpy(bytes.data() + o_jobs, t2.jobs.data(), njobs * sizeof(PJob));
+    memcpy(bytes.data() + o_kps, t2.kps.data(), t2.kps.size() * sizeof(KParams));
+    if (bytes != h->p_last) {
+        if (h->p_upload_pending) { HIPCHK(h, hipEventSynchronize(h->p_upload_ev)); h->p_upload_pending = false; }
+        memcpy(h->p_host, bytes.data(), bytes.size());
+        HIPCHK(h, hipMemcpyAsync(h->p_dev, h->p_host, bytes.size(), hipMemcpyHostToDevice, s));
+        HIPCHK(h, hipEventRecord(h->p_upload_ev, s));
+        h->p_upload_pending = true;
+        h->p_last = bytes;
+    }
+    // grid: every workgroup resident
+    const int occ = f64 ? persist_occupancy<double>(t2.lds) : persist_occupancy<float>(t2.lds);
+    const int per_cu = h->wgs_per_cu > 0 ? std::min(h->wgs_per_cu, occ) : occ;
+    const int grid = (int)std::min<long long>((long long)per_cu * h->n_cu, (long long)ntasks);
+    std::vector<long long> key = {(long long)ntasks, (long long)njobs, (long long)t2.kps.size(), grid,
+                                  t2.lds, f64 ? 1 : 0, (long long)(uintptr_t)h->p_dev};
+    if (key != h->graph_key) {
+        if (h->graph_exec) { (void)hipGraphExecDestroy(h->graph_exec); h->graph_exec = nullptr; }
+        if (h->graph) { (void)hipGraphDestroy(h->graph); h->graph = nullptr; }
+        if (!h->cap_stream) HIPCHK(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+        const PTask *dt = (const PTask *)h->p_dev;
+        const PJob *dj = (const PJob *)(h->p_dev + o_jobs);
+        const KParams *dk = (const KParams *)(h->p_dev + o_kps);
+        const int spin_limit = 1 << 20;
+        HIPCHK(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+        int nctr = (int)njobs + 1;
+        hipLaunchKernelGGL(k_reset, dim3((nctr + kBlock - 1) / kBlock), dim3(kBlock), 0, h->cap_stream, ctr, nctr);
+        if (f64)
+            hipLaunchKernelGGL(k_persist<double>, dim3(grid), dim3(kBlock), t2.lds, h->cap_stream, dt,
+                               (int)ntasks, dj, dk, h->p_err, spin_limit);
+        else
+            hipLaunchKernelGGL(k_persist<float>, dim3(grid), dim3(kBlock), t2.lds, h->cap_stream, dt,
+                               (int)ntasks, dj, dk, h->p_err, spin_limit);
+        hipError_t e = hipStreamEndCapture(h->cap_stream, &h->graph);
+        if (e != hipSuccess) { set_err(h->err, "graph capture failed: %s", hipGetErrorString(e)); return BDIS_E_HIP; }
+        HIPCHK(h, hipGraphInstantiate(&h->graph_exec, h->graph, nullptr, nullptr, 0));
+        h->graph_key = key;
+    }
+    HIPCHK(h, hipGraphLaunch(h->graph_exec, s));
+    h->last_batch_stream = s;
+    return BDIS_OK;
+}
+
 // Shared body of bdis_compute and bdis_compute_batch.
-bdis_status run(bdis_t *h, std::vector<PairIn> &pairs, hipStream_t s) {
+bdis_status run(bdis_t *h, std::vector<PairIn> &pairs, hipStream_t s, bool persistent = false) {
     DeviceGuard dg(h->device);
-    int Lreq = requested_levels(h->prm);
     const size_t esz = esize(h->prm);
     size_t total = 0;
     for (auto &p : pairs) {
-        if (!make_geo(p.W, p.H, p.patch, p.stride, Lreq, p.g)) {
+        if (!make_geo(p.W, p.H, p.patch, p.stride, requested_levels(h->prm, p.dmax), p.g)) {
             set_err(h->err, "image %dx%d smaller than patch %d", p.W, p.H, p.patch);
             return BDIS_E_INVALID_ARG;
         }
@@ -515,6 +745,7 @@ bdis_status run(bdis_t *h, std::vector<PairIn> &pairs, hipStream_t s) {
         carve(h->ws + off, p.g, esz, p.ws);
         off += align_up(pair_ws_bytes(p.g, esz));
     }
+    if (persistent) return run_persistent(h, pairs, s);
     std::vector<Launch> ls;
     plan_launches(h, pairs, ls);
     launch_all(h, ls, s);
@@ -561,7 +792,7 @@ bdis_status bdis_plan(const bdis_params *p, int32_t width, int32_t height, bdis_
     if (st != BDIS_OK) return st;
     if (!out) { set_err(g_thread_err, "out is NULL"); return BDIS_E_INVALID_ARG; }
     Geo g;
-    if (!make_geo(width, height, p->patch, p->stride, requested_levels(*p), g)) {
+    if (!make_geo(width, height, p->patch, p->stride, requested_levels(*p, p->max_disparity), g)) {
         set_err(g_thread_err, "image %dx%d smaller than patch %d", width, height, p->patch);
         return BDIS_E_INVALID_ARG;
     }
@@ -601,9 +832,11 @@ bdis_status bdis_create(const bdis_params *p, int device, bdis_t **out) {
     if (!h) { set_err(g_thread_err, "host allocation failed"); return BDIS_E_OOM; }
     h->prm = *p;
     h->device = device;
+    h->n_cu = prop.multiProcessorCount;
     DeviceGuard dg(device);
     if (hipMalloc(&h->gtab_d, kGtabFloats * sizeof(double)) != hipSuccess ||
-        hipMalloc(&h->gtab_f, kGtabFloats * sizeof(float)) != hipSuccess) {
+        hipMalloc(&h->gtab_f, kGtabFloats * sizeof(float)) != hipSuccess ||
+        hipEventCreateWithFlags(&h->p_upload_ev, hipEventDisableTiming) != hipSuccess) {
         (void)hipGetLastError();
         set_err(g_thread_err, "device setup failed");
         bdis_destroy(h);
@@ -636,7 +869,7 @@ bdis_status bdis_reserve(bdis_t *h, int32_t width, int32_t height, int32_t n_pai
     }
     Geo g;
     size_t worst = 0;
-    int Lreq = requested_levels(h->prm);
+    int Lreq = requested_levels(h->prm, h->prm.max_disparity);
     for (int p : kSupportedPatch)
         for (int s = 1; s <= p; s++)
             if (make_geo(width, height, p, s, Lreq, g)) worst = std::max(worst, align_up(pair_ws_bytes(g, sizeof(double))));
@@ -655,6 +888,7 @@ bdis_status bdis_compute(bdis_t *h, const uint8_t *left, const uint8_t *right, i
     p.left = left; p.right = right; p.disp = disp;
     p.W = width; p.H = height; p.pitch = pitch_bytes; p.dpitch = disp_pitch_elems;
     p.patch = h->prm.patch; p.stride = h->prm.stride;
+    p.dmax = h->prm.max_disparity;
     hipStream_t s = (hipStream_t)stream;
     st = run(h, pairs, s);
     if (st != BDIS_OK) return st;
@@ -675,11 +909,36 @@ bdis_status bdis_compute_batch(bdis_t *h, const bdis_pair *pairs, int32_t n, voi
         bdis_status st = check_pair(h, q.left, q.right, q.width, q.height, q.pitch_bytes, q.disp,
                                     q.disp_pitch_elems, p.patch);
         if (st != BDIS_OK) return st;
+        if (!(q.max_disparity >= 0.f) || !std::isfinite(q.max_disparity)) {
+            set_err(h->err, "pair %d: max_disparity must be >= 0", i);
+            return BDIS_E_INVALID_ARG;
+        }
         p.left = q.left; p.right = q.right; p.disp = q.disp;
         p.W = q.width; p.H = q.height; p.pitch = q.pitch_bytes; p.dpitch = q.disp_pitch_elems;
+        p.dmax = q.max_disparity > 0.f ? q.max_disparity : h->prm.max_disparity;
     }
     h->have_last = false;
-    return run(h, ps, (hipStream_t)stream);
+    h->last_batch_stream = (hipStream_t)stream;
+    return run(h, ps, (hipStream_t)stream, h->batch_mode == 0);
+}
+
+bdis_status bdis_set_batch_mode(bdis_t *h, int32_t mode, int32_t wgs_per_cu) {
+    if (!h) { set_err(g_thread_err, "handle is NULL"); return BDIS_E_INVALID_ARG; }
+    if (mode != 0 && mode != 1) { set_err(h->err, "batch mode must be 0 or 1"); return BDIS_E_INVALID_ARG; }
+    if (wgs_per_cu < 0 || wgs_per_cu > 64) { set_err(h->err, "wgs_per_cu must be in [0, 64]"); return BDIS_E_INVALID_ARG; }
+    h->batch_mode = mode;
+    if (h->wgs_per_cu != wgs_per_cu) h->graph_key.clear();
+    h->wgs_per_cu = wgs_per_cu;
+    return BDIS_OK;
+}
+
+bdis_status bdis_batch_error(bdis_t *h, int32_t *flag) {
+    if (!h || !flag) { set_err(g_thread_err, "NULL argument"); return BDIS_E_INVALID_ARG; }
+    *flag = 0;
+    DeviceGuard dg(h->device);
+    HIPCHK(h, hipStreamSynchronize(h->last_batch_stream));
+    if (h->batch_mode == 0 && h->p_err) HIPCHK(h, hipMemcpy(flag, h->p_err, sizeof(int), hipMemcpyDeviceToHost));
+    return BDIS_OK;
 }
 
 bdis_status bdis_set_tuning(bdis_t *h, int32_t n, const int32_t *max_width, const int32_t *patch,
@@ -778,6 +1037,12 @@ void bdis_destroy(bdis_t *h) {
         DeviceGuard dg(h->device);
         (void)hipDeviceSynchronize();
         if (h->ws) (void)hipFree(h->ws);
+        if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+        if (h->graph) (void)hipGraphDestroy(h->graph);
+        if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+        if (h->p_dev) (void)hipFree(h->p_dev);
+        if (h->p_host) (void)hipHostFree(h->p_host);
+        if (h->p_upload_ev) (void)hipEventDestroy(h->p_upload_ev);
         if (h->gtab_d) (void)hipFree(h->gtab_d);
         if (h->gtab_f) (void)hipFree(h->gtab_f);
         for (auto &r : h->pending) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }

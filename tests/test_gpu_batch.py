@@ -1,0 +1,171 @@
+"""Batched execution: one persistent launch replayed from a hipGraph (mode 0)
+and one launch per level (mode 1) must both give, bit for bit, what
+bdis_compute gives on each pair alone, for pairs of mixed sizes and pyramid
+depths.  Graph replays with new buffers and repeated replays with eager
+work in between are checked replay by replay."""
+import numpy as np
+import pytest
+
+from paper_2106_07136_amd import synth
+from tests.parity_util import assert_parity, oracle_params
+
+pytestmark = pytest.mark.gpu
+
+# (width, height, max disparity, seed): levels come from the disparity
+MIXED = [(160, 120, 16.0, 1), (320, 240, 32.0, 2), (97, 61, 8.0, 3), (160, 120, 16.0, 4),
+         (200, 150, 20.0, 5), (64, 48, 6.0, 6), (640, 480, 64.0, 7)]
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _pairs(torch, spec, seed_shift=0):
+    out = []
+    for (W, H, d, s) in spec:
+        p = synth.make_pair(W, H, d, s + seed_shift)
+        out.append((p, torch.from_numpy(p.left).cuda(), torch.from_numpy(p.right).cuda(), d))
+    return out
+
+
+def _single(torch, base, pairs, patch=None, stride=None):
+    """Reference: each pair alone through bdis_compute with its own max disparity."""
+    import dataclasses
+
+    from paper_2106_07136_amd import bdis
+    res = []
+    for (p, L, R, d) in pairs:
+        prm = dataclasses.replace(base, max_disparity=d, patch=patch or base.patch,
+                                  stride=stride or base.stride)
+        h = bdis.Bdis(prm)
+        res.append(h.compute(L, R).cpu().numpy())
+        h.close()
+    return res
+
+
+def _bits(a):
+    return np.ascontiguousarray(a).view(np.uint32)
+
+
+def _run_batch(h, pairs, outs=None):
+    lefts = [q[1] for q in pairs]
+    rights = [q[2] for q in pairs]
+    outs = h.compute_batch(lefts, rights, outs, max_disparity=[q[3] for q in pairs])
+    return [o.cpu().numpy() for o in outs]
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_batch_equals_single(torch_cuda, mode):
+    from paper_2106_07136_amd import bdis
+    base = bdis.Params(levels=0, iters=10)
+    pairs = _pairs(torch_cuda, MIXED)
+    ref = _single(torch_cuda, base, pairs)
+    h = bdis.Bdis(base)
+    h.set_batch_mode(mode)
+    got = _run_batch(h, pairs)
+    assert h.batch_error() == 0
+    for i, (g, r) in enumerate(zip(got, ref)):
+        np.testing.assert_array_equal(_bits(g), _bits(r), err_msg=f"pair {i} mode {mode}")
+
+
+def test_batch_pair_matches_oracle(torch_cuda, ref):
+    from paper_2106_07136_amd import bdis
+    base = bdis.Params(levels=0, iters=10)
+    pairs = _pairs(torch_cuda, MIXED[:3])
+    h = bdis.Bdis(base)
+    got = _run_batch(h, pairs)
+    for (p, _, _, d), g in zip(pairs, got):
+        H, W = p.left.shape
+        L = bdis.plan(bdis.Params(levels=0, max_disparity=d), W, H)["levels"]
+        exp = ref.compute(p.left, p.right, oracle_params(ref, bdis.Params(levels=L, iters=10)))
+        assert_parity(g, exp, f"batch {W}x{H}")
+
+
+def test_graph_replay_with_new_buffers(torch_cuda):
+    """The graph is built once for the batch layout; new buffers only
+    re-upload the task tables.  Every replay is checked against the eager
+    per-pair results, with unrelated torch work between replays."""
+    from paper_2106_07136_amd import bdis
+    torch = torch_cuda
+    base = bdis.Params(levels=0, iters=8)
+    spec = MIXED[:4]
+    A = _pairs(torch, spec)
+    B = _pairs(torch, spec, seed_shift=100)
+    refA = _single(torch, base, A)
+    refB = _single(torch, base, B)
+    h = bdis.Bdis(base)
+    h.set_batch_mode(0)
+    outs = [torch.empty(q[1].shape, dtype=torch.float32, device="cuda") for q in A]
+    for rep in range(3):
+        for pairs, ref in ((A, refA), (B, refB)):
+            got = _run_batch(h, pairs, outs)
+            assert h.batch_error() == 0
+            for i, (g, r) in enumerate(zip(got, ref)):
+                np.testing.assert_array_equal(_bits(g), _bits(r), err_msg=f"replay {rep} pair {i}")
+            x = torch.randn(512, 512, device="cuda")
+            (x @ x).sum().item()  # eager work between replays
+    # the same buffers again: no table upload, plain replay
+    for rep in range(3):
+        got = _run_batch(h, B, outs)
+        for g, r in zip(got, refB):
+            np.testing.assert_array_equal(_bits(g), _bits(r))
+
+
+def test_tuning_table_selects_patch_and_stride(torch_cuda):
+    from paper_2106_07136_amd import bdis
+    base = bdis.Params(levels=0, iters=8, autotune=1)
+    small = [q for q in MIXED if q[0] <= 160][:3]
+    large = [q for q in MIXED if q[0] > 160][:2]
+    S = _pairs(torch_cuda, small)
+    Lg = _pairs(torch_cuda, large)
+    refS = _single(torch_cuda, bdis.Params(levels=0, iters=8), S, patch=12, stride=3)
+    refL = _single(torch_cuda, bdis.Params(levels=0, iters=8), Lg, patch=8, stride=6)
+    for mode in (0, 1):
+        h = bdis.Bdis(base)
+        h.set_batch_mode(mode)
+        h.set_tuning([(160, 12, 3), (100000, 8, 6)])
+        got = _run_batch(h, S + Lg)
+        for g, r in zip(got, refS + refL):
+            np.testing.assert_array_equal(_bits(g), _bits(r))
+
+
+def test_persistent_mode_patch_limits(torch_cuda):
+    from paper_2106_07136_amd import bdis
+    pairs = _pairs(torch_cuda, MIXED[:2])
+    h = bdis.Bdis(bdis.Params(levels=0, patch=16, stride=8))
+    h.set_batch_mode(0)
+    with pytest.raises(bdis.BdisError) as e:
+        _run_batch(h, pairs)
+    assert e.value.status == bdis.E_UNSUPPORTED
+    h.set_batch_mode(1)
+    got = _run_batch(h, pairs)
+    assert all(np.isfinite(g).any() for g in got)
+
+
+def test_batch_fp32(torch_cuda):
+    from paper_2106_07136_amd import bdis
+    base = bdis.Params(levels=0, iters=8, precision=1)
+    pairs = _pairs(torch_cuda, MIXED[:4])
+    ref = _single(torch_cuda, base, pairs)
+    h = bdis.Bdis(base)
+    got = _run_batch(h, pairs)
+    for g, r in zip(got, ref):
+        np.testing.assert_array_equal(_bits(g), _bits(r))
+
+
+def test_wgs_per_cu_setting(torch_cuda):
+    from paper_2106_07136_amd import bdis
+    base = bdis.Params(levels=0, iters=8)
+    pairs = _pairs(torch_cuda, MIXED[:3])
+    ref = _single(torch_cuda, base, pairs)
+    h = bdis.Bdis(base)
+    for w in (1, 2):
+        h.set_batch_mode(0, w)
+        got = _run_batch(h, pairs)
+        assert h.batch_error() == 0
+        for g, r in zip(got, ref):
+            np.testing.assert_array_equal(_bits(g), _bits(r))
