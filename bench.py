@@ -74,6 +74,66 @@ def cpu_baseline(pair, oparams, budget_s=20.0):
                       f"{n * t1:.1f} s of CPU work; single-thread {W * H / t1 / 1e6:.3f} Mpixel/s"}
 
 
+def batched_leg(batch, calib, steps, warmup, precision):
+    """Mixed batch of 64 pairs in one persistent launch, autotuned first."""
+    import numpy as np
+    import torch
+
+    from paper_2106_07136_amd import autotune, bdis
+    dev = torch.device("cuda:0")
+    base = bdis.Params(levels=0, iters=12, precision=precision)
+    classes = [(320, [p for p in calib if p.left.shape[1] == 320]),
+               (640, [p for p in calib if p.left.shape[1] == 640]),
+               (100000, [p for p in calib if p.left.shape[1] == 1280])]
+    log("bench: autotuning patch/stride per size class")
+    tuned = autotune.tune(base, classes, reps=3, log=log)
+    L = [torch.from_numpy(p.left).to(dev) for p in batch]
+    R = [torch.from_numpy(p.right).to(dev) for p in batch]
+    O = [torch.empty(p.left.shape, dtype=torch.float32, device=dev) for p in batch]
+    dm = [p.d_max for p in batch]
+    mpx = sum(p.left.size for p in batch) / 1e6
+
+    def timed(h):
+        for _ in range(warmup):
+            h.compute_batch(L, R, O, max_disparity=dm)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            h.compute_batch(L, R, O, max_disparity=dm)
+        e1.record()
+        torch.cuda.synchronize()
+        assert h.batch_error() == 0, "persistent batch reported a dependency timeout"
+        return e0.elapsed_time(e1) / steps
+
+    h = bdis.Bdis(bdis.Params(levels=0, iters=12, precision=precision, autotune=1))
+    autotune.apply(h, tuned)
+    ms = timed(h)
+    epe, cov = [], []
+    for o, p in zip(O, batch):
+        d = o.cpu().numpy()
+        m = np.isfinite(d) & p.valid
+        epe.append(float(np.abs(d[m] - p.disp[m]).mean()))
+        cov.append(float(m.sum() / p.valid.sum()))
+    h0 = bdis.Bdis(base)
+    modes = {}
+    for m in (0, 1, 2):
+        h0.set_batch_mode(m)
+        modes[m] = timed(h0)
+    log(f"bench: batched {mpx:.2f} Mpx: tuned {ms:.3f} ms; patch 8 stride 4: level graph {modes[0]:.3f} ms, "
+        f"direct launches {modes[1]:.3f} ms, persistent kernel {modes[2]:.3f} ms")
+    return {"workload": "plain BDIS, 64 synthetic pairs per launch (24x320x240, 24x640x480, "
+                        "16x1280x720), disparity up to 10% of the width, automatic levels, 12 iterations",
+            "value": mpx / (ms / 1e3), "unit": "Mpixel/s", "ms_per_batch": ms, "mpixel_per_batch": mpx,
+            "steps": steps, "tuning": tuned["table"], "batch_mode": tuned["batch_mode"],
+            "wgs_per_cu": tuned["wgs_per_cu"],
+            "p8s4_level_graph_mpxs": mpx / (modes[0] / 1e3),
+            "p8s4_direct_launches_mpxs": mpx / (modes[1] / 1e3),
+            "p8s4_persistent_kernel_mpxs": mpx / (modes[2] / 1e3),
+            "epe_px": float(np.mean(epe)), "coverage": float(np.mean(cov))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,6 +141,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--precision", type=int, default=0, help="0 = FP64 (default), 1 = FP32")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-pair batched leg")
+    ap.add_argument("--batch-steps", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); stereo pairs are "
@@ -96,6 +158,13 @@ def main():
     LEVELS, PATCH, STRIDE, ITERS = 5, 8, 4, 12
     log(f"bench: generating {W}x{H} pair seed {SEED}")
     pair = synth.make_pair(W, H, DMAX, SEED)
+    batch = calib = None
+    if not args.no_batch:
+        log("bench: generating the 64-pair mixed batch and 24 calibration pairs")
+        batch = synth.make_pairs(synth.mixed_batch_spec(3000))
+        calib = synth.make_pairs([(Wc, Hc, 0.1 * Wc, 3900 + 10 * i + j)
+                                  for i, (Wc, Hc) in enumerate(((320, 240), (640, 480), (1280, 720)))
+                                  for j in range(8)])
     dev = torch.device("cuda:0")
     L = torch.from_numpy(pair.left).to(dev)
     R = torch.from_numpy(pair.right).to(dev)
@@ -165,6 +234,8 @@ def main():
         "roofline": roof,
         "kernels": kernels,
     }
+    if batch is not None:
+        res["batched"] = batched_leg(batch, calib, args.batch_steps, 2, args.precision)
     if not args.no_cpu:
         import oracle
         log("bench: CPU oracle baseline")

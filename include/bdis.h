@@ -152,20 +152,22 @@ BDIS_API bdis_status bdis_compute(bdis_t *h, const uint8_t *left, const uint8_t 
 BDIS_API bdis_status bdis_compute_batch(bdis_t *h, const bdis_pair *pairs, int32_t n, void *stream);
 
 /* How bdis_compute_batch runs a batch.
- *   mode 0 (default): one persistent kernel over a task list of every block
- *     of every pair and level, dependencies tracked by per-job completion
- *     counters, captured with a counter-reset kernel in a hipGraph that is
- *     replayed while the batch layout stays the same (new buffer pointers
- *     only re-upload the task tables).  Patch sides 8 and 12 only.
- *   mode 1: one launch per kernel kind and level over all pairs.
+ *   mode 0 (default): one launch per kernel kind and level over all pairs,
+ *     the whole sequence captured once in a hipGraph and replayed while the
+ *     batch (sizes, pointers, parameters) stays the same.
+ *   mode 1: the same launches issued directly on the stream.
+ *   mode 2: one persistent kernel over a task list of every block of every
+ *     pair and level, dependencies tracked by per-job completion counters,
+ *     captured with a counter-reset kernel in a hipGraph; new buffer pointers
+ *     only re-upload the task tables.  Patch sides 8 and 12 only.
  * wgs_per_cu: persistent workgroups per compute unit (0 = as many as fit).
- * Results are the same in both modes, bit for bit. */
+ * Results are the same in every mode, bit for bit. */
 BDIS_API bdis_status bdis_set_batch_mode(bdis_t *h, int32_t mode, int32_t wgs_per_cu);
 
 /* Waits for the last bdis_compute_batch and reports whether the persistent
  * kernel had to give up a dependency wait (*flag = 1: that batch's results are
  * not valid; it cannot happen when the kernel owns the GPU).  *flag = 0 in
- * mode 1. */
+ * modes 0 and 1. */
 BDIS_API bdis_status bdis_batch_error(bdis_t *h, int32_t *flag);
 
 /* Autotuner table: for images whose width is <= max_width[i] (ascending),

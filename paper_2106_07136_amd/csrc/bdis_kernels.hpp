@@ -41,43 +41,54 @@ struct KParams {
     double conv_tol;     // not converged iff |last LK step| > conv_tol (<= 0: off)
 };
 
+static_assert(sizeof(KParams) == 56, "KParams has no padding: it is compared byte for byte");
+
+// Job descriptors have no padding bytes (pointers first, ints after, an
+// explicit pad where needed): they are copied and compared byte for byte.
 struct PyrJob {
     const void *src_l, *src_r;  // level l-1 (uint8 when l-1 == 0)
+    void *dst_l, *dst_r;        // level l (arithmetic type), pitch = wd
     int src_pitch;              // elements
     int ws, hs;                 // level l-1 size
-    void *dst_l, *dst_r;        // level l (arithmetic type), pitch = wd
-    int wd, hd;
-    int block0;
+    int wd, hd;                 // level l size
+    int ppt;                    // coarse pixels per thread (block = ppt * kBlock)
+    int block0;                 // first block of this job in its launch
+    int pad_;
 };
+static_assert(sizeof(PyrJob) == 4 * 8 + 8 * 4, "PyrJob must have no padding");
 
 struct LkJob {
     const void *L, *R;     // this level's images
-    int pitch;             // elements
-    int W, H;
     const void *Uc;        // coarse field (level + 1), pitch Wc; null at coarsest
+    void *rec_u, *rec_w, *rec_u0;  // per-patch records, arithmetic type
+    int8_t *rec_st;        // per-patch outcome
+    int pitch;             // image pitch, elements
+    int W, H;
     int Wc, Hc;
     int nx, ny, stride;
     int reach;             // staged span reaches this many columns left of a
                            // patch (the level's largest expected disparity)
-    void *rec_u, *rec_w, *rec_u0;  // arithmetic type
-    int8_t *rec_st;
     int block0;
 };
+static_assert(sizeof(LkJob) == 7 * 8 + 10 * 4, "LkJob must have no padding");
 
 struct DenseJob {
     const void *L, *R;     // images (DIS fusion only)
-    int pitch;
-    int W, H, patch, stride, nx, ny;
     const void *rec_u, *rec_w;
     const void *gtab;      // patch x patch spatial weights
     const void *Uc;        // fallback source (0 < l < L-1)
-    int Wc, Hc;
-    int mode;              // 0: fallback to 2*Uc, 1: zero (coarsest), 2: NaN (level 0)
     void *U;               // level field out (pitch W), or null
     float *out;            // level 0: disparity out (= -U), or null
+    int pitch;
+    int W, H, patch, stride, nx, ny;
+    int Wc, Hc;
+    int mode;              // 0: fallback to 2*Uc, 1: zero (coarsest), 2: NaN (level 0)
     int out_pitch;
+    int ppt;               // pixels per thread (block = ppt * kBlock pixels)
     int block0;
+    int pad_;
 };
+static_assert(sizeof(DenseJob) == 8 * 8 + 14 * 4, "DenseJob must have no padding");
 
 // ---------------------------------------------------------------- helpers
 
@@ -88,6 +99,7 @@ constexpr int kMaxJobs = 24;
 template <typename Job>
 struct JobPack {
     int n;
+    int pad_;
     Job j[kMaxJobs];
 };
 
@@ -264,18 +276,17 @@ __device__ __forceinline__ void pyr_pixel(const PyrJob &J, int i, const KParams 
     }
 }
 
-// Block lb of a pyramid job: kPixPerThread coarse pixels per thread.
-constexpr int kPixPerThread = 4;
-__host__ __device__ constexpr int pyr_blocks(int wd, int hd) {
-    return (wd * hd + kBlock * kPixPerThread - 1) / (kBlock * kPixPerThread);
+// Block lb of a pyramid job: ppt coarse pixels per thread (1 for a launch
+// per level, more for the coarser tasks of the persistent kernel).
+__host__ __device__ constexpr int pyr_blocks(int wd, int hd, int ppt) {
+    return (wd * hd + kBlock * ppt - 1) / (kBlock * ppt);
 }
 
 template <typename T, bool U8>
 __device__ __forceinline__ void pyr_block(const PyrJob &J, int lb, const KParams &kp) {
     const int n = J.wd * J.hd;
-#pragma unroll
-    for (int q = 0; q < kPixPerThread; q++) {
-        int i = (lb * kPixPerThread + q) * kBlock + (int)threadIdx.x;
+    for (int q = 0; q < J.ppt; q++) {
+        int i = (lb * J.ppt + q) * kBlock + (int)threadIdx.x;
         if (i < n) pyr_pixel<T, U8>(J, i, kp);
     }
 }
@@ -654,16 +665,15 @@ __device__ __forceinline__ void dense_pixel(const DenseJob &J, const int i, cons
     if (J.U) static_cast<T *>(J.U)[i] = U;
 }
 
-__host__ __device__ constexpr int dense_blocks(int w, int h) {
-    return (w * h + kBlock * kPixPerThread - 1) / (kBlock * kPixPerThread);
+__host__ __device__ constexpr int dense_blocks(int w, int h, int ppt) {
+    return (w * h + kBlock * ppt - 1) / (kBlock * ppt);
 }
 
 template <typename T, bool U8>
 __device__ __forceinline__ void dense_block(const DenseJob &J, int lb, const KParams &kp) {
     const int n = J.W * J.H;
-#pragma unroll
-    for (int q = 0; q < kPixPerThread; q++) {
-        int i = (lb * kPixPerThread + q) * kBlock + (int)threadIdx.x;
+    for (int q = 0; q < J.ppt; q++) {
+        int i = (lb * J.ppt + q) * kBlock + (int)threadIdx.x;
         if (i < n) dense_pixel<T, U8>(J, i, kp);
     }
 }

@@ -19,19 +19,21 @@ namespace bdis {
 enum { PK_PYR = 0, PK_LK = 1, PK_DENSE = 2 };
 
 struct PJob {
+    int *done;       // this job's completion counter (blocks finished)
+    const int *dep0; // jobs this one reads: counter and the count meaning done
+    const int *dep1;
     int kind;        // PK_*
     int patch;       // LK patch side
     int u8;          // level-0 images (uint8) or a pyramid level
     int kp;          // index of the job's KParams
-    int *done;       // this job's completion counter (blocks finished)
-    const int *dep0; // jobs this one reads: counter and the count meaning done
     int need0;
-    const int *dep1;
     int need1;
     PyrJob pyr;
     LkJob lk;
     DenseJob dense;
 };
+static_assert(sizeof(PJob) == 3 * 8 + 6 * 4 + sizeof(PyrJob) + sizeof(LkJob) + sizeof(DenseJob),
+              "PJob must have no padding");
 
 struct PTask {
     int job;

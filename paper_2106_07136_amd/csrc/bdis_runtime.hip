@@ -198,9 +198,11 @@ struct bdis_ctx {
     bool p_upload_pending = false;
     std::vector<char> p_last;     // last uploaded table bytes
     std::vector<char> p_key;      // batch description the tables were built for
-    hipGraph_t graph = nullptr;
+    hipGraph_t graph = nullptr;            // persistent kernel graph (mode 2)
     hipGraphExec_t graph_exec = nullptr;
     std::vector<long long> graph_key;
+    hipGraphExec_t lv_exec = nullptr;      // per-level launch graph (mode 0)
+    std::vector<char> lv_key;
     int *p_err = nullptr;         // device error flag of the last persistent run
     hipStream_t last_batch_stream = nullptr;
     int n_cu = 0;
@@ -309,14 +311,14 @@ void append(std::vector<Launch> &ls, Kind kind, int level, int patch, bool u8, b
             std::vector<Job> &jobs, const KParams &kp, F blocks_of) {
     for (size_t s0 = 0; s0 < jobs.size(); s0 += kMaxJobs) {
         JobPack<Job> pk;
-        memset(&pk, 0, sizeof pk);
+        memset(&pk, 0, sizeof pk);  // padding included: packs are compared byte for byte
         pk.n = 0;
         int blocks = 0;
         for (size_t i = s0; i < jobs.size() && i < s0 + kMaxJobs; i++) {
-            Job j = jobs[i];
-            j.block0 = blocks;
-            blocks += blocks_of(j);
-            pk.j[pk.n++] = j;
+            memcpy(&pk.j[pk.n], &jobs[i], sizeof(Job));
+            pk.j[pk.n].block0 = blocks;
+            blocks += blocks_of(pk.j[pk.n]);
+            pk.n++;
         }
         if (blocks == 0) continue;
         Launch L{kind, level, patch, u8, f64, blocks, kp, {}};
@@ -349,24 +351,25 @@ void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<Launch> &l
         std::vector<PyrJob> jobs;
         for (auto &p : pairs) {
             if (p.g.L <= l) continue;
-            PyrJob j;
+            PyrJob j{};  // zeroed padding: job packs are compared byte for byte
             j.src_l = l == 1 ? (const void *)p.left : p.ws.pyr_l[l - 1];
             j.src_r = l == 1 ? (const void *)p.right : p.ws.pyr_r[l - 1];
             j.src_pitch = l == 1 ? p.pitch : p.g.W[l - 1];
             j.ws = p.g.W[l - 1]; j.hs = p.g.H[l - 1];
             j.dst_l = p.ws.pyr_l[l]; j.dst_r = p.ws.pyr_r[l];
             j.wd = p.g.W[l]; j.hd = p.g.H[l];
+            j.ppt = 1;
             jobs.push_back(j);
         }
         append(ls, K_PYR, l, 0, l == 1, f64, jobs, kp0,
-               [](const PyrJob &j) { return pyr_blocks(j.wd, j.hd); });
+               [](const PyrJob &j) { return pyr_blocks(j.wd, j.hd, j.ppt); });
     }
     for (int l = Lmax - 1; l >= 0; l--) {
         for (int P : kSupportedPatch) {
             std::vector<LkJob> jobs;
             for (auto &p : pairs) {
                 if (p.g.L <= l || p.patch != P) continue;
-                LkJob j;
+                LkJob j{};
                 j.L = l == 0 ? (const void *)p.left : p.ws.pyr_l[l];
                 j.R = l == 0 ? (const void *)p.right : p.ws.pyr_r[l];
                 j.pitch = l == 0 ? p.pitch : p.g.W[l];
@@ -387,7 +390,7 @@ void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<Launch> &l
         std::vector<DenseJob> jobs;
         for (auto &p : pairs) {
             if (p.g.L <= l) continue;
-            DenseJob j;
+            DenseJob j{};
             j.L = l == 0 ? (const void *)p.left : p.ws.pyr_l[l];
             j.R = l == 0 ? (const void *)p.right : p.ws.pyr_r[l];
             j.pitch = l == 0 ? p.pitch : p.g.W[l];
@@ -405,10 +408,11 @@ void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<Launch> &l
             j.U = l == 0 ? nullptr : p.ws.U[l];
             j.out = l == 0 ? p.disp : nullptr;
             j.out_pitch = p.dpitch;
+            j.ppt = 1;
             jobs.push_back(j);
         }
         append(ls, K_DENSE, l, 0, l == 0, f64, jobs, kp0,
-               [](const DenseJob &j) { return dense_blocks(j.W, j.H); });
+               [](const DenseJob &j) { return dense_blocks(j.W, j.H, j.ppt); });
     }
 }
 
@@ -538,9 +542,9 @@ void build_ptables(bdis_t *h, std::vector<PairIn> &pairs, int *ctr, PTables &t) 
     std::vector<int> idx((size_t)np * kMaxLevels * 3, -1);
     auto at = [&](int p, int l, int k) -> int & { return idx[((size_t)p * kMaxLevels + l) * 3 + k]; };
     auto blocks_of = [&](const PJob &j) {
-        if (j.kind == PK_PYR) return pyr_blocks(j.pyr.wd, j.pyr.hd);
+        if (j.kind == PK_PYR) return pyr_blocks(j.pyr.wd, j.pyr.hd, j.pyr.ppt);
         if (j.kind == PK_LK) return j.lk.ny * lk_bpr(j.patch, j.lk.nx);
-        return dense_blocks(j.dense.W, j.dense.H);
+        return dense_blocks(j.dense.W, j.dense.H, j.dense.ppt);
     };
     // jobs name their dependencies by job id while the list is built; the
     // counters' device addresses are bound at the end
@@ -570,6 +574,7 @@ void build_ptables(bdis_t *h, std::vector<PairIn> &pairs, int *ctr, PTables &t) 
             y.ws = q.g.W[l - 1]; y.hs = q.g.H[l - 1];
             y.dst_l = q.ws.pyr_l[l]; y.dst_r = q.ws.pyr_r[l];
             y.wd = q.g.W[l]; y.hd = q.g.H[l];
+            y.ppt = 4;
             add_job(j, p, l, l >= 2 ? at(p, l - 1, PK_PYR) : -1, -1);
         }
     for (int l = Lmax - 1; l >= 0; l--) {
@@ -623,6 +628,7 @@ void build_ptables(bdis_t *h, std::vector<PairIn> &pairs, int *ctr, PTables &t) 
             d.U = l == 0 ? nullptr : q.ws.U[l];
             d.out = l == 0 ? q.disp : nullptr;
             d.out_pitch = q.dpitch;
+            d.ppt = 4;
             add_job(j, p, l, at(p, l, PK_LK), -1);
         }
     }
@@ -726,8 +732,49 @@ bdis_status run_persistent(bdis_t *h, std::vector<PairIn> &pairs, hipStream_t s)
     return BDIS_OK;
 }
 
+// Mode 0: the per-level launch sequence captured in a hipGraph, re-captured
+// only when the launches (kernels, grids, job packs) change.
+bdis_status run_level_graph(bdis_t *h, const std::vector<Launch> &ls, hipStream_t s) {
+    std::vector<char> key;
+    for (const Launch &L : ls) {
+        const int hdr[6] = {(int)L.kind, L.level, L.patch, (int)L.u8, (int)L.f64, L.blocks};
+        key.insert(key.end(), reinterpret_cast<const char *>(hdr), reinterpret_cast<const char *>(hdr + 6));
+        const char *kp = reinterpret_cast<const char *>(&L.kp);
+        key.insert(key.end(), kp, kp + sizeof(KParams));
+        key.insert(key.end(), L.pack.begin(), L.pack.end());
+    }
+    if (key != h->lv_key || !h->lv_exec) {
+        if (!h->cap_stream) HIPCHK(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+        const bool prof = h->profiling;
+        h->profiling = false;  // no event records inside the captured graph
+        HIPCHK(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+        launch_all(h, ls, h->cap_stream);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+        h->profiling = prof;
+        if (e != hipSuccess) { set_err(h->err, "graph capture failed: %s", hipGetErrorString(e)); return BDIS_E_HIP; }
+        bool updated = false;
+        if (h->lv_exec) {
+            hipGraphExecUpdateResult res;
+            hipGraphNode_t bad = nullptr;
+            updated = hipGraphExecUpdate(h->lv_exec, g, &bad, &res) == hipSuccess && res == hipGraphExecUpdateSuccess;
+            if (!updated) {
+                (void)hipGetLastError();
+                (void)hipGraphExecDestroy(h->lv_exec);
+                h->lv_exec = nullptr;
+            }
+        }
+        hipError_t ie = updated ? hipSuccess : hipGraphInstantiate(&h->lv_exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess) { set_err(h->err, "graph instantiate failed: %s", hipGetErrorString(ie)); return BDIS_E_HIP; }
+        h->lv_key.swap(key);
+    }
+    HIPCHK(h, hipGraphLaunch(h->lv_exec, s));
+    return BDIS_OK;
+}
+
 // Shared body of bdis_compute and bdis_compute_batch.
-bdis_status run(bdis_t *h, std::vector<PairIn> &pairs, hipStream_t s, bool persistent = false) {
+bdis_status run(bdis_t *h, std::vector<PairIn> &pairs, hipStream_t s, int mode = 1) {
     DeviceGuard dg(h->device);
     const size_t esz = esize(h->prm);
     size_t total = 0;
@@ -745,9 +792,10 @@ bdis_status run(bdis_t *h, std::vector<PairIn> &pairs, hipStream_t s, bool persi
         carve(h->ws + off, p.g, esz, p.ws);
         off += align_up(pair_ws_bytes(p.g, esz));
     }
-    if (persistent) return run_persistent(h, pairs, s);
+    if (mode == 2) return run_persistent(h, pairs, s);
     std::vector<Launch> ls;
     plan_launches(h, pairs, ls);
+    if (mode == 0) return run_level_graph(h, ls, s);
     launch_all(h, ls, s);
     HIPCHK(h, hipGetLastError());
     return BDIS_OK;
@@ -919,12 +967,12 @@ bdis_status bdis_compute_batch(bdis_t *h, const bdis_pair *pairs, int32_t n, voi
     }
     h->have_last = false;
     h->last_batch_stream = (hipStream_t)stream;
-    return run(h, ps, (hipStream_t)stream, h->batch_mode == 0);
+    return run(h, ps, (hipStream_t)stream, h->batch_mode);
 }
 
 bdis_status bdis_set_batch_mode(bdis_t *h, int32_t mode, int32_t wgs_per_cu) {
     if (!h) { set_err(g_thread_err, "handle is NULL"); return BDIS_E_INVALID_ARG; }
-    if (mode != 0 && mode != 1) { set_err(h->err, "batch mode must be 0 or 1"); return BDIS_E_INVALID_ARG; }
+    if (mode < 0 || mode > 2) { set_err(h->err, "batch mode must be 0, 1 or 2"); return BDIS_E_INVALID_ARG; }
     if (wgs_per_cu < 0 || wgs_per_cu > 64) { set_err(h->err, "wgs_per_cu must be in [0, 64]"); return BDIS_E_INVALID_ARG; }
     h->batch_mode = mode;
     if (h->wgs_per_cu != wgs_per_cu) h->graph_key.clear();
@@ -937,7 +985,7 @@ bdis_status bdis_batch_error(bdis_t *h, int32_t *flag) {
     *flag = 0;
     DeviceGuard dg(h->device);
     HIPCHK(h, hipStreamSynchronize(h->last_batch_stream));
-    if (h->batch_mode == 0 && h->p_err) HIPCHK(h, hipMemcpy(flag, h->p_err, sizeof(int), hipMemcpyDeviceToHost));
+    if (h->batch_mode == 2 && h->p_err) HIPCHK(h, hipMemcpy(flag, h->p_err, sizeof(int), hipMemcpyDeviceToHost));
     return BDIS_OK;
 }
 
@@ -1039,6 +1087,7 @@ void bdis_destroy(bdis_t *h) {
         if (h->ws) (void)hipFree(h->ws);
         if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
         if (h->graph) (void)hipGraphDestroy(h->graph);
+        if (h->lv_exec) (void)hipGraphExecDestroy(h->lv_exec);
         if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
         if (h->p_dev) (void)hipFree(h->p_dev);
         if (h->p_host) (void)hipHostFree(h->p_host);

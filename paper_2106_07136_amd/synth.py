@@ -172,3 +172,32 @@ def random_pair_tiny(W: int, H: int, seed: int, lo=0, hi=256) -> tuple[np.ndarra
     a = rng.integers(lo, hi, (H, W), dtype=np.uint8)
     b = rng.integers(lo, hi, (H, W), dtype=np.uint8)
     return a, b
+
+
+def _make_one(args):
+    W, H, d, s = args
+    return make_pair(W, H, d, s)
+
+
+def make_pairs(spec, workers: int = 0):
+    """make_pair for each (W, H, d_max, seed) of spec, in order, on a pool of
+    worker processes (0 = one per CPU, at most 16).  Call it before the GPU
+    is touched in this process: workers are forked."""
+    import multiprocessing as mp
+    import os
+    spec = list(spec)
+    n = workers or min(16, os.cpu_count() or 1, max(1, len(spec)))
+    if n <= 1 or len(spec) <= 1:
+        return [_make_one(a) for a in spec]
+    with mp.get_context("fork").Pool(n) as pool:
+        return pool.map(_make_one, spec, chunksize=1)
+
+
+def mixed_batch_spec(seed0: int = 3000):
+    """64 pairs of mixed sizes: 24 at 320x240, 24 at 640x480, 16 at 1280x720,
+    disparity up to 10 % of the width, seeds seed0, seed0 + 1, ..."""
+    spec = []
+    for (W, H, n) in ((320, 240, 24), (640, 480, 24), (1280, 720, 16)):
+        for _ in range(n):
+            spec.append((W, H, 0.1 * W, seed0 + len(spec)))
+    return spec

@@ -1,5 +1,6 @@
-"""Batched execution: one persistent launch replayed from a hipGraph (mode 0)
-and one launch per level (mode 1) must both give, bit for bit, what
+"""Batched execution: per-level launches replayed from a hipGraph (mode 0),
+the same launches issued directly (mode 1) and one persistent launch
+replayed from a hipGraph (mode 2) must all give, bit for bit, what
 bdis_compute gives on each pair alone, for pairs of mixed sizes and pyramid
 depths.  Graph replays with new buffers and repeated replays with eager
 work in between are checked replay by replay."""
@@ -58,7 +59,7 @@ def _run_batch(h, pairs, outs=None):
     return [o.cpu().numpy() for o in outs]
 
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 def test_batch_equals_single(torch_cuda, mode):
     from paper_2106_07136_amd import bdis
     base = bdis.Params(levels=0, iters=10)
@@ -85,10 +86,12 @@ def test_batch_pair_matches_oracle(torch_cuda, ref):
         assert_parity(g, exp, f"batch {W}x{H}")
 
 
-def test_graph_replay_with_new_buffers(torch_cuda):
-    """The graph is built once for the batch layout; new buffers only
-    re-upload the task tables.  Every replay is checked against the eager
-    per-pair results, with unrelated torch work between replays."""
+@pytest.mark.parametrize("mode", [0, 2])
+def test_graph_replay_with_new_buffers(torch_cuda, mode):
+    """Graph modes: mode 0 updates its graph for new buffers, mode 2 keeps
+    its graph and re-uploads the task tables.  Every replay is checked
+    against the eager per-pair results, with unrelated torch work between
+    replays."""
     from paper_2106_07136_amd import bdis
     torch = torch_cuda
     base = bdis.Params(levels=0, iters=8)
@@ -98,7 +101,7 @@ def test_graph_replay_with_new_buffers(torch_cuda):
     refA = _single(torch, base, A)
     refB = _single(torch, base, B)
     h = bdis.Bdis(base)
-    h.set_batch_mode(0)
+    h.set_batch_mode(mode)
     outs = [torch.empty(q[1].shape, dtype=torch.float32, device="cuda") for q in A]
     for rep in range(3):
         for pairs, ref in ((A, refA), (B, refB)):
@@ -124,7 +127,7 @@ def test_tuning_table_selects_patch_and_stride(torch_cuda):
     Lg = _pairs(torch_cuda, large)
     refS = _single(torch_cuda, bdis.Params(levels=0, iters=8), S, patch=12, stride=3)
     refL = _single(torch_cuda, bdis.Params(levels=0, iters=8), Lg, patch=8, stride=6)
-    for mode in (0, 1):
+    for mode in (0, 1, 2):
         h = bdis.Bdis(base)
         h.set_batch_mode(mode)
         h.set_tuning([(160, 12, 3), (100000, 8, 6)])
@@ -137,13 +140,14 @@ def test_persistent_mode_patch_limits(torch_cuda):
     from paper_2106_07136_amd import bdis
     pairs = _pairs(torch_cuda, MIXED[:2])
     h = bdis.Bdis(bdis.Params(levels=0, patch=16, stride=8))
-    h.set_batch_mode(0)
+    h.set_batch_mode(2)
     with pytest.raises(bdis.BdisError) as e:
         _run_batch(h, pairs)
     assert e.value.status == bdis.E_UNSUPPORTED
-    h.set_batch_mode(1)
-    got = _run_batch(h, pairs)
-    assert all(np.isfinite(g).any() for g in got)
+    for mode in (0, 1):
+        h.set_batch_mode(mode)
+        got = _run_batch(h, pairs)
+        assert all(np.isfinite(g).any() for g in got)
 
 
 def test_batch_fp32(torch_cuda):
@@ -151,10 +155,12 @@ def test_batch_fp32(torch_cuda):
     base = bdis.Params(levels=0, iters=8, precision=1)
     pairs = _pairs(torch_cuda, MIXED[:4])
     ref = _single(torch_cuda, base, pairs)
-    h = bdis.Bdis(base)
-    got = _run_batch(h, pairs)
-    for g, r in zip(got, ref):
-        np.testing.assert_array_equal(_bits(g), _bits(r))
+    for mode in (0, 2):
+        h = bdis.Bdis(base)
+        h.set_batch_mode(mode)
+        got = _run_batch(h, pairs)
+        for g, r in zip(got, ref):
+            np.testing.assert_array_equal(_bits(g), _bits(r))
 
 
 def test_wgs_per_cu_setting(torch_cuda):
@@ -164,7 +170,7 @@ def test_wgs_per_cu_setting(torch_cuda):
     ref = _single(torch_cuda, base, pairs)
     h = bdis.Bdis(base)
     for w in (1, 2):
-        h.set_batch_mode(0, w)
+        h.set_batch_mode(2, w)
         got = _run_batch(h, pairs)
         assert h.batch_error() == 0
         for g, r in zip(got, ref):
