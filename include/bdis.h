@@ -210,6 +210,52 @@ BDIS_API bdis_status bdis_set_profiling(bdis_t *h, int32_t on);
  * bdis_set_profiling(h, 1). */
 BDIS_API bdis_status bdis_get_profile(bdis_t *h, bdis_kernel_time *out, int32_t cap, int32_t *count);
 
+/* ------------------------------------------------------------------------
+ * Learned proposal network (an added serving pattern, not in the paper):
+ * four 3x3 convolutions with ReLU on the 1/16 pyramid level -> (coarse
+ * disparity, confidence logit).  BF16 weights and activations, FP32
+ * accumulation on the matrix cores (implicit GEMM).  FP32 master weights
+ * and Adam moments stay on the device.  Parameter vector layout (FP32): for
+ * each layer in order, weights [3][3][C_in][C_out] (tap row, tap column,
+ * input channel, output channel) then biases [C_out]; layer (C_in, C_out):
+ * (16, C), (C, C), (C, C), (C, 2).  Input: NHWC bfloat16, 16 channels.
+ * Output: NHWC FP32, 2 channels.  All device pointers are caller-owned.
+ * ------------------------------------------------------------------------ */
+typedef struct bdisnet_ctx bdisnet_t;
+
+/* channels C: 32 or 48.  Weights start at zero (set them before use). */
+BDIS_API bdis_status bdisnet_create(int32_t channels, int device, bdisnet_t **out);
+BDIS_API void bdisnet_destroy(bdisnet_t *h);               /* NULL-safe */
+BDIS_API int64_t bdisnet_param_count(const bdisnet_t *h);
+/* FP32 master weights from/to HOST memory (n = bdisnet_param_count);
+ * setting them also clears the Adam moments.  Synchronous. */
+BDIS_API bdis_status bdisnet_set_params(bdisnet_t *h, const float *host, int64_t n);
+BDIS_API bdis_status bdisnet_get_params(bdisnet_t *h, float *host, int64_t n);
+/* Forward of n images of hh x ww (device x, device out); the handle keeps
+ * the activations for one backward. */
+BDIS_API bdis_status bdisnet_forward(bdisnet_t *h, const uint16_t *x, int32_t n, int32_t hh, int32_t ww,
+                                     float *out, void *stream);
+/* Training loss of the last forward against target (device FP32 per pixel,
+ * coarse disparity) on valid pixels (device uint8): mean over valid pixels
+ * of Huber(d - t; delta) + conf_weight * BCE(sigmoid(c), [|d - t| < conf_tol]).
+ * Writes the scalar to device *loss and keeps d loss / d output. */
+BDIS_API bdis_status bdisnet_loss(bdisnet_t *h, const float *target, const uint8_t *valid, float delta,
+                                  float conf_tol, float conf_weight, float *loss, void *stream);
+/* Use a caller-supplied d loss / d output (device FP32, 2 channels) instead. */
+BDIS_API bdis_status bdisnet_set_output_grad(bdisnet_t *h, const float *gout, void *stream);
+/* Gradients of all parameters from the kept activations and output
+ * gradient (deterministic: no atomics). */
+BDIS_API bdis_status bdisnet_backward(bdisnet_t *h, void *stream);
+BDIS_API bdis_status bdisnet_get_grads(bdisnet_t *h, float *host, int64_t n);
+/* One Adam step (step counts from 1) on the FP32 master weights, then the
+ * BF16 copies used by the kernels are refreshed. */
+BDIS_API bdis_status bdisnet_adam_step(bdisnet_t *h, float lr, float beta1, float beta2, float eps,
+                                       int32_t step, void *stream);
+/* Input of layer `layer` (0 = the network input) from the last forward, as
+ * bfloat16 bits in HOST memory.  Synchronous. */
+BDIS_API bdis_status bdisnet_debug_activation(bdisnet_t *h, int32_t layer, uint16_t *host, size_t elems);
+BDIS_API const char *bdisnet_last_error(const bdisnet_t *h);
+
 /* Frees the handle and its workspace; NULL is allowed. */
 BDIS_API void bdis_destroy(bdis_t *h);
 

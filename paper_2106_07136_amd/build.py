@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbdis.so")
-SOURCES = [os.path.join(CSRC, "bdis_runtime.hip")]
+SOURCES = [os.path.join(CSRC, "bdis_runtime.hip"), os.path.join(CSRC, "bdisnet.hip")]
 DEPS = SOURCES + [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))] + \
     [os.path.join(ROOT, "include", "bdis.h")]
 
