@@ -94,6 +94,7 @@ typedef struct {
 } bdis_params;
 
 typedef struct bdis_ctx bdis_t;
+typedef struct bdisnet_ctx bdisnet_t;  /* proposal network, see below */
 
 /* One stereo pair for bdis_compute_batch (device pointers, caller-owned).
  * max_disparity > 0 overrides the handle's for this pair (automatic level
@@ -221,8 +222,6 @@ BDIS_API bdis_status bdis_get_profile(bdis_t *h, bdis_kernel_time *out, int32_t 
  * (16, C), (C, C), (C, C), (C, 2).  Input: NHWC bfloat16, 16 channels.
  * Output: NHWC FP32, 2 channels.  All device pointers are caller-owned.
  * ------------------------------------------------------------------------ */
-typedef struct bdisnet_ctx bdisnet_t;
-
 /* channels C: 32 or 48.  Weights start at zero (set them before use). */
 BDIS_API bdis_status bdisnet_create(int32_t channels, int device, bdisnet_t **out);
 BDIS_API void bdisnet_destroy(bdisnet_t *h);               /* NULL-safe */
@@ -255,6 +254,27 @@ BDIS_API bdis_status bdisnet_adam_step(bdisnet_t *h, float lr, float beta1, floa
  * bfloat16 bits in HOST memory.  Synchronous. */
 BDIS_API bdis_status bdisnet_debug_activation(bdisnet_t *h, int32_t layer, uint16_t *host, size_t elems);
 BDIS_API const char *bdisnet_last_error(const bdisnet_t *h);
+
+/* Attaches a proposal network (NULL detaches) for params.init =
+ * BDIS_INIT_LEARNED.  The learned path: pyramid down to the 1/16 level, the
+ * network there (pairs of one 1/16 size batched together), then a gate that
+ * writes the initial field of level learned_fine_levels: u = -4 d (d the
+ * network disparity read bilinearly, the factor being the scale between the
+ * 1/16 level and that level) where the confidence is >= conf_threshold.  The
+ * plain levels from the coarsest down to learned_fine_levels run for a pair
+ * only when some network pixel of it is below the threshold, and then
+ * replace the initial field only where the confidence is low (plain
+ * fallback).  The finer levels run with learned_iters LK iterations.  The
+ * handle does not own the network; keep it alive while it is attached.
+ * Errors: BDIS_E_INVALID_ARG (network on another device). */
+BDIS_API bdis_status bdis_set_net(bdis_t *h, bdisnet_t *net);
+
+/* Network input of n pairs whose 1/16 levels have the same size: builds
+ * their pyramids down to the 1/16 level and writes x (device, NHWC
+ * bfloat16, n x H16 x W16 x 16): (L - 128)/64, (R - 128)/64 and
+ * |L(x) - R(x - d)|/64 for d = 0..13, R's column clamped.  Used to build
+ * training batches. */
+BDIS_API bdis_status bdis_net_input(bdis_t *h, const bdis_pair *pairs, int32_t n, uint16_t *x, void *stream);
 
 /* Frees the handle and its workspace; NULL is allowed. */
 BDIS_API void bdis_destroy(bdis_t *h);

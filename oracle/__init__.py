@@ -111,6 +111,9 @@ def lib():
         L.ref_compute.restype = C.c_int
         L.ref_compute.argtypes = [C.POINTER(_Params), _PU8, _PU8, C.c_int, C.c_int, C.c_int,
                                   _PD, C.POINTER(_Trace)]
+        L.ref_compute_init.restype = C.c_int
+        L.ref_compute_init.argtypes = [C.POINTER(_Params), _PU8, _PU8, C.c_int, C.c_int, C.c_int,
+                                       C.c_int, _PD, C.c_int, _PD]
         L.ref_num_levels.restype = C.c_int
         L.ref_grid_count.restype = C.c_int
         L.ref_grid_pos.restype = C.c_int
@@ -289,4 +292,23 @@ def compute(left, right, params: Params | None = None, trace: bool = False):
         raise ValueError(f"ref_compute failed: {rc}")
     if trace:
         return disp, keep
+    return disp
+
+
+def compute_init(left, right, params: Params, init_level: int, U_init, init_iters: int):
+    """Levels init_level-1 .. 0 from the dense field U_init of level
+    init_level (the learned-init pipeline with its proposal as an input)."""
+    left = np.ascontiguousarray(left, np.uint8)
+    right = np.ascontiguousarray(right, np.uint8)
+    H, W = left.shape
+    U = np.ascontiguousarray(U_init, np.float64)
+    w, h = level_dims(W, H, init_level)
+    if U.shape != (h, w):
+        raise ValueError(f"U_init must be {h}x{w}")
+    disp = np.empty((H, W))
+    p = params._c()
+    rc = lib().ref_compute_init(C.byref(p), _u8(left), _u8(right), W, H, W, init_level, _d(U),
+                                init_iters, _d(disp))
+    if rc != 0:
+        raise ValueError(f"ref_compute_init failed: {rc}")
     return disp

@@ -479,15 +479,39 @@ void ref_densify(const ref_params *P, int W, int H, int nx, int ny, const double
 /* Returns 0 on success, -1 on bad arguments, -2 on allocation failure.
  * disp: W*H doubles, row-major, d = -U_0, NaN where no patch covered the
  * pixel (Sec. 3.2: such pixels are not estimated). */
+static int ref_compute_impl(const ref_params *P, const uint8_t *Limg, const uint8_t *Rimg, int W,
+                            int H, int pitch, double *disp, ref_trace *trace, int init_level,
+                            const double *U_init, int init_iters);
+
 int ref_compute(const ref_params *P, const uint8_t *Limg, const uint8_t *Rimg, int W, int H,
                 int pitch, double *disp, ref_trace *trace)
+{
+    return ref_compute_impl(P, Limg, Rimg, W, H, pitch, disp, trace, -1, NULL, 0);
+}
+
+/* The fine levels only, from a given initial field: U_init is the dense
+ * field of level init_level (level pixels, row-major, that level's size);
+ * levels init_level-1 .. 0 run as in ref_compute with init_iters LK
+ * iterations.  This is the learned-init pipeline with the proposal taken as
+ * an input. */
+int ref_compute_init(const ref_params *P, const uint8_t *Limg, const uint8_t *Rimg, int W, int H,
+                     int pitch, int init_level, const double *U_init, int init_iters, double *disp)
+{
+    if (!U_init || init_level < 1 || init_iters < 0 || init_iters > 1000)
+        return -1;
+    return ref_compute_impl(P, Limg, Rimg, W, H, pitch, disp, NULL, init_level, U_init, init_iters);
+}
+
+static int ref_compute_impl(const ref_params *P, const uint8_t *Limg, const uint8_t *Rimg, int W,
+                            int H, int pitch, double *disp, ref_trace *trace, int init_level,
+                            const double *U_init, int init_iters)
 {
     if (!P || !Limg || !Rimg || !disp || W < 1 || H < 1 || pitch < W || P->patch < 1 ||
         P->stride < 1 || P->iters < 0 || P->iters > 1000 || P->window < 1 || (P->window % 2) == 0 ||
         P->window > 63 || W < P->patch || H < P->patch)
         return -1;
     int NL = ref_num_levels(W, H, P->patch, P->levels);
-    if (NL < 1)
+    if (NL < 1 || (init_level >= 0 && init_level >= NL))
         return -1;
 
     double *pl[REF_MAX_LEVELS], *pr[REF_MAX_LEVELS], *gl[REF_MAX_LEVELS], *U[REF_MAX_LEVELS];
@@ -536,7 +560,15 @@ int ref_compute(const ref_params *P, const uint8_t *Limg, const uint8_t *Rimg, i
     for (int l = 0; l < NL; l++)
         ref_grad_x(pl[l], Ws[l], Hs[l], gl[l]);
 
-    for (int l = NL - 1; l >= 0; l--) {
+    int top = NL - 1;
+    if (init_level >= 0) {
+        memcpy(U[init_level], U_init, (size_t)Ws[init_level] * Hs[init_level] * sizeof(double));
+        top = init_level - 1;
+    }
+    ref_params Pl = *P;
+    if (init_level >= 0)
+        Pl.iters = init_iters;
+    for (int l = top; l >= 0; l--) {
         int w = Ws[l], h = Hs[l], p = P->patch;
         int nx = ref_grid_count(w, p, P->stride), ny = ref_grid_count(h, p, P->stride);
         size_t np = (size_t)nx * ny;
@@ -560,7 +592,7 @@ int ref_compute(const ref_params *P, const uint8_t *Limg, const uint8_t *Rimg, i
                     u0 = 2.0 * ref_bilinear(U[l + 1], Ws[l + 1], Hs[l + 1], 0.5 * cx, 0.5 * cy);
                 }
                 ref_patch_out o;
-                ref_patch(P, pl[l], pr[l], gl[l], ml[l], mr[l], w, h, x0, y0, u0, &o);
+                ref_patch(&Pl, pl[l], pr[l], gl[l], ml[l], mr[l], w, h, x0, y0, u0, &o);
                 pu[k] = o.u;
                 pp[k] = o.status == REF_KEPT ? o.post : 0.0;
                 ps[k] = (int8_t)o.status;

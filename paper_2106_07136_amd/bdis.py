@@ -108,6 +108,8 @@ def lib():
         L.bdis_debug_stage.argtypes = [vp, i32, i32, vp, C.c_size_t]
         L.bdis_set_batch_mode.argtypes = [vp, i32, i32]
         L.bdis_batch_error.argtypes = [vp, C.POINTER(i32)]
+        L.bdis_set_net.argtypes = [vp, vp]
+        L.bdis_net_input.argtypes = [vp, C.POINTER(CPair), i32, vp, vp]
         L.bdis_set_profiling.argtypes = [vp, i32]
         L.bdis_get_profile.argtypes = [vp, C.POINTER(CKernelTime), i32, C.POINTER(i32)]
         L.bdis_destroy.argtypes = [vp]
@@ -119,7 +121,7 @@ def lib():
         for name in ("bdis_plan", "bdis_create", "bdis_set_params", "bdis_reserve", "bdis_compute",
                      "bdis_compute_batch", "bdis_set_tuning", "bdis_debug_stage",
                      "bdis_set_profiling", "bdis_get_profile", "bdis_set_batch_mode",
-                     "bdis_batch_error"):
+                     "bdis_batch_error", "bdis_set_net", "bdis_net_input"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -206,6 +208,28 @@ class Bdis:
         _check(lib().bdis_compute(self._h, left.data_ptr(), right.data_ptr(), W, H, left.stride(0),
                                   out.data_ptr(), out.stride(0), _stream_ptr(stream)), self._h)
         self._last_shape = (W, H)
+        return out
+
+    def set_net(self, net):
+        """Attach a paper_2106_07136_amd.net.ProposalNet (None detaches); it is
+        used when params.init == 1 (learned)."""
+        _check(lib().bdis_set_net(self._h, net.handle if net is not None else None), self._h)
+        self._net = net
+
+    def net_input(self, lefts, rights, out=None, stream=None):
+        """Network input (N, H/16, W/16, 16) bfloat16 for same-size pairs."""
+        import torch
+        n = len(lefts)
+        H, W = lefts[0].shape
+        h16, w16 = H, W
+        for _ in range(4):
+            h16, w16 = (h16 + 1) // 2, (w16 + 1) // 2
+        if out is None:
+            out = torch.empty((n, h16, w16, 16), dtype=torch.bfloat16, device=lefts[0].device)
+        arr = (CPair * n)()
+        for i, (l, r) in enumerate(zip(lefts, rights)):
+            arr[i] = CPair(l.data_ptr(), r.data_ptr(), None, l.shape[1], l.shape[0], l.stride(0), 0, 0.0)
+        _check(lib().bdis_net_input(self._h, arr, n, out.data_ptr(), _stream_ptr(stream)), self._h)
         return out
 
     def set_batch_mode(self, mode: int, wgs_per_cu: int = 0):

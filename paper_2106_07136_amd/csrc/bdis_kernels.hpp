@@ -62,6 +62,7 @@ struct LkJob {
     const void *Uc;        // coarse field (level + 1), pitch Wc; null at coarsest
     void *rec_u, *rec_w, *rec_u0;  // per-patch records, arithmetic type
     int8_t *rec_st;        // per-patch outcome
+    const int *run_flag;   // non-null: the job runs only if *run_flag != 0
     int pitch;             // image pitch, elements
     int W, H;
     int Wc, Hc;
@@ -70,7 +71,7 @@ struct LkJob {
                            // patch (the level's largest expected disparity)
     int block0;
 };
-static_assert(sizeof(LkJob) == 7 * 8 + 10 * 4, "LkJob must have no padding");
+static_assert(sizeof(LkJob) == 8 * 8 + 10 * 4, "LkJob must have no padding");
 
 struct DenseJob {
     const void *L, *R;     // images (DIS fusion only)
@@ -79,6 +80,8 @@ struct DenseJob {
     const void *Uc;        // fallback source (0 < l < L-1)
     void *U;               // level field out (pitch W), or null
     float *out;            // level 0: disparity out (= -U), or null
+    const int *run_flag;   // non-null: the job runs only if *run_flag != 0
+    const uint8_t *keep;   // non-null: pixels with keep[i] != 0 are left as they are
     int pitch;
     int W, H, patch, stride, nx, ny;
     int Wc, Hc;
@@ -88,7 +91,33 @@ struct DenseJob {
     int block0;
     int pad_;
 };
-static_assert(sizeof(DenseJob) == 8 * 8 + 14 * 4, "DenseJob must have no padding");
+static_assert(sizeof(DenseJob) == 10 * 8 + 14 * 4, "DenseJob must have no padding");
+
+// Input of the proposal network for one pair at its level (NHWC bfloat16,
+// 16 channels).
+struct NetInJob {
+    const void *L, *R;     // pyramid level images (arithmetic type, sign = invalid)
+    uint16_t *x;           // output, W * H * 16
+    int W, H;
+    int block0;
+    int pad_;
+};
+static_assert(sizeof(NetInJob) == 3 * 8 + 4 * 4, "NetInJob must have no padding");
+
+// Learned initial field of one pair at the injection level from the network
+// output at the network level.
+struct GateJob {
+    const float *net;      // network output (H4 x W4 x 2: disparity, confidence logit)
+    void *U;               // field at the injection level (arithmetic type), Wi x Hi
+    uint8_t *keep;         // 1 where the learned value is kept (confident)
+    int *flag;             // set to 1 when some network pixel is not confident
+    int W4, H4, Wi, Hi;
+    int block0;
+    float thr;             // confidence threshold
+    float sxy;             // injection-level pixel -> network-level coordinate
+    float sd;              // network disparity -> shift u at the injection level
+};
+static_assert(sizeof(GateJob) == 4 * 8 + 8 * 4, "GateJob must have no padding");
 
 // ---------------------------------------------------------------- helpers
 
@@ -340,6 +369,7 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
     using S = LkShape<P>;
     constexpr int SEG = S::SEG, PPB = S::PPB, NCMAX = S::NCMAX;
     constexpr int NCPAD = NCMAX + 1;
+    if (J.run_flag && *J.run_flag == 0) return;  // uniform over the block
 
     const int W = J.W;
     const int bpr = lk_blocks_per_row<P>(J.nx);
@@ -614,6 +644,8 @@ __global__ __launch_bounds__(kBlock) void k_lk(const JobPack<LkJob> pk, KParams 
 // NaN at level 0, zero at the coarsest level, else twice the coarse field.
 template <typename T, bool U8>
 __device__ __forceinline__ void dense_pixel(const DenseJob &J, const int i, const KParams &kp) {
+    if (J.run_flag && *J.run_flag == 0) return;
+    if (J.keep && J.keep[i]) return;
     const int y = i / J.W, x = i - y * J.W;
     const int P = J.patch, st = J.stride;
     const T *rec_u = static_cast<const T *>(J.rec_u);
@@ -682,6 +714,81 @@ template <typename T, bool U8>
 __global__ __launch_bounds__(kBlock) void k_dense(const JobPack<DenseJob> pk, KParams kp) {
     const DenseJob &J = pk.j[find_job(pk, (int)blockIdx.x)];
     dense_block<T, U8>(J, (int)blockIdx.x - J.block0, kp);
+}
+
+// ---------------------------------------------------------------- learned init
+
+// Network input for one pyramid pixel: (L - 128)/64, (R - 128)/64, then
+// |L(x) - R(x - d)| / 64 for d = 0..13 (R's column clamped), in the
+// arithmetic type, rounded to bfloat16 through float.
+__device__ inline uint16_t to_bf16(double v) {
+    float f = (float)v;
+    uint32_t u = __builtin_bit_cast(uint32_t, f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+constexpr int kNetIn = 16;
+constexpr int kNetDisp = kNetIn - 2;
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_net_input(const JobPack<NetInJob> pk) {
+    const NetInJob &J = pk.j[find_job(pk, (int)blockIdx.x)];
+    const int i = ((int)blockIdx.x - J.block0) * kBlock + (int)threadIdx.x;
+    if (i >= J.W * J.H) return;
+    const int y = i / J.W, x = i - y * J.W;
+    const T *L = static_cast<const T *>(J.L), *R = static_cast<const T *>(J.R);
+    const double lv = (double)fabs(L[i]), rv = (double)fabs(R[i]);
+    uint16_t *o = J.x + (size_t)i * kNetIn;
+    o[0] = to_bf16((lv - 128.0) / 64.0);
+    o[1] = to_bf16((rv - 128.0) / 64.0);
+    for (int d = 0; d < kNetDisp; d++) {
+        const int xs = x - d < 0 ? 0 : x - d;
+        o[2 + d] = to_bf16(fabs(lv - (double)fabs(R[(size_t)y * J.W + xs])) / 64.0);
+    }
+}
+
+// Bilinear read of channel ch of an interleaved 2-channel map, coordinates
+// clamped; SIG applies the logistic function to the four taps first.
+template <bool SIG>
+__device__ inline float bilinear2(const float *F, int W, int H, int ch, float X, float Y) {
+    X = fminf(fmaxf(X, 0.f), (float)(W - 1));
+    Y = fminf(fmaxf(Y, 0.f), (float)(H - 1));
+    int mx = min(max((int)floorf(X), 0), max(W - 2, 0));
+    int my = min(max((int)floorf(Y), 0), max(H - 2, 0));
+    float fx = W > 1 ? X - (float)mx : 0.f, fy = H > 1 ? Y - (float)my : 0.f;
+    int mx1 = W > 1 ? mx + 1 : mx, my1 = H > 1 ? my + 1 : my;
+    auto at = [&](int yy, int xx) {
+        float v = F[((size_t)yy * W + xx) * 2 + ch];
+        return SIG ? 1.f / (1.f + expf(-v)) : v;
+    };
+    float a = (1.f - fx) * at(my, mx) + fx * at(my, mx1);
+    float b = (1.f - fx) * at(my1, mx) + fx * at(my1, mx1);
+    return (1.f - fy) * a + fy * b;
+}
+
+// Learned field at the injection level: u = sd * disparity(x * sxy) and
+// keep = confidence(x * sxy) >= thr.  Block 0 of each pair also sets the
+// pair's fallback flag: 1 when any network pixel is below the threshold.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gate(const JobPack<GateJob> pk) {
+    const GateJob &J = pk.j[find_job(pk, (int)blockIdx.x)];
+    const int lb = (int)blockIdx.x - J.block0;
+    if (lb == 0) {
+        int low = 0;
+        for (int q = (int)threadIdx.x; q < J.W4 * J.H4; q += kBlock)
+            low |= (1.f / (1.f + expf(-J.net[(size_t)q * 2 + 1]))) < J.thr;
+        low = __syncthreads_or(low);
+        if (threadIdx.x == 0) *J.flag = low ? 1 : 0;
+    }
+    const int i = lb * kBlock + (int)threadIdx.x;
+    if (i >= J.Wi * J.Hi) return;
+    const int y = i / J.Wi, x = i - y * J.Wi;
+    const float X = (float)x * J.sxy, Y = (float)y * J.sxy;
+    const float d = bilinear2<false>(J.net, J.W4, J.H4, 0, X, Y);
+    const float c = bilinear2<true>(J.net, J.W4, J.H4, 1, X, Y);
+    static_cast<T *>(J.U)[i] = (T)(J.sd * d);
+    J.keep[i] = c >= J.thr ? 1 : 0;
 }
 
 }  // namespace bdis

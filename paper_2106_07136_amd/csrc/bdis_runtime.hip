@@ -15,6 +15,7 @@
 #include "bdis.h"
 #include "bdis_kernels.hpp"
 #include "bdis_persist.hpp"
+#include "bdisnet_internal.hpp"
 
 using namespace bdis;
 
@@ -23,6 +24,7 @@ namespace {
 constexpr int kMaxLevels = 12;
 constexpr int kSupportedPatch[] = {4, 6, 8, 10, 12, 16};
 constexpr int kMaxTuning = 8;
+constexpr int kNetLevel = 4;  // the proposal network runs on the 1/16 pyramid level
 
 thread_local char g_thread_err[512] = "";
 
@@ -77,7 +79,11 @@ bdis_status check_params(const bdis_params *p, char *err) {
     if (p->init != BDIS_INIT_ZERO && p->init != BDIS_INIT_LEARNED) { set_err(err, "init must be 0 or 1"); return BDIS_E_INVALID_ARG; }
     if (p->autotune != 0 && p->autotune != 1) { set_err(err, "autotune must be 0 or 1"); return BDIS_E_INVALID_ARG; }
     if (!patch_supported(p->patch)) { set_err(err, "patch %d not built (4, 6, 8, 10, 12, 16)", p->patch); return BDIS_E_UNSUPPORTED; }
-    if (p->init == BDIS_INIT_LEARNED) { set_err(err, "learned init is not available in this build"); return BDIS_E_UNSUPPORTED; }
+    if (p->learned_fine_levels < 1 || p->learned_fine_levels > kNetLevel) {
+        set_err(err, "learned_fine_levels must be in [1, %d]", kNetLevel); return BDIS_E_INVALID_ARG;
+    }
+    if (p->learned_iters < 0 || p->learned_iters > 1000) { set_err(err, "learned_iters outside [0, 1000]"); return BDIS_E_INVALID_ARG; }
+    if (!(p->conf_threshold >= 0.f && p->conf_threshold <= 1.f)) { set_err(err, "conf_threshold must be in [0, 1]"); return BDIS_E_INVALID_ARG; }
     return BDIS_OK;
 }
 
@@ -90,14 +96,16 @@ int requested_levels(const bdis_params &p, float dmax) {
 
 // Geometry of one pair under (patch, stride).
 struct Geo {
-    int L;
+    int L;   // LK levels
+    int Lp;  // pyramid levels (>= L; deeper when the network needs its level)
     int W[kMaxLevels], H[kMaxLevels], nx[kMaxLevels], ny[kMaxLevels];
     long long patches;
 };
 
 int grid_count(int n, int p, int st) { return n < p ? 0 : (n - p + st - 1) / st + 1; }
 
-bool make_geo(int W, int H, int patch, int stride, int Lreq, Geo &g) {
+// min_pyr: pyramid levels needed beyond the LK levels (the network's level).
+bool make_geo(int W, int H, int patch, int stride, int Lreq, Geo &g, int min_pyr = 0) {
     if (W < patch || H < patch) return false;
     g.L = 0;
     g.patches = 0;
@@ -112,47 +120,83 @@ bool make_geo(int W, int H, int patch, int stride, int Lreq, Geo &g) {
         w = (w + 1) / 2;
         h = (h + 1) / 2;
     }
+    g.Lp = g.L;
+    for (int l = g.L; l < min_pyr && l < kMaxLevels; l++) {
+        g.W[l] = w; g.H[l] = h;
+        g.nx[l] = g.ny[l] = 0;
+        g.Lp = l + 1;
+        w = (w + 1) / 2;
+        h = (h + 1) / 2;
+    }
     return g.L >= 1;
 }
 
 size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
 
 // Workspace of one pair, elements of the arithmetic type (esz bytes):
-// pyramid levels >= 1 (2 images), fields U_l for l >= 1, and per-level patch
-// records (u, w, u0 + a status byte).
+// pyramid levels >= 1 (2 images), fields U_l for LK levels l >= 1, per-level
+// patch records (u, w, u0 + a status byte), and for the learned init the
+// keep mask at the injection level and the fallback flag.
 struct PairWs {
     void *pyr_l[kMaxLevels], *pyr_r[kMaxLevels], *U[kMaxLevels];
     void *rec_u[kMaxLevels], *rec_w[kMaxLevels], *rec_u0[kMaxLevels];
     int8_t *rec_st[kMaxLevels];
+    uint8_t *keep;
+    int *flag;
 };
 
-size_t pair_ws_bytes(const Geo &g, size_t esz) {
+// inj: injection level of the learned init (0 = no learned buffers)
+size_t pair_ws_bytes(const Geo &g, size_t esz, int inj = 0) {
     size_t b = 0;
-    for (int l = 0; l < g.L; l++) {
+    for (int l = 0; l < g.Lp; l++) {
         size_t px = (size_t)g.W[l] * g.H[l], np = (size_t)g.nx[l] * g.ny[l];
-        if (l >= 1) b += 3 * align_up(px * esz);
-        b += 3 * align_up(np * esz) + align_up(np);
+        if (l >= 1) b += 2 * align_up(px * esz);
+        if (l >= 1 && l < g.L) b += align_up(px * esz);
+        if (l < g.L) b += 3 * align_up(np * esz) + align_up(np);
     }
+    if (inj > 0) b += align_up((size_t)g.W[inj] * g.H[inj]) + align_up(sizeof(int));
     return b;
 }
 
-void carve(char *base, const Geo &g, size_t esz, PairWs &w) {
+void carve(char *base, const Geo &g, size_t esz, PairWs &w, int inj = 0) {
     memset(&w, 0, sizeof w);
     size_t off = 0;
     auto take = [&](size_t bytes) { char *p = base + off; off += align_up(bytes); return (void *)p; };
-    for (int l = 0; l < g.L; l++) {
+    for (int l = 0; l < g.Lp; l++) {
         size_t px = (size_t)g.W[l] * g.H[l], np = (size_t)g.nx[l] * g.ny[l];
         if (l >= 1) {
             w.pyr_l[l] = take(px * esz);
             w.pyr_r[l] = take(px * esz);
-            w.U[l] = take(px * esz);
         }
-        w.rec_u[l] = take(np * esz);
-        w.rec_w[l] = take(np * esz);
-        w.rec_u0[l] = take(np * esz);
-        w.rec_st[l] = (int8_t *)take(np);
+        if (l >= 1 && l < g.L) w.U[l] = take(px * esz);
+        if (l < g.L) {
+            w.rec_u[l] = take(np * esz);
+            w.rec_w[l] = take(np * esz);
+            w.rec_u0[l] = take(np * esz);
+            w.rec_st[l] = (int8_t *)take(np);
+        }
+    }
+    if (inj > 0) {
+        w.keep = (uint8_t *)take((size_t)g.W[inj] * g.H[inj]);
+        w.flag = (int *)take(sizeof(int));
     }
 }
+
+// Same-size pairs whose network input, hidden activations and output share
+// one contiguous batch.
+struct NetGroup {
+    int W4, H4;
+    std::vector<int> pairs;  // indices into the call's pair list
+    uint16_t *x = nullptr, *a[3] = {};
+    float *out = nullptr;
+};
+
+// Kernel-argument payload of a network forward launch.
+struct NetLaunch {
+    uint16_t *x, *a1, *a2, *a3;
+    float *out;
+    int n, H, W, pad_;
+};
 
 struct PairIn {
     const uint8_t *left, *right;
@@ -162,6 +206,8 @@ struct PairIn {
     float dmax;  // largest expected disparity, level-0 pixels
     Geo g;
     PairWs ws;
+    int group = -1;   // learned init: network group and index in it
+    int gindex = 0;
 };
 
 }  // namespace
@@ -174,6 +220,8 @@ struct bdis_ctx {
     size_t ws_bytes = 0;
     double *gtab_d = nullptr;  // spatial Gaussian tables, one per precision
     float *gtab_f = nullptr;
+    bdisnet_t *net = nullptr;  // proposal network for init = BDIS_INIT_LEARNED
+    std::vector<NetGroup> groups;
     // last single-pair run, for bdis_debug_stage
     bool have_last = false;
     PairIn last;
@@ -292,7 +340,7 @@ bdis_status ensure_ws(bdis_t *h, size_t bytes) {
 }
 
 // A launch: kernel kind, template selectors and its jobs (passed by value).
-enum Kind { K_PYR, K_LK, K_DENSE };
+enum Kind { K_PYR, K_LK, K_DENSE, K_NETIN, K_NET, K_GATE };
 struct Launch {
     Kind kind;
     int level;
@@ -342,15 +390,29 @@ int lk_bpr(int P, int nx) {
 // Build every launch for a set of pairs: pyramid levels 1..Lmax-1, then for
 // each level from the coarsest down, LK (per patch size) and the
 // densification.
+bool learned(const bdis_t *h) { return h->prm.init == BDIS_INIT_LEARNED; }
+
+// Build every launch for a set of pairs: pyramid levels 1..Lp-1, then for
+// each level from the coarsest down, LK (per patch size) and the
+// densification.  With the learned init, the network input, forward and
+// gate come after the pyramid; the levels at and above the injection level
+// run only for pairs the gate flagged (plain fallback where the network is
+// not confident), the injection level's densification leaves the confident
+// pixels alone, and the finer levels use learned_iters.
 void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<Launch> &ls) {
-    int Lmax = 0;
+    int Lmax = 0, Lpmax = 0;
     const bool f64 = h->prm.precision == 0;
-    for (auto &p : pairs) Lmax = std::max(Lmax, p.g.L);
+    const bool lrn = learned(h);
+    const int inj = h->prm.learned_fine_levels;
+    for (auto &p : pairs) {
+        Lmax = std::max(Lmax, p.g.L);
+        Lpmax = std::max(Lpmax, p.g.Lp);
+    }
     KParams kp0 = make_kparams(h->prm, h->prm.patch);
-    for (int l = 1; l < Lmax; l++) {
+    for (int l = 1; l < Lpmax; l++) {
         std::vector<PyrJob> jobs;
         for (auto &p : pairs) {
-            if (p.g.L <= l) continue;
+            if (p.g.Lp <= l) continue;
             PyrJob j{};  // zeroed padding: job packs are compared byte for byte
             j.src_l = l == 1 ? (const void *)p.left : p.ws.pyr_l[l - 1];
             j.src_r = l == 1 ? (const void *)p.right : p.ws.pyr_r[l - 1];
@@ -364,7 +426,45 @@ void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<Launch> &l
         append(ls, K_PYR, l, 0, l == 1, f64, jobs, kp0,
                [](const PyrJob &j) { return pyr_blocks(j.wd, j.hd, j.ppt); });
     }
+    if (lrn) {
+        std::vector<NetInJob> in;
+        std::vector<GateJob> gate;
+        for (auto &p : pairs) {
+            const NetGroup &G = h->groups[p.group];
+            NetInJob j{};
+            j.L = p.ws.pyr_l[kNetLevel];
+            j.R = p.ws.pyr_r[kNetLevel];
+            j.x = G.x + (size_t)p.gindex * G.W4 * G.H4 * kNetIn;
+            j.W = G.W4; j.H = G.H4;
+            in.push_back(j);
+            GateJob q{};
+            q.net = G.out + (size_t)p.gindex * G.W4 * G.H4 * 2;
+            q.U = p.ws.U[inj];
+            q.keep = p.ws.keep;
+            q.flag = p.ws.flag;
+            q.W4 = G.W4; q.H4 = G.H4;
+            q.Wi = p.g.W[inj]; q.Hi = p.g.H[inj];
+            q.thr = h->prm.conf_threshold;
+            q.sxy = 1.f / (float)(1 << (kNetLevel - inj));
+            q.sd = -(float)(1 << (kNetLevel - inj));
+            gate.push_back(q);
+        }
+        append(ls, K_NETIN, kNetLevel, 0, false, f64, in, kp0,
+               [](const NetInJob &j) { return (j.W * j.H + kBlock - 1) / kBlock; });
+        for (const NetGroup &G : h->groups) {
+            Launch L{K_NET, kNetLevel, 0, false, f64, 0, kp0, {}};
+            NetLaunch nl{G.x, G.a[0], G.a[1], G.a[2], G.out, (int)G.pairs.size(), G.H4, G.W4, 0};
+            L.pack.resize(sizeof nl);
+            memcpy(L.pack.data(), &nl, sizeof nl);
+            ls.push_back(std::move(L));
+        }
+        append(ls, K_GATE, inj, 0, false, f64, gate, kp0,
+               [](const GateJob &j) { return (j.Wi * j.Hi + kBlock - 1) / kBlock; });
+    }
     for (int l = Lmax - 1; l >= 0; l--) {
+        const bool fallback = lrn && l >= inj;  // plain level kept only as the fallback
+        KParams kpl = kp0;
+        if (lrn && l < inj) kpl.iters = h->prm.learned_iters;
         for (int P : kSupportedPatch) {
             std::vector<LkJob> jobs;
             for (auto &p : pairs) {
@@ -382,9 +482,12 @@ void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<Launch> &l
                 j.reach = (int)std::ceil(std::max(0.f, p.dmax) / (float)(1 << l)) + 1;
                 j.rec_u = p.ws.rec_u[l]; j.rec_w = p.ws.rec_w[l];
                 j.rec_u0 = p.ws.rec_u0[l]; j.rec_st = p.ws.rec_st[l];
+                j.run_flag = fallback ? p.ws.flag : nullptr;
                 jobs.push_back(j);
             }
-            append(ls, K_LK, l, P, l == 0, f64, jobs, make_kparams(h->prm, P),
+            KParams kpp = make_kparams(h->prm, P);
+            kpp.iters = kpl.iters;
+            append(ls, K_LK, l, P, l == 0, f64, jobs, kpp,
                    [P](const LkJob &j) { return j.ny * lk_bpr(P, j.nx); });
         }
         std::vector<DenseJob> jobs;
@@ -408,6 +511,8 @@ void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<Launch> &l
             j.U = l == 0 ? nullptr : p.ws.U[l];
             j.out = l == 0 ? p.disp : nullptr;
             j.out_pitch = p.dpitch;
+            j.run_flag = fallback ? p.ws.flag : nullptr;
+            j.keep = (lrn && l == inj) ? p.ws.keep : nullptr;
             j.ppt = 1;
             jobs.push_back(j);
         }
@@ -420,6 +525,7 @@ void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<Launch> &l
 static_assert(sizeof(JobPack<PyrJob>) + sizeof(KParams) <= 4000, "pyramid job pack too large");
 static_assert(sizeof(JobPack<LkJob>) + sizeof(KParams) <= 4000, "LK job pack too large");
 static_assert(sizeof(JobPack<DenseJob>) + sizeof(KParams) <= 4000, "densify job pack too large");
+static_assert(sizeof(JobPack<NetInJob>) <= 4000 && sizeof(JobPack<GateJob>) <= 4000, "job pack too large");
 
 template <typename Job>
 const JobPack<Job> &pack_of(const Launch &L) {
@@ -434,8 +540,21 @@ void launch_lk(const Launch &L, hipStream_t s) {
 }
 
 template <typename T>
-void launch_one(const Launch &L, hipStream_t s) {
+void launch_one(bdis_t *h, const Launch &L, hipStream_t s) {
     switch (L.kind) {
+    case K_NETIN:
+        hipLaunchKernelGGL(k_net_input<T>, dim3(L.blocks), dim3(kBlock), 0, s, pack_of<NetInJob>(L));
+        break;
+    case K_NET: {
+        NetLaunch nl;
+        memcpy(&nl, L.pack.data(), sizeof nl);
+        uint16_t *acts[4] = {nl.x, nl.a1, nl.a2, nl.a3};
+        (void)bdisnet::forward_internal(h->net, nl.x, nl.n, nl.H, nl.W, nl.out, acts, s);
+        break;
+    }
+    case K_GATE:
+        hipLaunchKernelGGL(k_gate<T>, dim3(L.blocks), dim3(kBlock), 0, s, pack_of<GateJob>(L));
+        break;
     case K_PYR: {
         const JobPack<PyrJob> &pk = pack_of<PyrJob>(L);
         if (L.u8) hipLaunchKernelGGL((k_pyr<T, true>), dim3(L.blocks), dim3(kBlock), 0, s, pk, L.kp);
@@ -467,7 +586,10 @@ std::string launch_name(const Launch &L) {
     switch (L.kind) {
     case K_PYR: snprintf(buf, sizeof buf, "pyr_%s_l%d", t, L.level); break;
     case K_LK: snprintf(buf, sizeof buf, "lk_%s_p%d_l%d", t, L.patch, L.level); break;
-    default: snprintf(buf, sizeof buf, "dense_%s_l%d", t, L.level); break;
+    case K_DENSE: snprintf(buf, sizeof buf, "dense_%s_l%d", t, L.level); break;
+    case K_NETIN: snprintf(buf, sizeof buf, "netin_%s", t); break;
+    case K_NET: snprintf(buf, sizeof buf, "net_forward"); break;
+    default: snprintf(buf, sizeof buf, "gate_%s", t); break;
     }
     return buf;
 }
@@ -493,8 +615,8 @@ void launch_all(bdis_t *h, const std::vector<Launch> &ls, hipStream_t s) {
             b = take_event(h);
             if (a && b) (void)hipEventRecord(a, s);
         }
-        if (L.f64) launch_one<double>(L, s);
-        else launch_one<float>(L, s);
+        if (L.f64) launch_one<double>(h, L, s);
+        else launch_one<float>(h, L, s);
         if (h->profiling && a && b) {
             (void)hipEventRecord(b, s);
             h->pending.push_back({launch_name(L), a, b});
@@ -777,20 +899,69 @@ bdis_status run_level_graph(bdis_t *h, const std::vector<Launch> &ls, hipStream_
 bdis_status run(bdis_t *h, std::vector<PairIn> &pairs, hipStream_t s, int mode = 1) {
     DeviceGuard dg(h->device);
     const size_t esz = esize(h->prm);
+    const bool lrn = learned(h);
+    const int inj = lrn ? h->prm.learned_fine_levels : 0;
+    if (lrn && !h->net) { set_err(h->err, "init = learned but no network is attached (bdis_set_net)"); return BDIS_E_STATE; }
+    if (lrn && mode == 2) { set_err(h->err, "the persistent batch kernel does not run the learned init"); return BDIS_E_UNSUPPORTED; }
     size_t total = 0;
     for (auto &p : pairs) {
-        if (!make_geo(p.W, p.H, p.patch, p.stride, requested_levels(h->prm, p.dmax), p.g)) {
+        if (!make_geo(p.W, p.H, p.patch, p.stride, requested_levels(h->prm, p.dmax), p.g, lrn ? kNetLevel + 1 : 0)) {
             set_err(h->err, "image %dx%d smaller than patch %d", p.W, p.H, p.patch);
             return BDIS_E_INVALID_ARG;
         }
-        total += align_up(pair_ws_bytes(p.g, esz));
+        if (lrn && (p.g.L <= inj || p.g.Lp <= kNetLevel || p.g.W[kNetLevel] < 2 || p.g.H[kNetLevel] < 2)) {
+            set_err(h->err, "image %dx%d too small for the learned init (needs %d LK levels and a 1/16 level)",
+                    p.W, p.H, inj + 1);
+            return BDIS_E_INVALID_ARG;
+        }
+        total += align_up(pair_ws_bytes(p.g, esz, inj));
     }
-    bdis_status st = ensure_ws(h, total);
+    // network batches: pairs grouped by their 1/16-level size
+    h->groups.clear();
+    size_t net_bytes = 0;
+    if (lrn) {
+        const int C = bdisnet::channels(h->net);
+        for (size_t i = 0; i < pairs.size(); i++) {
+            PairIn &p = pairs[i];
+            int gi = -1;
+            for (size_t k = 0; k < h->groups.size(); k++)
+                if (h->groups[k].W4 == p.g.W[kNetLevel] && h->groups[k].H4 == p.g.H[kNetLevel]) gi = (int)k;
+            if (gi < 0) {
+                NetGroup G;
+                G.W4 = p.g.W[kNetLevel];
+                G.H4 = p.g.H[kNetLevel];
+                h->groups.push_back(G);
+                gi = (int)h->groups.size() - 1;
+            }
+            p.group = gi;
+            p.gindex = (int)h->groups[gi].pairs.size();
+            h->groups[gi].pairs.push_back((int)i);
+        }
+        for (const NetGroup &G : h->groups) {
+            size_t px = (size_t)G.pairs.size() * G.W4 * G.H4;
+            net_bytes += align_up(px * kNetIn * 2) + 3 * align_up(px * C * 2) + align_up(px * 2 * 4);
+        }
+    }
+    bdis_status st = ensure_ws(h, total + net_bytes);
     if (st != BDIS_OK) return st;
     size_t off = 0;
     for (auto &p : pairs) {
-        carve(h->ws + off, p.g, esz, p.ws);
-        off += align_up(pair_ws_bytes(p.g, esz));
+        carve(h->ws + off, p.g, esz, p.ws, inj);
+        off += align_up(pair_ws_bytes(p.g, esz, inj));
+    }
+    if (lrn) {
+        const int C = bdisnet::channels(h->net);
+        for (NetGroup &G : h->groups) {
+            size_t px = (size_t)G.pairs.size() * G.W4 * G.H4;
+            G.x = (uint16_t *)(h->ws + off);
+            off += align_up(px * kNetIn * 2);
+            for (int a = 0; a < 3; a++) {
+                G.a[a] = (uint16_t *)(h->ws + off);
+                off += align_up(px * C * 2);
+            }
+            G.out = (float *)(h->ws + off);
+            off += align_up(px * 2 * 4);
+        }
     }
     if (mode == 2) return run_persistent(h, pairs, s);
     std::vector<Launch> ls;
@@ -986,6 +1157,87 @@ bdis_status bdis_batch_error(bdis_t *h, int32_t *flag) {
     DeviceGuard dg(h->device);
     HIPCHK(h, hipStreamSynchronize(h->last_batch_stream));
     if (h->batch_mode == 2 && h->p_err) HIPCHK(h, hipMemcpy(flag, h->p_err, sizeof(int), hipMemcpyDeviceToHost));
+    return BDIS_OK;
+}
+
+bdis_status bdis_set_net(bdis_t *h, bdisnet_t *net) {
+    if (!h) { set_err(g_thread_err, "handle is NULL"); return BDIS_E_INVALID_ARG; }
+    if (net && bdisnet::device_of(net) != h->device) { set_err(h->err, "network is on another device"); return BDIS_E_INVALID_ARG; }
+    h->net = net;
+    h->lv_key.clear();
+    return BDIS_OK;
+}
+
+bdis_status bdis_net_input(bdis_t *h, const bdis_pair *pairs, int32_t n, uint16_t *x, void *stream) {
+    if (!h) { set_err(g_thread_err, "handle is NULL"); return BDIS_E_INVALID_ARG; }
+    if (!pairs || n < 1 || n > 4096 || !x) { set_err(h->err, "need 1 <= n <= 4096 pairs and an output"); return BDIS_E_INVALID_ARG; }
+    std::vector<PairIn> ps(n);
+    for (int i = 0; i < n; i++) {
+        const bdis_pair &q = pairs[i];
+        PairIn &p = ps[i];
+        p.patch = h->prm.patch;
+        p.stride = h->prm.stride;
+        bdis_status st = check_pair(h, q.left, q.right, q.width, q.height, q.pitch_bytes, q.disp ? q.disp : (float *)x,
+                                    q.disp ? q.disp_pitch_elems : q.width, p.patch);
+        if (st != BDIS_OK) return st;
+        p.left = q.left; p.right = q.right; p.disp = q.disp;
+        p.W = q.width; p.H = q.height; p.pitch = q.pitch_bytes; p.dpitch = q.disp_pitch_elems;
+        p.dmax = q.max_disparity > 0.f ? q.max_disparity : h->prm.max_disparity;
+        make_geo(p.W, p.H, p.patch, p.stride, 1, p.g, kNetLevel + 1);
+        if (p.g.Lp <= kNetLevel || p.g.W[kNetLevel] < 2 || p.g.H[kNetLevel] < 2) {
+            set_err(h->err, "pair %d too small for a 1/16 level", i);
+            return BDIS_E_INVALID_ARG;
+        }
+        if (p.g.W[kNetLevel] != ps[0].g.W[kNetLevel] || p.g.H[kNetLevel] != ps[0].g.H[kNetLevel]) {
+            set_err(h->err, "pair %d: 1/16 level size differs from pair 0", i);
+            return BDIS_E_INVALID_ARG;
+        }
+    }
+    DeviceGuard dg(h->device);
+    const size_t esz = esize(h->prm);
+    size_t total = 0;
+    for (auto &p : ps) total += align_up(pair_ws_bytes(p.g, esz));
+    bdis_status st = ensure_ws(h, total);
+    if (st != BDIS_OK) return st;
+    size_t off = 0;
+    for (auto &p : ps) {
+        carve(h->ws + off, p.g, esz, p.ws);
+        off += align_up(pair_ws_bytes(p.g, esz));
+    }
+    const bool f64 = h->prm.precision == 0;
+    KParams kp0 = make_kparams(h->prm, h->prm.patch);
+    std::vector<Launch> ls;
+    for (int l = 1; l <= kNetLevel; l++) {
+        std::vector<PyrJob> jobs;
+        for (auto &p : ps) {
+            PyrJob j{};
+            j.src_l = l == 1 ? (const void *)p.left : p.ws.pyr_l[l - 1];
+            j.src_r = l == 1 ? (const void *)p.right : p.ws.pyr_r[l - 1];
+            j.src_pitch = l == 1 ? p.pitch : p.g.W[l - 1];
+            j.ws = p.g.W[l - 1]; j.hs = p.g.H[l - 1];
+            j.dst_l = p.ws.pyr_l[l]; j.dst_r = p.ws.pyr_r[l];
+            j.wd = p.g.W[l]; j.hd = p.g.H[l];
+            j.ppt = 1;
+            jobs.push_back(j);
+        }
+        append(ls, K_PYR, l, 0, l == 1, f64, jobs, kp0,
+               [](const PyrJob &j) { return pyr_blocks(j.wd, j.hd, j.ppt); });
+    }
+    std::vector<NetInJob> in;
+    const size_t per = (size_t)ps[0].g.W[kNetLevel] * ps[0].g.H[kNetLevel] * kNetIn;
+    for (int i = 0; i < n; i++) {
+        NetInJob j{};
+        j.L = ps[i].ws.pyr_l[kNetLevel];
+        j.R = ps[i].ws.pyr_r[kNetLevel];
+        j.x = x + per * i;
+        j.W = ps[i].g.W[kNetLevel];
+        j.H = ps[i].g.H[kNetLevel];
+        in.push_back(j);
+    }
+    append(ls, K_NETIN, kNetLevel, 0, false, f64, in, kp0,
+           [](const NetInJob &j) { return (j.W * j.H + kBlock - 1) / kBlock; });
+    launch_all(h, ls, (hipStream_t)stream);
+    HIPCHK(h, hipGetLastError());
     return BDIS_OK;
 }
 

@@ -492,3 +492,19 @@ def test_e2e_invalid_arguments(ref):
         ref.compute(a, a, ref.Params(patch=8))
     with pytest.raises(ValueError):
         ref.compute(np.zeros((20, 20), np.uint8), np.zeros((20, 20), np.uint8), ref.Params(window=4))
+
+
+def test_compute_init_with_own_field_is_compute(ref):
+    """Injecting the plain pipeline's own level-2 field and running levels
+    1, 0 with the same iterations reproduces the plain result exactly."""
+    P = synth.make_pair(160, 120, 16, seed=4)
+    prm = ref.Params(levels=4, iters=8)
+    d, tr = ref.compute(P.left, P.right, prm, trace=True)
+    d2 = ref.compute_init(P.left, P.right, prm, 2, tr[2]["field"], 8)
+    np.testing.assert_array_equal(np.isnan(d), np.isnan(d2))
+    np.testing.assert_array_equal(d[np.isfinite(d)], d2[np.isfinite(d2)])
+    # a perfect constant proposal on an integer shift needs no coarse levels
+    S = synth.integer_shift_pair(160, 120, 6, seed=3)
+    w2, h2 = ref.level_dims(160, 120, 2)
+    d3 = ref.compute_init(S.left, S.right, prm, 2, np.full((h2, w2), -6 / 4.0), 8)
+    assert np.nanmax(np.abs(d3[8:-8, 14:-8] - 6)) < 1e-3
