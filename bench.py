@@ -1,17 +1,22 @@
 """Throughput benchmark of the BDIS stereo hot path on one MI355X.
 
-A step is one bdis_compute call: the whole path (pyramid, per-level LK +
-posterior, densification, coarse to fine) over one synthetic 640x480 pair
-whose images already sit in device memory.  Prints one JSON line with the
-disparity throughput, the roofline position of the dominant kernel (timed
-with HIP events on the launch stream) and the FP64 CPU oracle timed on the
-host's cores as a baseline.
+Headline (`value`): a step is one bdis_compute call -- the whole path
+(pyramid, per-level LK + posterior, densification, coarse to fine) over one
+synthetic 640x480 pair whose images already sit in device memory.  The one
+JSON line also carries:
+  roofline       the dominant kernel, timed with HIP events on its launch
+                 stream over a profiled pass of the same steps;
+  cpu_baseline   the FP64 CPU oracle on the host's cores (a baseline only);
+  batched        64 mixed-size pairs per call, patch/stride autotuned;
+  learned_640    64 held-out 640x480 pairs per call, plain vs learned init;
+  learned_mixed  32 1920x1080 + 32 640x480 pairs per call, plain vs learned.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -27,6 +32,8 @@ PAPER_MPXS = 10 * 640 * 480 / 1e6  # 10 Hz at 640x480, one i5-9400 core (Sec. 3.
 PEAK_FP64_VECTOR = 78.6e12
 PEAK_FP32_VECTOR = 157.3e12
 PEAK_HBM = 8.0e12
+
+WEIGHTS = os.path.join(ROOT, "paper_2106_07136_amd", "weights", "proposal_c{C}.npz")
 
 
 def log(msg):
@@ -74,64 +81,116 @@ def cpu_baseline(pair, oparams, budget_s=20.0):
                       f"{n * t1:.1f} s of CPU work; single-thread {W * H / t1 / 1e6:.3f} Mpixel/s"}
 
 
-def batched_leg(batch, calib, steps, warmup, precision):
-    """Mixed batch of 64 pairs in one persistent launch, autotuned first."""
-    import numpy as np
+def timed(fn, steps, warmup):
+    """Mean ms per call of fn() over `steps` calls after `warmup`; torch
+    events on the current stream, synchronised on both sides."""
     import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
 
-    from paper_2106_07136_amd import autotune, bdis
+
+def accuracy(outs, pairs):
+    """Mean end-point error and >3 px outlier rate over the pixels that are
+    estimated and visible in the right image; coverage of the visible ones."""
+    import numpy as np
+    epe, bad, cov = [], [], []
+    for o, p in zip(outs, pairs):
+        d = o.cpu().numpy() if hasattr(o, "cpu") else o
+        m = np.isfinite(d) & p.valid
+        err = np.abs(d[m] - p.disp[m])
+        epe.append(float(err.mean()))
+        bad.append(float((err > 3).mean()))
+        cov.append(float(m.sum() / p.valid.sum()))
+    return {"epe_px": float(np.mean(epe)), "outliers_3px": float(np.mean(bad)),
+            "coverage": float(np.mean(cov))}
+
+
+def _batch_io(pairs):
+    import torch
     dev = torch.device("cuda:0")
+    L = [torch.from_numpy(p.left).to(dev) for p in pairs]
+    R = [torch.from_numpy(p.right).to(dev) for p in pairs]
+    O = [torch.empty(p.left.shape, dtype=torch.float32, device=dev) for p in pairs]
+    return L, R, O, [p.d_max for p in pairs]
+
+
+def batched_leg(batch, calib, steps, warmup, precision):
+    """Mixed batch of 64 pairs per call, patch/stride autotuned first; the
+    three batch executions are timed at the paper's patch 8 / stride 4."""
+    from paper_2106_07136_amd import autotune, bdis
     base = bdis.Params(levels=0, iters=12, precision=precision)
     classes = [(320, [p for p in calib if p.left.shape[1] == 320]),
                (640, [p for p in calib if p.left.shape[1] == 640]),
                (100000, [p for p in calib if p.left.shape[1] == 1280])]
     log("bench: autotuning patch/stride per size class")
     tuned = autotune.tune(base, classes, reps=3, log=log)
-    L = [torch.from_numpy(p.left).to(dev) for p in batch]
-    R = [torch.from_numpy(p.right).to(dev) for p in batch]
-    O = [torch.empty(p.left.shape, dtype=torch.float32, device=dev) for p in batch]
-    dm = [p.d_max for p in batch]
+    L, R, O, dm = _batch_io(batch)
     mpx = sum(p.left.size for p in batch) / 1e6
-
-    def timed(h):
-        for _ in range(warmup):
-            h.compute_batch(L, R, O, max_disparity=dm)
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(steps):
-            h.compute_batch(L, R, O, max_disparity=dm)
-        e1.record()
-        torch.cuda.synchronize()
-        assert h.batch_error() == 0, "persistent batch reported a dependency timeout"
-        return e0.elapsed_time(e1) / steps
-
-    h = bdis.Bdis(bdis.Params(levels=0, iters=12, precision=precision, autotune=1))
+    h = bdis.Bdis(dataclasses.replace(base, autotune=1))
     autotune.apply(h, tuned)
-    ms = timed(h)
-    epe, cov = [], []
-    for o, p in zip(O, batch):
-        d = o.cpu().numpy()
-        m = np.isfinite(d) & p.valid
-        epe.append(float(np.abs(d[m] - p.disp[m]).mean()))
-        cov.append(float(m.sum() / p.valid.sum()))
+    ms = timed(lambda: h.compute_batch(L, R, O, max_disparity=dm), steps, warmup)
+    assert h.batch_error() == 0, "persistent batch reported a dependency timeout"
+    acc = accuracy(O, batch)
     h0 = bdis.Bdis(base)
     modes = {}
     for m in (0, 1, 2):
         h0.set_batch_mode(m)
-        modes[m] = timed(h0)
+        modes[m] = timed(lambda: h0.compute_batch(L, R, O, max_disparity=dm), steps, warmup)
+        assert h0.batch_error() == 0, "persistent batch reported a dependency timeout"
     log(f"bench: batched {mpx:.2f} Mpx: tuned {ms:.3f} ms; patch 8 stride 4: level graph {modes[0]:.3f} ms, "
         f"direct launches {modes[1]:.3f} ms, persistent kernel {modes[2]:.3f} ms")
-    return {"workload": "plain BDIS, 64 synthetic pairs per launch (24x320x240, 24x640x480, "
+    return {"workload": "plain BDIS, 64 synthetic pairs per call (24x320x240, 24x640x480, "
                         "16x1280x720), disparity up to 10% of the width, automatic levels, 12 iterations",
             "value": mpx / (ms / 1e3), "unit": "Mpixel/s", "ms_per_batch": ms, "mpixel_per_batch": mpx,
             "steps": steps, "tuning": tuned["table"], "batch_mode": tuned["batch_mode"],
-            "wgs_per_cu": tuned["wgs_per_cu"],
+            "wgs_per_cu": tuned["wgs_per_cu"], **acc,
             "p8s4_level_graph_mpxs": mpx / (modes[0] / 1e3),
             "p8s4_direct_launches_mpxs": mpx / (modes[1] / 1e3),
-            "p8s4_persistent_kernel_mpxs": mpx / (modes[2] / 1e3),
-            "epe_px": float(np.mean(epe)), "coverage": float(np.mean(cov))}
+            "p8s4_persistent_kernel_mpxs": mpx / (modes[2] / 1e3)}
+
+
+def learned_leg(pairs, channels, steps, warmup, precision, workload):
+    """Plain vs learned initialisation on the same batch.  The learned run
+    uses the fewest fine-level LK iterations (of 12, 8, 6, 4) whose EPE stays
+    within 2 % of the plain run's and whose coverage within 2 % of it."""
+    from paper_2106_07136_amd import bdis, net, train
+    flat, C, _ = train.load(WEIGHTS.format(C=channels))
+    pn = net.ProposalNet(C)
+    pn.set_params(flat)
+    L, R, O, dm = _batch_io(pairs)
+    mpx = sum(p.left.size for p in pairs) / 1e6
+    base = bdis.Params(levels=0, iters=12, precision=precision)
+    hp = bdis.Bdis(base)
+    ms_plain = timed(lambda: hp.compute_batch(L, R, O, max_disparity=dm), steps, warmup)
+    acc_plain = accuracy(O, pairs)
+    log(f"bench: {workload[:24]}: plain {ms_plain:.3f} ms {acc_plain}")
+    runs = {}
+    for it in (12, 8, 6, 4):
+        hl = bdis.Bdis(dataclasses.replace(base, init=1, learned_iters=it))
+        hl.set_net(pn)
+        ms = timed(lambda: hl.compute_batch(L, R, O, max_disparity=dm), steps, warmup)
+        runs[it] = (ms, accuracy(O, pairs))
+        log(f"bench: {workload[:24]}: learned, {it} fine iterations: {ms:.3f} ms {runs[it][1]}")
+        hl.close()
+    ok = [it for it, (_, a) in runs.items()
+          if a["epe_px"] <= 1.02 * acc_plain["epe_px"] and a["coverage"] >= 0.98 * acc_plain["coverage"]]
+    pick = min(ok) if ok else 12
+    ms_l, acc_l = runs[pick]
+    return {"workload": workload, "unit": "Mpixel/s", "mpixel_per_batch": mpx, "steps": steps,
+            "plain": {"value": mpx / (ms_plain / 1e3), "ms_per_batch": ms_plain, **acc_plain},
+            "learned": {"value": mpx / (ms_l / 1e3), "ms_per_batch": ms_l, "learned_iters": pick,
+                        "channels": C, **acc_l},
+            "speedup": ms_plain / ms_l,
+            "sweep": {str(k): {"ms_per_batch": v[0], **v[1]} for k, v in runs.items()}}
 
 
 def main():
@@ -143,14 +202,25 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-pair batched leg")
     ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run 5 device-to-device copies of MIB MiB (scale for HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); stereo pairs are "
               "independent, so several GPUs would each run their own share", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
+
+    if args.copy_calibration:
+        n = args.copy_calibration << 20
+        src_t = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+        dst_t = torch.empty_like(src_t)
+        for _ in range(5):
+            dst_t.copy_(src_t)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "copies": 5}), flush=True)
+        return
 
     from paper_2106_07136_amd import bdis, synth
 
@@ -158,13 +228,17 @@ def main():
     LEVELS, PATCH, STRIDE, ITERS = 5, 8, 4, 12
     log(f"bench: generating {W}x{H} pair seed {SEED}")
     pair = synth.make_pair(W, H, DMAX, SEED)
-    batch = calib = None
+    batch = calib = held = mixed = None
     if not args.no_batch:
         log("bench: generating the 64-pair mixed batch and 24 calibration pairs")
         batch = synth.make_pairs(synth.mixed_batch_spec(3000))
         calib = synth.make_pairs([(Wc, Hc, 0.1 * Wc, 3900 + 10 * i + j)
                                   for i, (Wc, Hc) in enumerate(((320, 240), (640, 480), (1280, 720)))
                                   for j in range(8)])
+        log("bench: generating 64 held-out 640x480 pairs and 32+32 mixed 1920x1080/640x480 pairs")
+        held = synth.make_pairs([(640, 480, 64.0, 90000 + i) for i in range(64)])
+        mixed = synth.make_pairs([(1920, 1080, 192.0, 50000 + i) for i in range(32)] +
+                                 [(640, 480, 64.0, 51000 + i) for i in range(32)])
     dev = torch.device("cuda:0")
     L = torch.from_numpy(pair.left).to(dev)
     R = torch.from_numpy(pair.right).to(dev)
@@ -191,10 +265,8 @@ def main():
     ms = e0.elapsed_time(e1)
     ms_step = ms / args.steps
     value = W * H * args.steps / (ms / 1e3) / 1e6
-    d = out.cpu().numpy()
-    finite = np.isfinite(d)
-    epe = float(np.abs(d - pair.disp)[finite].mean())
-    log(f"bench: {ms_step * 1e3:.1f} us/step, {value:.1f} Mpixel/s, coverage {finite.mean():.3f}, EPE {epe:.3f}")
+    acc = accuracy([out], [pair])
+    log(f"bench: {ms_step * 1e3:.1f} us/step, {value:.1f} Mpixel/s, {acc}")
 
     # per-kernel durations from HIP events on the launch stream
     log("bench: profiled pass")
@@ -230,12 +302,20 @@ def main():
                                "5 levels, patch 8, stride 4, 12 LK iterations)",
                    "width": W, "height": H, "levels": LEVELS, "patch": PATCH, "stride": STRIDE,
                    "iters": ITERS, "seed": SEED, "patches": info["patches"]},
-        "accuracy": {"epe_px": epe, "coverage": float(finite.mean())},
+        "accuracy": acc,
         "roofline": roof,
         "kernels": kernels,
     }
     if batch is not None:
         res["batched"] = batched_leg(batch, calib, args.batch_steps, 2, args.precision)
+        res["learned_640"] = learned_leg(
+            held, 32, args.batch_steps, 2, args.precision,
+            "64 held-out 640x480 pairs per call (seeds 90000-90063, disparity 0-64 px), plain vs learned "
+            "init (32-channel proposal net, plain fallback where confidence < 0.5)")
+        res["learned_mixed"] = learned_leg(
+            mixed, 48, args.batch_steps, 2, args.precision,
+            "32x1920x1080 (seeds 50000-50031, disparity 0-192 px) + 32x640x480 (seeds 51000-51031) pairs "
+            "per call, plain vs learned init (48-channel proposal net)")
     if not args.no_cpu:
         import oracle
         log("bench: CPU oracle baseline")
