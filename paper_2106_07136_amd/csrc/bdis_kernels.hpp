@@ -142,6 +142,18 @@ __device__ __forceinline__ int find_job(const JobPack<Job> &pk, int b) {
     return lo;
 }
 
+// Workgroups of a launch are dealt to the chip's eight XCDs in turn (XCD =
+// block id mod 8), and each XCD has its own L2.  Renumbering the blocks so
+// that every XCD gets one contiguous range of tiles keeps the rows that
+// neighbouring tiles share (filter halos, the patch records a pixel gathers)
+// inside one L2 instead of fetching them from HBM once per XCD.  Bijective on
+// [0, n) for any n.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_block(int bid, int n) {
+    const int q = n / kXcds, r = n % kXcds, x = bid % kXcds, k = bid / kXcds;
+    return x * q + (x < r ? x : r) + k;
+}
+
 __device__ __forceinline__ int reflect101(int i, int n) {
     if (n == 1) return 0;
     while (i < 0 || i >= n) {
@@ -184,9 +196,11 @@ constexpr int kDppXor2 = 0x4E;    // quad_perm [2, 3, 0, 1]
 constexpr int kDppHalfMirror = 0x141;
 constexpr int kDppMirror = 0x140;
 
+// (every pattern stays inside its row and all lanes are active, so no lane
+// reads out of bounds: bound_ctrl only spares the copy of an old value)
 template <int CTRL>
 __device__ __forceinline__ int dpp_i(int v) {
-    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true);
 }
 template <int CTRL>
 __device__ __forceinline__ float dpp_v(float v) {
@@ -322,8 +336,9 @@ __device__ __forceinline__ void pyr_block(const PyrJob &J, int lb, const KParams
 
 template <typename T, bool U8>
 __global__ __launch_bounds__(kBlock) void k_pyr(const JobPack<PyrJob> pk, KParams kp) {
-    const PyrJob &J = pk.j[find_job(pk, (int)blockIdx.x)];
-    pyr_block<T, U8>(J, (int)blockIdx.x - J.block0, kp);
+    const int bid = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const PyrJob &J = pk.j[find_job(pk, bid)];
+    pyr_block<T, U8>(J, bid - J.block0, kp);
 }
 
 // ---------------------------------------------------------------- LK + posterior
@@ -384,19 +399,23 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
     const int y = y0 + (row_on ? r : 0);
     const size_t row0 = (size_t)y * J.pitch;
 
-    // template row and gradient (independent of the shift: issued first)
+    // template row and gradient (independent of the shift: issued first).
+    // One read of the P + 2 columns x0 - 1 .. x0 + P, clamped to the row,
+    // serves the template and both neighbours of the central difference.
     T Tv[P], Jg[P];
     uint32_t vmask = 0;
+    {
+        T raw[P + 2];
+        bool rv[P + 2];
 #pragma unroll
-    for (int c = 0; c < P; c++) {
-        int x = x0 + c;
-        bool v;
-        Tv[c] = pix<T, U8>(J.L, row0 + x, kp, v);
-        T gp = pixv<T, U8>(J.L, row0 + min(x + 1, W - 1));
-        T gm = pixv<T, U8>(J.L, row0 + max(x - 1, 0));
-        Jg[c] = T(0.5) * (gp - gm);
-        v = v && row_on;
-        vmask |= (uint32_t)v << c;
+        for (int j = 0; j < P + 2; j++)
+            raw[j] = pix<T, U8>(J.L, row0 + min(max(x0 - 1 + j, 0), W - 1), kp, rv[j]);
+#pragma unroll
+        for (int c = 0; c < P; c++) {
+            Tv[c] = raw[c + 1];
+            Jg[c] = T(0.5) * (raw[c + 2] - raw[c]);
+            vmask |= (uint32_t)(rv[c + 1] && row_on) << c;
+        }
     }
 
     // initial shift: twice the coarse field at the patch centre (Sec. 2.1)
@@ -520,19 +539,55 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
     } else {
         T step = 0;
         const T invH = T(1) / Hs;
+        // sum_c J_c T_c of this lane's row: the template part of sum J e
+        T jt0 = 0, jt1 = 0;
+#pragma unroll
+        for (int c = 0; c < P; c += 2) {
+            jt0 += Jg[c] * Tv[c];
+            if (c + 1 < P) jt1 += Jg[c + 1] * Tv[c + 1];
+        }
+        const T jt = jt0 + jt1;
         for (int t = 0; t < kp.iters; t++) {
             T uc = fmin(fmax(u, ulo), uhi);
             T ui = floor(uc), uf = uc - ui;
-            T I[P];
-            sample(x0 + (int)ui, uf, I);
-            // two interleaved partial sums shorten the dependent chain
-            T s0 = 0, s1 = 0;
+            const int xi0 = x0 + (int)ui;
+            T s;
+            if (xi0 >= col_lo && xi0 + P <= col_hi) {
+                // staged and inside the row, so every sample interpolates
+                // with the same f = uf:  sum_c J_c ((1 - f) R_m+c + f R_m+c+1)
+                // = A + f (B - A) with A, B the dot products of J with the
+                // taps at m + c and m + c + 1
+                const int base = rbase + xi0;
+                T v[P + 1];
 #pragma unroll
-            for (int c = 0; c < P; c += 2) {
-                s0 += Jg[c] * (I[c] - Tv[c]);
-                if (c + 1 < P) s1 += Jg[c + 1] * (I[c + 1] - Tv[c + 1]);
+                for (int c = 0; c <= P; c++) {
+                    v[c] = Rs[base + c];
+                    if constexpr (!U8) v[c] = fabs(v[c]);
+                }
+                T a0 = 0, a1 = 0, b0 = 0, b1 = 0;
+#pragma unroll
+                for (int c = 0; c < P; c += 2) {
+                    a0 += Jg[c] * v[c];
+                    b0 += Jg[c] * v[c + 1];
+                    if (c + 1 < P) {
+                        a1 += Jg[c + 1] * v[c + 1];
+                        b1 += Jg[c + 1] * v[c + 2];
+                    }
+                }
+                const T A = a0 + a1, B = b0 + b1;
+                s = A + uf * (B - A) - jt;
+            } else {
+                T I[P];
+                sample(xi0, uf, I);
+                T s0 = 0, s1 = 0;
+#pragma unroll
+                for (int c = 0; c < P; c += 2) {
+                    s0 += Jg[c] * (I[c] - Tv[c]);
+                    if (c + 1 < P) s1 += Jg[c + 1] * (I[c + 1] - Tv[c + 1]);
+                }
+                s = s0 + s1;
             }
-            T b = seg_sum<SEG>(s0 + s1);
+            const T b = seg_sum<SEG>(s);
             step = b * invH;
             u = u - step;
         }
@@ -632,6 +687,10 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
 template <typename T, int P, bool U8>
 __global__ __launch_bounds__(kBlock) void k_lk(const JobPack<LkJob> pk, KParams kp) {
     __shared__ T Rs[lk_lds_bytes<T, P>() / sizeof(T)];
+    // Blocks in launch order (no XCD renumbering): at level 0 the many
+    // blocks that stage the same few image lines contend for one L2 when
+    // neighbouring patch rows share an XCD; spread over the XCDs they run
+    // faster although more lines come from beyond the L2.
     const LkJob &J = pk.j[find_job(pk, (int)blockIdx.x)];
     lk_block<T, P, U8>(J, (int)blockIdx.x - J.block0, kp, Rs);
 }
@@ -712,8 +771,9 @@ __device__ __forceinline__ void dense_block(const DenseJob &J, int lb, const KPa
 
 template <typename T, bool U8>
 __global__ __launch_bounds__(kBlock) void k_dense(const JobPack<DenseJob> pk, KParams kp) {
-    const DenseJob &J = pk.j[find_job(pk, (int)blockIdx.x)];
-    dense_block<T, U8>(J, (int)blockIdx.x - J.block0, kp);
+    const int bid = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const DenseJob &J = pk.j[find_job(pk, bid)];
+    dense_block<T, U8>(J, bid - J.block0, kp);
 }
 
 // ---------------------------------------------------------------- learned init
