@@ -32,6 +32,7 @@ PAPER_MPXS = 10 * 640 * 480 / 1e6  # 10 Hz at 640x480, one i5-9400 core (Sec. 3.
 PEAK_FP64_VECTOR = 78.6e12
 PEAK_FP32_VECTOR = 157.3e12
 PEAK_HBM = 8.0e12
+PEAK_BF16_MFMA = 2.5e15
 
 WEIGHTS = os.path.join(ROOT, "paper_2106_07136_amd", "weights", "proposal_c{C}.npz")
 
@@ -95,6 +96,13 @@ def cpu_baseline(pair, oparams, budget_s=20.0):
     return {"value": n * W * H / wall / 1e6, "unit": "Mpixel/s", "cores": cores, "kind": "oracle",
             "sample": f"{n} runs of the 640x480 pair (seed 2) on {cores} threads, "
                       f"{n * t1:.1f} s of CPU work; single-thread {W * H / t1 / 1e6:.3f} Mpixel/s"}
+
+
+def net_flops(channels, pixels):
+    """FLOPs of one proposal-net forward over `pixels` 1/16-level pixels:
+    four 3x3 convolutions 16 -> C -> C -> C -> 2, two per multiply-add."""
+    C = channels
+    return 2 * 9 * (16 * C + C * C + C * C + C * 2) * pixels
 
 
 def timed(fn, steps, warmup):
@@ -201,11 +209,30 @@ def learned_leg(pairs, channels, steps, warmup, precision, workload):
           if a["epe_px"] <= 1.02 * acc_plain["epe_px"] and a["coverage"] >= 0.98 * acc_plain["coverage"]]
     pick = min(ok) if ok else 12
     ms_l, acc_l = runs[pick]
+    # proposal-net forward: MFMA utilisation from per-launch HIP events
+    hl = bdis.Bdis(dataclasses.replace(base, init=1, learned_iters=pick))
+    hl.set_net(pn)
+    hl.set_batch_mode(1)  # direct launches: events around each one
+    hl.set_profiling(True)
+    for _ in range(steps):
+        hl.compute_batch(L, R, O, max_disparity=dm)
+    prof = hl.profile()
+    hl.close()
+    n_net, t_net = prof["net_forward"]
+    px4 = sum(((p.left.shape[0] + 15) // 16) * ((p.left.shape[1] + 15) // 16) for p in pairs)
+    net_fl = net_flops(C, px4)
+    net_s = t_net / 1e3 / steps
+    mfma = {"flops_per_batch": net_fl, "us_per_batch": net_s * 1e6, "launches_per_batch": n_net // steps,
+            "achieved_tflops": net_fl / net_s / 1e12, "peak_tflops": PEAK_BF16_MFMA / 1e12,
+            "frac": net_fl / net_s / PEAK_BF16_MFMA,
+            "share_of_batch": net_s * 1e3 / ms_l}
+    log(f"bench: {workload[:24]}: net forward {net_s * 1e6:.1f} us per batch, "
+        f"{mfma['achieved_tflops']:.1f} TFLOP/s ({100 * mfma['frac']:.2f} % of BF16 MFMA peak)")
     return {"workload": workload, "unit": "Mpixel/s", "mpixel_per_batch": mpx, "steps": steps,
             "plain": {"value": mpx / (ms_plain / 1e3), "ms_per_batch": ms_plain, **acc_plain},
             "learned": {"value": mpx / (ms_l / 1e3), "ms_per_batch": ms_l, "learned_iters": pick,
                         "channels": C, **acc_l},
-            "speedup": ms_plain / ms_l,
+            "speedup": ms_plain / ms_l, "net_mfma": mfma,
             "sweep": {str(k): {"ms_per_batch": v[0], **v[1]} for k, v in runs.items()}}
 
 

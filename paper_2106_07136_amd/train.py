@@ -56,11 +56,17 @@ def targets_from_disparity(d, factor=16, min_frac=0.5):
 
 def build_dataset(sizes, workers, chunk):
     """sizes: list of (W, H, d_max, n, seed0).  Generates the pairs of every
-    size and returns one (X, T, V) triple of GPU tensors per size."""
+    size and returns one (X, T, V) triple of GPU tensors per size.  With
+    workers > 1 the pairs come from a forked pool, which must be started
+    before this process touches the GPU; workers <= 1 generates in-process."""
     import multiprocessing as mp
     spec = [(W, H, d, s0 + i) for (W, H, d, n, s0) in sizes for i in range(n)]
-    pool = mp.get_context("fork").Pool(workers)  # before the GPU is touched
-    it = pool.imap(_gen, spec, chunksize=4)
+    pool = None
+    if workers > 1:
+        pool = mp.get_context("fork").Pool(workers)
+        it = pool.imap(_gen, spec, chunksize=4)
+    else:
+        it = map(_gen, spec)
     import torch
 
     from . import bdis
@@ -90,8 +96,9 @@ def build_dataset(sizes, workers, chunk):
             log(f"train: data {W}x{H} {done}/{n} pairs ({time.time() - t0:.0f} s)")
         h.close()
         data.append((X, T, V))
-    pool.close()
-    pool.join()
+    if pool is not None:
+        pool.close()
+        pool.join()
     return data
 
 
