@@ -172,6 +172,26 @@ def batched_leg(batch, calib, steps, warmup, precision):
         assert h0.batch_error() == 0, "persistent batch reported a dependency timeout"
     log(f"bench: batched {mpx:.2f} Mpx: tuned {ms:.3f} ms; patch 8 stride 4: level graph {modes[0]:.3f} ms, "
         f"direct launches {modes[1]:.3f} ms, persistent kernel {modes[2]:.3f} ms")
+    # LK + posterior launches of the batch at patch 8 / stride 4: FLOP rate
+    # at scale, from per-launch HIP events (direct launches)
+    h0.set_batch_mode(1)
+    h0.set_profiling(True)
+    for _ in range(steps):
+        h0.compute_batch(L, R, O, max_disparity=dm)
+    prof = h0.profile()
+    h0.set_profiling(False)
+    lk_s = sum(t for k, (n, t) in prof.items() if k.startswith("lk_")) / 1e3 / steps
+    all_s = sum(t for k, (n, t) in prof.items()) / 1e3 / steps
+    fl = 0
+    for p in batch:
+        info = bdis.plan(dataclasses.replace(base, max_disparity=p.d_max), p.left.shape[1], p.left.shape[0])
+        fl += lk_flops(info["patches"], base.patch, base.iters, base.window)
+    peak = PEAK_FP64_VECTOR if precision == 0 else PEAK_FP32_VECTOR
+    lk_roof = {"bound": "alu", "achieved": fl / lk_s / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+               "frac": fl / lk_s / peak, "algorithmic_flops": fl, "lk_us_per_batch": lk_s * 1e6,
+               "lk_share_of_kernel_time": lk_s / all_s}
+    log(f"bench: batched LK launches {lk_s * 1e6:.0f} us per batch, {lk_roof['achieved']:.1f} TFLOP/s "
+        f"({100 * lk_roof['frac']:.1f} % of peak), {100 * lk_s / all_s:.0f} % of kernel time")
     return {"workload": "plain BDIS, 64 synthetic pairs per call (24x320x240, 24x640x480, "
                         "16x1280x720), disparity up to 10% of the width, automatic levels, 12 iterations",
             "value": mpx / (ms / 1e3), "unit": "Mpixel/s", "ms_per_batch": ms, "mpixel_per_batch": mpx,
@@ -179,7 +199,7 @@ def batched_leg(batch, calib, steps, warmup, precision):
             "wgs_per_cu": tuned["wgs_per_cu"], **acc,
             "p8s4_level_graph_mpxs": mpx / (modes[0] / 1e3),
             "p8s4_direct_launches_mpxs": mpx / (modes[1] / 1e3),
-            "p8s4_persistent_kernel_mpxs": mpx / (modes[2] / 1e3)}
+            "p8s4_persistent_kernel_mpxs": mpx / (modes[2] / 1e3), "lk_roofline_p8s4": lk_roof}
 
 
 def learned_leg(pairs, channels, steps, warmup, precision, workload):

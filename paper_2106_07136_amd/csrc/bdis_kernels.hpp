@@ -378,8 +378,9 @@ template <typename T, int P>
 __host__ __device__ constexpr int lk_lds_bytes() { return P * (LkShape<P>::NCMAX + 1) * (int)sizeof(T); }
 
 // Block lb of an LK job; Rs is the block's LDS staging area of
-// lk_lds_bytes<T, P>() bytes.
-template <typename T, int P, bool U8>
+// lk_lds_bytes<T, P>() bytes.  WN >= kp.window bounds the window samples
+// (5 for the paper's window, 9 for any allowed one).
+template <typename T, int P, bool U8, int WN = 9>
 __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KParams &kp, T *__restrict__ Rs) {
     using S = LkShape<P>;
     constexpr int SEG = S::SEG, PPB = S::PPB, NCMAX = S::NCMAX;
@@ -603,46 +604,50 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
             // sum d^2 - (sum d)^2 / n with every window sum reduced at once
             // (in double precision the two forms agree to ~1e-13 relative)
             const int cw = (kp.window - 1) / 2;
-            constexpr int WMAX = 9;
-            T acc[2 * WMAX];
+            // WN: compile-time bound on the window count (kp.window <= WN),
+            // so that only the sums of samples that exist are reduced
+            auto window_post = [&]() -> T {
+                T acc[2 * WN];
 #pragma unroll
-            for (int i = 0; i < WMAX; i++) {
-                acc[2 * i] = 0;
-                acc[2 * i + 1] = 0;
-                if (i < kp.window) {
-                    T ud = u + (T)(i - cw) * (T)kp.window_step;
-                    T uc = fmin(fmax(ud, ulo), uhi);
-                    T ui = floor(uc), uf = uc - ui;
-                    T d[P];
-                    sample(x0 + (int)ui, uf, d);
+                for (int i = 0; i < WN; i++) {
+                    acc[2 * i] = 0;
+                    acc[2 * i + 1] = 0;
+                    if (i < kp.window) {
+                        T ud = u + (T)(i - cw) * (T)kp.window_step;
+                        T uc = fmin(fmax(ud, ulo), uhi);
+                        T ui = floor(uc), uf = uc - ui;
+                        T d[P];
+                        sample(x0 + (int)ui, uf, d);
 #pragma unroll
-                    for (int c = 0; c < P; c++) {
-                        T q = ((vmask >> c) & 1u) ? d[c] - Tv[c] : T(0);
-                        acc[2 * i] += q;
-                        acc[2 * i + 1] += q * q;
+                        for (int c = 0; c < P; c++) {
+                            T q = ((vmask >> c) & 1u) ? d[c] - Tv[c] : T(0);
+                            acc[2 * i] += q;
+                            acc[2 * i + 1] += q * q;
+                        }
                     }
                 }
-            }
-            seg_sum_n<SEG, 2 * WMAX>(acc);
-            const T ninv = T(1) / (T)n;
-            auto energy = [&](int i) -> T {
-                T E = T(0);
+                seg_sum_n<SEG, 2 * WN>(acc);
+                const T ninv = T(1) / (T)n;
+                auto energy = [&](int i) -> T {
+                    T E = T(0);
 #pragma unroll
-                for (int j = 0; j < WMAX; j++)
-                    if (j == i) E = acc[2 * j + 1] - acc[2 * j] * acc[2 * j] * ninv;
-                return E;
+                    for (int j = 0; j < WN; j++)
+                        if (j == i) E = acc[2 * j + 1] - acc[2 * j] * acc[2 * j] * ninv;
+                    return E;
+                };
+                const T Ec = energy(cw);
+                // p = 1 / sum_i exp(-(E_i - E_c) / tau): lane r of the
+                // segment evaluates the term of sample r (and r + SEG); the
+                // centre term is 1
+                T term = 0;
+#pragma unroll
+                for (int q = 0; q < (WN + SEG - 1) / SEG; q++) {
+                    int i = r + q * SEG;
+                    if (i < kp.window) term += i == cw ? T(1) : exp(-(energy(i) - Ec) / (T)kp.tau);
+                }
+                return T(1) / seg_sum<SEG>(term);
             };
-            const T Ec = energy(cw);
-            // p = 1 / sum_i exp(-(E_i - E_c) / tau): lane r of the segment
-            // evaluates the terms of samples r, r + SEG (the centre term is 1)
-            T term = 0;
-#pragma unroll
-            for (int q = 0; q < (WMAX + SEG - 1) / SEG; q++) {
-                int i = r + q * SEG;
-                if (i < kp.window) term += i == cw ? T(1) : exp(-(energy(i) - Ec) / (T)kp.tau);
-            }
-            const T z = seg_sum<SEG>(term);
-            post = T(1) / z;
+            post = window_post();
             // gamma gate at the final shift: left valid, sample inside the
             // row, both right taps valid (Sec. 3, Sec. 3.2)
             T uc = fmin(fmax(u, ulo), uhi);
@@ -652,22 +657,22 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
             int m0 = min(max(xi0, 0), W - 2);
             T v[P + 2];
             fetch(m0, v, std::integral_constant<int, P + 2>());
+            uint32_t rmask = 0;  // bit j: right tap m0 + j is valid
+#pragma unroll
+            for (int j = 0; j < P + 2; j++) {
+                bool vj;
+                if constexpr (U8) vj = v[j] >= (T)kp.vlo && v[j] <= (T)kp.vhi;
+                else vj = !signbit(v[j]);
+                rmask |= (uint32_t)vj << j;
+            }
             int cnt = 0;
 #pragma unroll
             for (int c = 0; c < P; c++) {
                 int xi = xi0 + c;
                 bool inb = xi >= 0 && (xi < W - 1 || (xi == W - 1 && uf == T(0)));
                 int m = min(max(xi, 0), W - 2) - m0;  // 0 <= m <= P
-                T a = v[m], b = v[m + 1];
-                bool va, vb;
-                if constexpr (U8) {
-                    va = a >= (T)kp.vlo && a <= (T)kp.vhi;
-                    vb = b >= (T)kp.vlo && b <= (T)kp.vhi;
-                } else {
-                    va = !signbit(a);
-                    vb = !signbit(b);
-                }
-                cnt += (((vmask >> c) & 1u) && inb && va && vb) ? 1 : 0;
+                bool vab = ((rmask >> m) & 3u) == 3u;  // taps m and m + 1
+                cnt += (((vmask >> c) & 1u) && inb && vab) ? 1 : 0;
             }
             cnt = seg_sum_i<SEG>(cnt);
             if (cnt < kp.min_valid) {
@@ -684,15 +689,18 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
     }
 }
 
-template <typename T, int P, bool U8>
-__global__ __launch_bounds__(kBlock) void k_lk(const JobPack<LkJob> pk, KParams kp) {
+// OCC: waves per SIMD the register allocation must allow.  4 is what the
+// kernel needs unconstrained; 5 trims registers (a few bytes of spill) and
+// pays off when the launch has many more blocks than the chip holds.
+template <typename T, int P, bool U8, int WN, int OCC>
+__global__ __launch_bounds__(kBlock, OCC) void k_lk(const JobPack<LkJob> pk, KParams kp) {
     __shared__ T Rs[lk_lds_bytes<T, P>() / sizeof(T)];
     // Blocks in launch order (no XCD renumbering): at level 0 the many
     // blocks that stage the same few image lines contend for one L2 when
     // neighbouring patch rows share an XCD; spread over the XCDs they run
     // faster although more lines come from beyond the L2.
     const LkJob &J = pk.j[find_job(pk, (int)blockIdx.x)];
-    lk_block<T, P, U8>(J, (int)blockIdx.x - J.block0, kp, Rs);
+    lk_block<T, P, U8, WN>(J, (int)blockIdx.x - J.block0, kp, Rs);
 }
 
 // ---------------------------------------------------------------- densify

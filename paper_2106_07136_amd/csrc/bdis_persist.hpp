@@ -59,16 +59,18 @@ __global__ __launch_bounds__(kBlock) void k_reset(int *counters, int n) {
         counters[i] = 0;
 }
 
-template <typename T, int P>
+template <typename T, int P, int WN>
 __device__ __forceinline__ void lk_task(const PJob &J, int lb, const KParams &kp, T *Rs) {
-    if (J.u8) lk_block<T, P, true>(J.lk, lb, kp, Rs);
-    else lk_block<T, P, false>(J.lk, lb, kp, Rs);
+    if (J.u8) lk_block<T, P, true, WN>(J.lk, lb, kp, Rs);
+    else lk_block<T, P, false, WN>(J.lk, lb, kp, Rs);
 }
 
 // Patch sides the persistent kernel is built for (the autotuner's space).
 __host__ __device__ constexpr bool persist_patch_ok(int p) { return p == 8 || p == 12; }
 
-template <typename T>
+// WN: the window bound of the LK tasks, as for k_lk (the same code, so the
+// results equal those of the launch-per-level executions bit for bit).
+template <typename T, int WN>
 __global__ __launch_bounds__(kBlock) void k_persist(const PTask *__restrict__ tasks, int ntasks,
                                                     const PJob *__restrict__ jobs,
                                                     const KParams *__restrict__ kps, int *err,
@@ -100,8 +102,8 @@ __global__ __launch_bounds__(kBlock) void k_persist(const PTask *__restrict__ ta
             else pyr_block<T, false>(J.pyr, tk.lb, kp);
             break;
         case PK_LK:
-            if (J.patch == 8) lk_task<T, 8>(J, tk.lb, kp, Rs);
-            else lk_task<T, 12>(J, tk.lb, kp, Rs);
+            if (J.patch == 8) lk_task<T, 8, WN>(J, tk.lb, kp, Rs);
+            else lk_task<T, 12, WN>(J, tk.lb, kp, Rs);
             break;
         default:
             if (J.u8) dense_block<T, true>(J.dense, tk.lb, kp);

@@ -533,10 +533,25 @@ const JobPack<Job> &pack_of(const Launch &L) {
 }
 
 template <typename T, int P>
-void launch_lk(const Launch &L, hipStream_t s) {
+void launch_lk(const bdis_t *h, const Launch &L, hipStream_t s) {
     const JobPack<LkJob> &pk = pack_of<LkJob>(L);
-    if (L.u8) hipLaunchKernelGGL((k_lk<T, P, true>), dim3(L.blocks), dim3(kBlock), 0, s, pk, L.kp);
-    else hipLaunchKernelGGL((k_lk<T, P, false>), dim3(L.blocks), dim3(kBlock), 0, s, pk, L.kp);
+    // one window bound per kernel (both in one kernel would cost
+    // occupancy); the register-trimmed variant for launches of more than
+    // four blocks per CU, where occupancy beats per-wave latency
+    const bool big = L.blocks > 4 * h->n_cu;
+    const dim3 g(L.blocks), b(kBlock);
+    if (L.kp.window <= 5) {
+        if (big) {
+            if (L.u8) hipLaunchKernelGGL((k_lk<T, P, true, 5, 5>), g, b, 0, s, pk, L.kp);
+            else hipLaunchKernelGGL((k_lk<T, P, false, 5, 5>), g, b, 0, s, pk, L.kp);
+        } else {
+            if (L.u8) hipLaunchKernelGGL((k_lk<T, P, true, 5, 4>), g, b, 0, s, pk, L.kp);
+            else hipLaunchKernelGGL((k_lk<T, P, false, 5, 4>), g, b, 0, s, pk, L.kp);
+        }
+    } else {
+        if (L.u8) hipLaunchKernelGGL((k_lk<T, P, true, 9, 4>), g, b, 0, s, pk, L.kp);
+        else hipLaunchKernelGGL((k_lk<T, P, false, 9, 4>), g, b, 0, s, pk, L.kp);
+    }
 }
 
 template <typename T>
@@ -563,12 +578,12 @@ void launch_one(bdis_t *h, const Launch &L, hipStream_t s) {
     }
     case K_LK:
         switch (L.patch) {
-        case 4: launch_lk<T, 4>(L, s); break;
-        case 6: launch_lk<T, 6>(L, s); break;
-        case 8: launch_lk<T, 8>(L, s); break;
-        case 10: launch_lk<T, 10>(L, s); break;
-        case 12: launch_lk<T, 12>(L, s); break;
-        case 16: launch_lk<T, 16>(L, s); break;
+        case 4: launch_lk<T, 4>(h, L, s); break;
+        case 6: launch_lk<T, 6>(h, L, s); break;
+        case 8: launch_lk<T, 8>(h, L, s); break;
+        case 10: launch_lk<T, 10>(h, L, s); break;
+        case 12: launch_lk<T, 12>(h, L, s); break;
+        case 16: launch_lk<T, 16>(h, L, s); break;
         }
         break;
     case K_DENSE: {
@@ -763,10 +778,10 @@ void build_ptables(bdis_t *h, std::vector<PairIn> &pairs, int *ctr, PTables &t) 
         }
 }
 
-template <typename T>
+template <typename T, int WN>
 int persist_occupancy(int lds) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persist<T>, kBlock, lds) != hipSuccess) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persist<T, WN>, kBlock, lds) != hipSuccess) {
         (void)hipGetLastError();
         return 1;
     }
@@ -822,11 +837,13 @@ bdis_status run_persistent(bdis_t *h, std::vector<PairIn> &pairs, hipStream_t s)
         h->p_last = bytes;
     }
     // grid: every workgroup resident
-    const int occ = f64 ? persist_occupancy<double>(t2.lds) : persist_occupancy<float>(t2.lds);
+    const bool w5 = h->prm.window <= 5;
+    const int occ = f64 ? (w5 ? persist_occupancy<double, 5>(t2.lds) : persist_occupancy<double, 9>(t2.lds))
+                        : (w5 ? persist_occupancy<float, 5>(t2.lds) : persist_occupancy<float, 9>(t2.lds));
     const int per_cu = h->wgs_per_cu > 0 ? std::min(h->wgs_per_cu, occ) : occ;
     const int grid = (int)std::min<long long>((long long)per_cu * h->n_cu, (long long)ntasks);
     std::vector<long long> key = {(long long)ntasks, (long long)njobs, (long long)t2.kps.size(), grid,
-                                  t2.lds, f64 ? 1 : 0, (long long)(uintptr_t)h->p_dev};
+                                  t2.lds, f64 ? 1 : 0, w5 ? 1 : 0, (long long)(uintptr_t)h->p_dev};
     if (key != h->graph_key) {
         if (h->graph_exec) { (void)hipGraphExecDestroy(h->graph_exec); h->graph_exec = nullptr; }
         if (h->graph) { (void)hipGraphDestroy(h->graph); h->graph = nullptr; }
@@ -838,12 +855,17 @@ bdis_status run_persistent(bdis_t *h, std::vector<PairIn> &pairs, hipStream_t s)
         HIPCHK(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
         int nctr = (int)njobs + 1;
         hipLaunchKernelGGL(k_reset, dim3((nctr + kBlock - 1) / kBlock), dim3(kBlock), 0, h->cap_stream, ctr, nctr);
-        if (f64)
-            hipLaunchKernelGGL(k_persist<double>, dim3(grid), dim3(kBlock), t2.lds, h->cap_stream, dt,
-                               (int)ntasks, dj, dk, h->p_err, spin_limit);
-        else
-            hipLaunchKernelGGL(k_persist<float>, dim3(grid), dim3(kBlock), t2.lds, h->cap_stream, dt,
-                               (int)ntasks, dj, dk, h->p_err, spin_limit);
+        auto go = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), t2.lds, h->cap_stream, dt, (int)ntasks, dj, dk,
+                               h->p_err, spin_limit);
+        };
+        if (f64) {
+            if (w5) go(k_persist<double, 5>);
+            else go(k_persist<double, 9>);
+        } else {
+            if (w5) go(k_persist<float, 5>);
+            else go(k_persist<float, 9>);
+        }
         hipError_t e = hipStreamEndCapture(h->cap_stream, &h->graph);
         if (e != hipSuccess) { set_err(h->err, "graph capture failed: %s", hipGetErrorString(e)); return BDIS_E_HIP; }
         HIPCHK(h, hipGraphInstantiate(&h->graph_exec, h->graph, nullptr, nullptr, 0));
