@@ -3,10 +3,11 @@
 // Paper: J. Song et al., "Bayesian dense inverse searching algorithm for
 // real-time stereo matching in minimally invasive surgery", arXiv 2106.07136.
 //
-// Three kernels per pyramid level, each launched once for every pair of a
-// call (a "job" is one pair at one level):
-//   k_pyr    blur + decimate one level of the left and right pyramids
-//            (Sec. 1, Fig. 1), validity carried in the sign bit;
+// Kernels, each launched once for every pair of a call (a "job" is one pair
+// at one level):
+//   k_pyr2   blur + decimate two levels of the left and right pyramids
+//            (Sec. 1, Fig. 1), validity carried in the sign bit (the
+//            persistent kernel runs one level per task: pyr_block);
 //   k_lk     per-patch inverse-compositional LK along x (Sec. 2.1, eq. (1)),
 //            then the windowed posterior (Sec. 2.2, eqs. (3)-(4)) and the
 //            discard gates (Sec. 3 gamma, Sec. 3.2);
@@ -56,6 +57,24 @@ struct PyrJob {
     int pad_;
 };
 static_assert(sizeof(PyrJob) == 4 * 8 + 8 * 4, "PyrJob must have no padding");
+
+// Two pyramid levels in one launch: level l+1 ("mid") and, when has2, level
+// l+2 ("dst") from level l.  Tiles are kP2X x kP2Y pixels of level l+2 (of
+// the virtual level l+2 when has2 == 0); each block also writes the level-
+// (l+1) pixels under its tile.
+struct Pyr2Job {
+    const void *src_l, *src_r;  // level l (uint8 when l == 0)
+    void *mid_l, *mid_r;        // level l+1, pitch = wm
+    void *dst_l, *dst_r;        // level l+2, pitch = wd (unused when has2 == 0)
+    int src_pitch;              // elements
+    int ws, hs;                 // level l size
+    int wm, hm;                 // level l+1 size
+    int wd, hd;                 // level l+2 size: ceil(wm / 2) x ceil(hm / 2)
+    int has2;                   // 1: write level l+2
+    int tiles_x;                // tiles per row of level l+2
+    int block0;
+};
+static_assert(sizeof(Pyr2Job) == 6 * 8 + 10 * 4, "Pyr2Job must have no padding");
 
 struct LkJob {
     const void *L, *R;     // this level's images
@@ -152,6 +171,12 @@ constexpr int kXcds = 8;
 __device__ __forceinline__ int xcd_block(int bid, int n) {
     const int q = n / kXcds, r = n % kXcds, x = bid % kXcds, k = bid / kXcds;
     return x * q + (x < r ? x : r) + k;
+}
+
+// reflect101 for -n < i < 2 n - 1 (one reflection suffices), n >= 2
+__device__ __forceinline__ int reflect101_near(int i, int n) {
+    i = i < 0 ? -i : i;
+    return i >= n ? 2 * (n - 1) - i : i;
 }
 
 __device__ __forceinline__ int reflect101(int i, int n) {
@@ -279,11 +304,36 @@ __device__ __forceinline__ T sample_row(const void *img, size_t row0, int W, int
 // reflect-101 borders, taken at the even fine position; valid iff all
 // existing 2x2 fine children are valid.  In double precision every level up
 // to the fifth is exact (dyadic sums of 8-bit values).
+constexpr double kBinom5[5] = {1.0 / 16, 4.0 / 16, 6.0 / 16, 4.0 / 16, 1.0 / 16};
+
+// Validity of a coarse pixel at fine position (x, y) = 2 (xc, yc): all of
+// its existing 2x2 fine children are valid.
+template <typename T, bool U8>
+__device__ __forceinline__ bool pyr_valid(const void *src, int pitch, int ws, int hs, int x, int y,
+                                          const KParams &kp) {
+    bool ok = true;
+#pragma unroll
+    for (int dy = 0; dy < 2; dy++)
+#pragma unroll
+        for (int dx = 0; dx < 2; dx++) {
+            int yy = y + dy, xx = x + dx;
+            if (yy < hs && xx < ws) {
+                bool v;
+                (void)pix<T, U8>(src, (size_t)yy * pitch + xx, kp, v);
+                ok = ok && v;
+            }
+        }
+    return ok;
+}
+
+// One coarse pixel of both images: binomial [1 4 6 4 1]/16 in x then y with
+// reflect-101 borders, taken at the even fine position; valid iff all
+// existing 2x2 fine children are valid.  In double precision every level up
+// to the fifth is exact (dyadic sums of 8-bit values).
 template <typename T, bool U8>
 __device__ __forceinline__ void pyr_pixel(const PyrJob &J, int i, const KParams &kp) {
     int yc = i / J.wd, xc = i - yc * J.wd;
     int x = 2 * xc, y = 2 * yc;
-    const T w5[5] = {T(1) / 16, T(4) / 16, T(6) / 16, T(4) / 16, T(1) / 16};
     int cols[5], rows[5];
 #pragma unroll
     for (int a = 0; a < 5; a++) {
@@ -299,21 +349,10 @@ __device__ __forceinline__ void pyr_pixel(const PyrJob &J, int i, const KParams 
             size_t r0 = (size_t)rows[a] * J.src_pitch;
             T h = 0;
 #pragma unroll
-            for (int b = 0; b < 5; b++) h += w5[b] * pixv<T, U8>(src, r0 + cols[b]);
-            acc += w5[a] * h;
+            for (int b = 0; b < 5; b++) h += (T)kBinom5[b] * pixv<T, U8>(src, r0 + cols[b]);
+            acc += (T)kBinom5[a] * h;
         }
-        bool ok = true;
-#pragma unroll
-        for (int dy = 0; dy < 2; dy++)
-#pragma unroll
-            for (int dx = 0; dx < 2; dx++) {
-                int yy = y + dy, xx = x + dx;
-                if (yy < J.hs && xx < J.ws) {
-                    bool v;
-                    (void)pix<T, U8>(src, (size_t)yy * J.src_pitch + xx, kp, v);
-                    ok = ok && v;
-                }
-            }
+        const bool ok = pyr_valid<T, U8>(src, J.src_pitch, J.ws, J.hs, x, y, kp);
         T *dst = static_cast<T *>(img ? J.dst_r : J.dst_l);
         dst[i] = ok ? acc : -acc;  // -0 keeps the invalid flag for a zero value
     }
@@ -334,11 +373,139 @@ __device__ __forceinline__ void pyr_block(const PyrJob &J, int lb, const KParams
     }
 }
 
+// Two levels per launch, separable through LDS.  The block's level-(l+2)
+// tile reads level l+1 at rows and columns 2 t - 2 .. 2 t + 2 (reflect-101);
+// that region ("mid", virtual coordinates) holds, at each position, the
+// level-(l+1) value of the reflected position.  Its in-image part is filtered
+// from level l in two passes -- rows of level l in x into H, then H in y --
+// the out-of-image part is copied from the reflected entries (always inside
+// the region), and the tile is filtered from mid.  The sums run in the same
+// order as pyr_pixel's, so both levels equal two single-level launches bit
+// for bit; the level-(l+1) pixels under the tile are written out as well.
+constexpr int kP2X = 16, kP2Y = 8;                         // level-(l+2) tile
+constexpr int kP2MX = 2 * kP2X + 3, kP2MY = 2 * kP2Y + 3;  // level-(l+1) region
+constexpr int kP2HY = 2 * (kP2MY - 1) + 5;                 // level-l rows of H
+static_assert(2 * kP2X * kP2Y == kBlock, "one thread per (image, tile pixel)");
+
 template <typename T, bool U8>
-__global__ __launch_bounds__(kBlock) void k_pyr(const JobPack<PyrJob> pk, KParams kp) {
+__global__ __launch_bounds__(kBlock) void k_pyr2(const JobPack<Pyr2Job> pk, KParams kp) {
+    __shared__ T Hs[2][kP2HY][kP2MX];
+    __shared__ uint8_t Vs[2][kP2HY][kP2MX];  // bits: source pixels xc, xc + 1 valid
+    __shared__ T mid[2][kP2MY][kP2MX];       // signed: sign bit = validity
     const int bid = xcd_block((int)blockIdx.x, (int)gridDim.x);
-    const PyrJob &J = pk.j[find_job(pk, bid)];
-    pyr_block<T, U8>(J, bid - J.block0, kp);
+    const Pyr2Job &J = pk.j[find_job(pk, bid)];
+    const int lb = bid - J.block0;
+    const int ty = lb / J.tiles_x, tx = lb - ty * J.tiles_x;
+    const int x2_0 = tx * kP2X, y2_0 = ty * kP2Y;
+    const int vx0 = 2 * x2_0 - 2, vy0 = 2 * y2_0 - 2;  // virtual origin of mid
+    // mid entries the tile reads (all of them are needed only with has2)
+    const int vx_end = J.has2 ? min(vx0 + kP2MX, 2 * J.wd + 1) : min(2 * x2_0 + 2 * kP2X, J.wm);
+    const int vy_end = J.has2 ? min(vy0 + kP2MY, 2 * J.hd + 1) : min(2 * y2_0 + 2 * kP2Y, J.hm);
+    // in-image part [xa, xb) x [ya, yb) of level l+1
+    const int xa = J.has2 ? max(vx0, 0) : 2 * x2_0, xb = min(vx_end, J.wm);
+    const int ya = J.has2 ? max(vy0, 0) : 2 * y2_0, yb = min(vy_end, J.hm);
+    const int ncol = xb - xa, nhrow = 2 * (yb - ya - 1) + 5;
+    // pass 1: H[r][c] = sum_b w_b src(row(2 ya - 2 + r), col(2 (xa + c) + b - 2)).
+    // Fixed trip count and clamped indices keep the loop one basic block, so
+    // every load of the thread is in flight before the first sum.
+    constexpr int NQ1 = (kP2HY * kP2MX + kBlock - 1) / kBlock;
+    const int n1 = nhrow * ncol;
+    // every tap is within 2 of the image (one reflection) unless a side < 3
+    const bool near = J.ws >= 3 && J.hs >= 3;
+    auto refl = [&](int i, int n) { return near ? reflect101_near(i, n) : reflect101(i, n); };
+    T hv[NQ1][2];
+    uint32_t vb[NQ1][2];  // validity of the source pixels at columns xc, xc + 1 of the row
+#pragma unroll
+    for (int it = 0; it < NQ1; it++) {
+        const int q = min((int)threadIdx.x + it * kBlock, n1 - 1);
+        const int r = q / ncol, c = q - r * ncol;
+        const size_t r0 = (size_t)refl(2 * ya - 2 + r, J.hs) * J.src_pitch;
+        const int xc = 2 * (xa + c);
+#pragma unroll
+        for (int img = 0; img < 2; img++) {
+            const void *src = img ? J.src_r : J.src_l;
+            T h = 0;
+            uint32_t bits = 0;
+#pragma unroll
+            for (int b = 0; b < 5; b++) {
+                bool v;
+                const T x = pix<T, U8>(src, r0 + refl(xc + b - 2, J.ws), kp, v);
+                h += (T)kBinom5[b] * x;
+                if (b == 2) bits |= v ? 1u : 0u;
+                if (b == 3) bits |= (v || xc + 1 >= J.ws) ? 2u : 0u;  // a missing child counts as valid
+            }
+            hv[it][img] = h;
+            vb[it][img] = bits;
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < NQ1; it++) {
+        const int q = (int)threadIdx.x + it * kBlock;
+        if (q < n1) {
+            const int r = q / ncol, c = q - r * ncol;
+            Hs[0][r][c] = hv[it][0];
+            Hs[1][r][c] = hv[it][1];
+            Vs[0][r][c] = (uint8_t)vb[it][0];
+            Vs[1][r][c] = (uint8_t)vb[it][1];
+        }
+    }
+    __syncthreads();
+    // pass 2: the in-image level-(l+1) values, their validity (the 2 x 2
+    // children: rows 2 r + 2, 2 r + 3 of H), the owned writes
+    constexpr int NQ2 = (kP2MY * kP2MX + kBlock - 1) / kBlock;
+    const int n2 = (yb - ya) * ncol;
+#pragma unroll
+    for (int it = 0; it < NQ2; it++) {
+        const int q = (int)threadIdx.x + it * kBlock;
+        if (q >= n2) continue;
+        const int r = q / ncol, c = q - r * ncol;
+        const int ym = ya + r, xm = xa + c;
+        const bool own = ym >= 2 * y2_0 && ym < 2 * y2_0 + 2 * kP2Y && xm >= 2 * x2_0 && xm < 2 * x2_0 + 2 * kP2X;
+        const bool row2 = 2 * ym + 1 < J.hs;
+#pragma unroll
+        for (int img = 0; img < 2; img++) {
+            T acc = 0;
+#pragma unroll
+            for (int a = 0; a < 5; a++) acc += (T)kBinom5[a] * Hs[img][2 * r + a][c];
+            const bool ok = Vs[img][2 * r + 2][c] == 3u && (!row2 || Vs[img][2 * r + 3][c] == 3u);
+            const T v = ok ? acc : -acc;
+            mid[img][ym - vy0][xm - vx0] = v;
+            if (own) static_cast<T *>(img ? J.mid_r : J.mid_l)[(size_t)ym * J.wm + xm] = v;
+        }
+    }
+    if (!J.has2) return;  // uniform over the block
+    __syncthreads();
+    // out-of-image mid entries: copies of their reflected positions
+    for (int q = (int)threadIdx.x; q < kP2MY * kP2MX; q += kBlock) {
+        const int t = q / kP2MX, c = q - t * kP2MX;
+        const int vy = vy0 + t, vx = vx0 + c;
+        if (vy >= vy_end || vx >= vx_end) continue;
+        if (vy >= 0 && vy < J.hm && vx >= 0 && vx < J.wm) continue;
+        const int ym = reflect101(vy, J.hm), xm = reflect101(vx, J.wm);
+#pragma unroll
+        for (int img = 0; img < 2; img++) mid[img][t][c] = mid[img][ym - vy0][xm - vx0];
+    }
+    __syncthreads();
+    // level l+2: thread = (image, pixel of the kP2X x kP2Y tile)
+    const int img = (int)threadIdx.x / (kP2X * kP2Y), pxl = (int)threadIdx.x % (kP2X * kP2Y);
+    const int x2 = x2_0 + pxl % kP2X, y2 = y2_0 + pxl / kP2X;
+    if (x2 >= J.wd || y2 >= J.hd) return;
+    const int t0 = 2 * (y2 - y2_0), c0 = 2 * (x2 - x2_0);  // mid index of tap -2
+    T acc = 0;
+#pragma unroll
+    for (int a = 0; a < 5; a++) {
+        T h = 0;
+#pragma unroll
+        for (int b = 0; b < 5; b++) h += (T)kBinom5[b] * fabs(mid[img][t0 + a][c0 + b]);
+        acc += (T)kBinom5[a] * h;
+    }
+    bool ok = true;
+#pragma unroll
+    for (int dy = 0; dy < 2; dy++)
+#pragma unroll
+        for (int dx = 0; dx < 2; dx++)
+            if (2 * y2 + dy < J.hm && 2 * x2 + dx < J.wm) ok = ok && !signbit(mid[img][t0 + 2 + dy][c0 + 2 + dx]);
+    static_cast<T *>(img ? J.dst_r : J.dst_l)[(size_t)y2 * J.wd + x2] = ok ? acc : -acc;
 }
 
 // ---------------------------------------------------------------- LK + posterior

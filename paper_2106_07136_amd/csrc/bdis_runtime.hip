@@ -340,7 +340,7 @@ bdis_status ensure_ws(bdis_t *h, size_t bytes) {
 }
 
 // A launch: kernel kind, template selectors and its jobs (passed by value).
-enum Kind { K_PYR, K_LK, K_DENSE, K_NETIN, K_NET, K_GATE };
+enum Kind { K_PYR2, K_LK, K_DENSE, K_NETIN, K_NET, K_GATE };
 struct Launch {
     Kind kind;
     int level;
@@ -387,6 +387,33 @@ int lk_bpr(int P, int nx) {
     }
 }
 
+// Pyramid levels 1 .. Lp-1 of every pair, two levels per launch: launch k
+// writes levels 2k+1 and 2k+2 (only 2k+1 for a pair whose pyramid ends
+// there).
+void plan_pyramid(std::vector<Launch> &ls, const std::vector<PairIn> &pairs, int Lpmax, bool f64,
+                  const KParams &kp0) {
+    for (int l = 1; l < Lpmax; l += 2) {
+        std::vector<Pyr2Job> jobs;
+        for (const auto &p : pairs) {
+            if (p.g.Lp <= l) continue;
+            Pyr2Job j{};
+            j.src_l = l == 1 ? (const void *)p.left : p.ws.pyr_l[l - 1];
+            j.src_r = l == 1 ? (const void *)p.right : p.ws.pyr_r[l - 1];
+            j.src_pitch = l == 1 ? p.pitch : p.g.W[l - 1];
+            j.ws = p.g.W[l - 1]; j.hs = p.g.H[l - 1];
+            j.mid_l = p.ws.pyr_l[l]; j.mid_r = p.ws.pyr_r[l];
+            j.wm = p.g.W[l]; j.hm = p.g.H[l];
+            j.wd = (j.wm + 1) / 2; j.hd = (j.hm + 1) / 2;
+            j.has2 = p.g.Lp > l + 1 ? 1 : 0;
+            if (j.has2) { j.dst_l = p.ws.pyr_l[l + 1]; j.dst_r = p.ws.pyr_r[l + 1]; }
+            j.tiles_x = (j.wd + kP2X - 1) / kP2X;
+            jobs.push_back(j);
+        }
+        append(ls, K_PYR2, l, 0, l == 1, f64, jobs, kp0,
+               [](const Pyr2Job &j) { return j.tiles_x * ((j.hd + kP2Y - 1) / kP2Y); });
+    }
+}
+
 // Build every launch for a set of pairs: pyramid levels 1..Lmax-1, then for
 // each level from the coarsest down, LK (per patch size) and the
 // densification.
@@ -409,23 +436,7 @@ void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<Launch> &l
         Lpmax = std::max(Lpmax, p.g.Lp);
     }
     KParams kp0 = make_kparams(h->prm, h->prm.patch);
-    for (int l = 1; l < Lpmax; l++) {
-        std::vector<PyrJob> jobs;
-        for (auto &p : pairs) {
-            if (p.g.Lp <= l) continue;
-            PyrJob j{};  // zeroed padding: job packs are compared byte for byte
-            j.src_l = l == 1 ? (const void *)p.left : p.ws.pyr_l[l - 1];
-            j.src_r = l == 1 ? (const void *)p.right : p.ws.pyr_r[l - 1];
-            j.src_pitch = l == 1 ? p.pitch : p.g.W[l - 1];
-            j.ws = p.g.W[l - 1]; j.hs = p.g.H[l - 1];
-            j.dst_l = p.ws.pyr_l[l]; j.dst_r = p.ws.pyr_r[l];
-            j.wd = p.g.W[l]; j.hd = p.g.H[l];
-            j.ppt = 1;
-            jobs.push_back(j);
-        }
-        append(ls, K_PYR, l, 0, l == 1, f64, jobs, kp0,
-               [](const PyrJob &j) { return pyr_blocks(j.wd, j.hd, j.ppt); });
-    }
+    plan_pyramid(ls, pairs, Lpmax, f64, kp0);
     if (lrn) {
         std::vector<NetInJob> in;
         std::vector<GateJob> gate;
@@ -570,10 +581,10 @@ void launch_one(bdis_t *h, const Launch &L, hipStream_t s) {
     case K_GATE:
         hipLaunchKernelGGL(k_gate<T>, dim3(L.blocks), dim3(kBlock), 0, s, pack_of<GateJob>(L));
         break;
-    case K_PYR: {
-        const JobPack<PyrJob> &pk = pack_of<PyrJob>(L);
-        if (L.u8) hipLaunchKernelGGL((k_pyr<T, true>), dim3(L.blocks), dim3(kBlock), 0, s, pk, L.kp);
-        else hipLaunchKernelGGL((k_pyr<T, false>), dim3(L.blocks), dim3(kBlock), 0, s, pk, L.kp);
+    case K_PYR2: {
+        const JobPack<Pyr2Job> &pk = pack_of<Pyr2Job>(L);
+        if (L.u8) hipLaunchKernelGGL((k_pyr2<T, true>), dim3(L.blocks), dim3(kBlock), 0, s, pk, L.kp);
+        else hipLaunchKernelGGL((k_pyr2<T, false>), dim3(L.blocks), dim3(kBlock), 0, s, pk, L.kp);
         break;
     }
     case K_LK:
@@ -599,7 +610,7 @@ std::string launch_name(const Launch &L) {
     char buf[48];
     const char *t = L.f64 ? "f64" : "f32";
     switch (L.kind) {
-    case K_PYR: snprintf(buf, sizeof buf, "pyr_%s_l%d", t, L.level); break;
+    case K_PYR2: snprintf(buf, sizeof buf, "pyr2_%s_l%d", t, L.level); break;
     case K_LK: snprintf(buf, sizeof buf, "lk_%s_p%d_l%d", t, L.patch, L.level); break;
     case K_DENSE: snprintf(buf, sizeof buf, "dense_%s_l%d", t, L.level); break;
     case K_NETIN: snprintf(buf, sizeof buf, "netin_%s", t); break;
@@ -1229,22 +1240,7 @@ bdis_status bdis_net_input(bdis_t *h, const bdis_pair *pairs, int32_t n, uint16_
     const bool f64 = h->prm.precision == 0;
     KParams kp0 = make_kparams(h->prm, h->prm.patch);
     std::vector<Launch> ls;
-    for (int l = 1; l <= kNetLevel; l++) {
-        std::vector<PyrJob> jobs;
-        for (auto &p : ps) {
-            PyrJob j{};
-            j.src_l = l == 1 ? (const void *)p.left : p.ws.pyr_l[l - 1];
-            j.src_r = l == 1 ? (const void *)p.right : p.ws.pyr_r[l - 1];
-            j.src_pitch = l == 1 ? p.pitch : p.g.W[l - 1];
-            j.ws = p.g.W[l - 1]; j.hs = p.g.H[l - 1];
-            j.dst_l = p.ws.pyr_l[l]; j.dst_r = p.ws.pyr_r[l];
-            j.wd = p.g.W[l]; j.hd = p.g.H[l];
-            j.ppt = 1;
-            jobs.push_back(j);
-        }
-        append(ls, K_PYR, l, 0, l == 1, f64, jobs, kp0,
-               [](const PyrJob &j) { return pyr_blocks(j.wd, j.hd, j.ppt); });
-    }
+    plan_pyramid(ls, ps, kNetLevel + 1, f64, kp0);
     std::vector<NetInJob> in;
     const size_t per = (size_t)ps[0].g.W[kNetLevel] * ps[0].g.H[kNetLevel] * kNetIn;
     for (int i = 0; i < n; i++) {
