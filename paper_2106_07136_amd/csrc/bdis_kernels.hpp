@@ -894,7 +894,62 @@ __device__ __forceinline__ void dense_pixel(const DenseJob &J, const int i, cons
     int xlo, xhi, xex, ylo, yhi, yex;
     range(x, J.W, J.nx, xlo, xhi, xex);
     range(y, J.H, J.ny, ylo, yhi, yex);
+    // the fallback field's taps go out with the patch records (one round trip)
+    T Uf = 0;
+    if (J.mode == 0) Uf = T(2) * bilinear<T>(static_cast<const T *>(J.Uc), J.Wc, J.Hc, T(0.5) * (T)x, T(0.5) * (T)y);
     T A = 0, B = 0;
+    auto add = [&](int py, int px, T wk, T uk, T g) {
+        T w;
+        if (kp.fusion == 1) {
+            size_t row0 = (size_t)y * J.pitch;
+            T uc = fmin(fmax(uk, -(T)(J.W + 2)), (T)(J.W + 2));
+            T ui = floor(uc), uf = uc - ui;
+            T res = sample_row<T, U8>(J.R, row0, J.W, x + (int)ui, uf) - pixv<T, U8>(J.L, row0 + x);
+            T q = res * res;
+            w = T(1) / (q > T(1) ? q : T(1));
+        } else {
+            w = wk * g;
+        }
+        A += w;
+        B += w * uk;
+    };
+    // Fast path: at most NC candidate patches per axis (lo .. hi, then the
+    // one snapped to the border), every record and mask load issued before
+    // the sums, which run in the same (row, column) order as the loop below.
+    constexpr int NC = 3;
+    const int ncx = xhi - xlo + 1 + (xex >= 0 ? 1 : 0), ncy = yhi - ylo + 1 + (yex >= 0 ? 1 : 0);
+    if (ncx <= NC && ncy <= NC) {
+        int px[NC], py[NC], jxs[NC], jys[NC];
+        bool vx[NC], vy[NC];
+#pragma unroll
+        for (int i = 0; i < NC; i++) {
+            int jx = i <= xhi - xlo ? xlo + i : (i == xhi - xlo + 1 ? xex : -1);
+            int jy = i <= yhi - ylo ? ylo + i : (i == yhi - ylo + 1 ? yex : -1);
+            px[i] = jx >= 0 ? grid_pos(jx, J.W, P, st) : 0;
+            py[i] = jy >= 0 ? grid_pos(jy, J.H, P, st) : 0;
+            vx[i] = jx >= 0 && x >= px[i] && x < px[i] + P;
+            vy[i] = jy >= 0 && y >= py[i] && y < py[i] + P;
+            jxs[i] = vx[i] ? jx : 0;
+            jys[i] = vy[i] ? jy : 0;
+        }
+        T wk[NC][NC], uk[NC][NC], g[NC][NC];
+#pragma unroll
+        for (int iy = 0; iy < NC; iy++)
+#pragma unroll
+            for (int ix = 0; ix < NC; ix++) {
+                const bool v = vy[iy] && vx[ix];
+                const int k = v ? jys[iy] * J.nx + jxs[ix] : 0;
+                wk[iy][ix] = rec_w[k];
+                uk[iy][ix] = rec_u[k];
+                g[iy][ix] = gtab[v ? (y - py[iy]) * P + (x - px[ix]) : 0];
+                if (!v) wk[iy][ix] = T(0);
+            }
+#pragma unroll
+        for (int iy = 0; iy < NC; iy++)
+#pragma unroll
+            for (int ix = 0; ix < NC; ix++)
+                if (wk[iy][ix] > T(0)) add(py[iy], px[ix], wk[iy][ix], uk[iy][ix], g[iy][ix]);
+    } else {
     for (int jy = ylo; jy <= (yex >= 0 ? yex : yhi); jy++) {
         if (jy > yhi && jy != yex) continue;
         int py = grid_pos(jy, J.H, P, st);
@@ -906,27 +961,15 @@ __device__ __forceinline__ void dense_pixel(const DenseJob &J, const int i, cons
             int k = jy * J.nx + jx;
             T wk = rec_w[k];
             if (!(wk > T(0))) continue;
-            T uk = rec_u[k];
-            T w;
-            if (kp.fusion == 1) {
-                size_t row0 = (size_t)y * J.pitch;
-                T uc = fmin(fmax(uk, -(T)(J.W + 2)), (T)(J.W + 2));
-                T ui = floor(uc), uf = uc - ui;
-                T res = sample_row<T, U8>(J.R, row0, J.W, x + (int)ui, uf) - pixv<T, U8>(J.L, row0 + x);
-                T q = res * res;
-                w = T(1) / (q > T(1) ? q : T(1));
-            } else {
-                w = wk * gtab[(y - py) * P + (x - px)];
-            }
-            A += w;
-            B += w * uk;
+            add(py, px, wk, rec_u[k], gtab[(y - py) * P + (x - px)]);
         }
+    }
     }
     T U;
     if (A > T(0)) U = B / A;
     else if (J.mode == 2) U = (T)__builtin_nan("");
     else if (J.mode == 1) U = 0;
-    else U = T(2) * bilinear<T>(static_cast<const T *>(J.Uc), J.Wc, J.Hc, T(0.5) * (T)x, T(0.5) * (T)y);
+    else U = Uf;
     if (J.out) J.out[(size_t)y * J.out_pitch + x] = (float)(-U);
     if (J.U) static_cast<T *>(J.U)[i] = U;
 }
