@@ -586,13 +586,8 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
         }
     }
 
-    // initial shift: twice the coarse field at the patch centre (Sec. 2.1)
-    T u0 = 0;
-    if (J.Uc) {
-        T cx = (T)x0 + T(0.5) * (T)(P - 1), cy = (T)y0 + T(0.5) * (T)(P - 1);
-        u0 = T(2) * bilinear<T>(static_cast<const T *>(J.Uc), J.Wc, J.Hc, T(0.5) * cx, T(0.5) * cy);
-    }
     const T ulo = -(T)(W + P + 2), uhi = (T)(W + 2);
+    T u0 = 0;
 
     // Staged span of the block's right rows, from static bounds so the loads
     // go out with the template and init loads: disparities d >= 0 shift the
@@ -605,7 +600,9 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
     col_lo = max(col_lo, col_hi - NCMAX + 1);
     const int nc = col_hi - col_lo + 1;
     // rows in passes of up to 8, columns in chunks of kBlock: every load of a
-    // pass is issued before the LDS writes (one memory round trip per pass)
+    // pass is issued before the LDS writes (one memory round trip per pass);
+    // the first pass's loads go out before the initial shift waits for its
+    // own, so template, staging and init share one round trip
     constexpr int CH = (NCMAX + kBlock - 1) / kBlock;
 #pragma unroll
     for (int r0 = 0; r0 < P; r0 += 8) {
@@ -622,6 +619,11 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
                     else buf[rr][q] = static_cast<const T *>(J.R)[g];
                 }
             }
+        if (r0 == 0 && J.Uc) {
+            // initial shift: twice the coarse field at the patch centre (Sec. 2.1)
+            T cx = (T)x0 + T(0.5) * (T)(P - 1), cy = (T)y0 + T(0.5) * (T)(P - 1);
+            u0 = T(2) * bilinear<T>(static_cast<const T *>(J.Uc), J.Wc, J.Hc, T(0.5) * cx, T(0.5) * cy);
+        }
 #pragma unroll
         for (int rr = 0; rr < 8; rr++)
 #pragma unroll
