@@ -918,9 +918,9 @@ __device__ __forceinline__ void dense_pixel(const DenseJob &J, const int i, cons
     // Fast path: at most NC candidate patches per axis (lo .. hi, then the
     // one snapped to the border), every record and mask load issued before
     // the sums, which run in the same (row, column) order as the loop below.
-    constexpr int NC = 3;
-    const int ncx = xhi - xlo + 1 + (xex >= 0 ? 1 : 0), ncy = yhi - ylo + 1 + (yex >= 0 ? 1 : 0);
-    if (ncx <= NC && ncy <= NC) {
+    // NC = 2 covers the interior at stride >= patch / 2, NC = 3 its border.
+    auto fast = [&](auto NC_) {
+        constexpr int NC = decltype(NC_)::value;
         int px[NC], py[NC], jxs[NC], jys[NC];
         bool vx[NC], vy[NC];
 #pragma unroll
@@ -951,6 +951,12 @@ __device__ __forceinline__ void dense_pixel(const DenseJob &J, const int i, cons
 #pragma unroll
             for (int ix = 0; ix < NC; ix++)
                 if (wk[iy][ix] > T(0)) add(py[iy], px[ix], wk[iy][ix], uk[iy][ix], g[iy][ix]);
+    };
+    const int ncx = xhi - xlo + 1 + (xex >= 0 ? 1 : 0), ncy = yhi - ylo + 1 + (yex >= 0 ? 1 : 0);
+    if (ncx <= 2 && ncy <= 2) {
+        fast(std::integral_constant<int, 2>());
+    } else if (ncx <= 3 && ncy <= 3) {
+        fast(std::integral_constant<int, 3>());
     } else {
     for (int jy = ylo; jy <= (yex >= 0 ? yex : yhi); jy++) {
         if (jy > yhi && jy != yex) continue;
