@@ -587,6 +587,16 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
     }
 
     const T ulo = -(T)(W + P + 2), uhi = (T)(W + 2);
+    // Integer part (and fraction) of a shift for the sampler.  The sampler
+    // clamps the shift to [ulo, uhi]; beyond that range every column of the
+    // patch row lies outside the image and reads its border pixel whatever
+    // the fraction is, so clamping the integer part alone gives the same
+    // samples and keeps the clamp off the iteration's dependency chain.
+    auto ishift = [&](T v, T &uf) -> int {
+        const T fl = floor(v);
+        uf = v - fl;
+        return min(max((int)fl, -(W + P + 2)), W + 2);
+    };
     T u0 = 0;
 
     // Staged span of the block's right rows, from static bounds so the loads
@@ -718,9 +728,8 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
         }
         const T jt = jt0 + jt1;
         for (int t = 0; t < kp.iters; t++) {
-            T uc = fmin(fmax(u, ulo), uhi);
-            T ui = floor(uc), uf = uc - ui;
-            const int xi0 = x0 + (int)ui;
+            T uf;
+            const int xi0 = x0 + ishift(u, uf);
             T s;
             if (xi0 >= col_lo && xi0 + P <= col_hi) {
                 // staged and inside the row, so every sample interpolates
@@ -783,10 +792,10 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
                     acc[2 * i + 1] = 0;
                     if (i < kp.window) {
                         T ud = u + (T)(i - cw) * (T)kp.window_step;
-                        T uc = fmin(fmax(ud, ulo), uhi);
-                        T ui = floor(uc), uf = uc - ui;
+                        T uf;
+                        const int xi0 = x0 + ishift(ud, uf);
                         T d[P];
-                        sample(x0 + (int)ui, uf, d);
+                        sample(xi0, uf, d);
 #pragma unroll
                         for (int c = 0; c < P; c++) {
                             T q = ((vmask >> c) & 1u) ? d[c] - Tv[c] : T(0);
