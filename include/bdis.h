@@ -165,6 +165,18 @@ BDIS_API bdis_status bdis_compute_batch(bdis_t *h, const bdis_pair *pairs, int32
  * Results are the same in every mode, bit for bit. */
 BDIS_API bdis_status bdis_set_batch_mode(bdis_t *h, int32_t mode, int32_t wgs_per_cu);
 
+/* Launch layout of the per-launch executions (bdis_compute, batch modes 0 and
+ * 1).  on = 1 (default): the densification of each level >= 1 (Sec. 2.3) runs
+ * inside the next finer level's LK launch -- each block writes its share of
+ * the coarser field and evaluates its patches' initial-shift taps itself --
+ * so a pair of L levels takes L + 1 launches after the pyramid instead of 2 L.
+ * It applies to the Bayesian fusion and to LK launches of at most four blocks
+ * per compute unit (one pair: latency-bound); large batches, the learned
+ * injection level and eq. (2)'s fusion keep their own densify launch.  on = 0:
+ * one densify launch per level.  Results are the same either way, bit for bit.  Errors:
+ * BDIS_E_INVALID_ARG for a NULL handle or on not in {0, 1}. */
+BDIS_API bdis_status bdis_set_fold_densify(bdis_t *h, int32_t on);
+
 /* Waits for the last bdis_compute_batch and reports whether the persistent
  * kernel had to give up a dependency wait (*flag = 1: that batch's results are
  * not valid; it cannot happen when the kernel owns the GPU).  *flag = 0 in

@@ -107,6 +107,7 @@ def lib():
         L.bdis_set_tuning.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
         L.bdis_debug_stage.argtypes = [vp, i32, i32, vp, C.c_size_t]
         L.bdis_set_batch_mode.argtypes = [vp, i32, i32]
+        L.bdis_set_fold_densify.argtypes = [vp, i32]
         L.bdis_batch_error.argtypes = [vp, C.POINTER(i32)]
         L.bdis_set_net.argtypes = [vp, vp]
         L.bdis_net_input.argtypes = [vp, C.POINTER(CPair), i32, vp, vp]
@@ -121,7 +122,7 @@ def lib():
         for name in ("bdis_plan", "bdis_create", "bdis_set_params", "bdis_reserve", "bdis_compute",
                      "bdis_compute_batch", "bdis_set_tuning", "bdis_debug_stage",
                      "bdis_set_profiling", "bdis_get_profile", "bdis_set_batch_mode",
-                     "bdis_batch_error", "bdis_set_net", "bdis_net_input"):
+                     "bdis_batch_error", "bdis_set_net", "bdis_net_input", "bdis_set_fold_densify"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -233,8 +234,14 @@ class Bdis:
         return out
 
     def set_batch_mode(self, mode: int, wgs_per_cu: int = 0):
-        """0: one persistent launch in a hipGraph; 1: one launch per level."""
+        """0: the per-level launches captured in a hipGraph (default); 1: the
+        same launches direct; 2: one persistent kernel."""
         _check(lib().bdis_set_batch_mode(self._h, mode, wgs_per_cu), self._h)
+
+    def set_fold_densify(self, on: bool):
+        """True (default): levels >= 1 are densified inside the next finer
+        level's LK launch; False: one densify launch per level."""
+        _check(lib().bdis_set_fold_densify(self._h, 1 if on else 0), self._h)
 
     def batch_error(self) -> int:
         f = C.c_int32()

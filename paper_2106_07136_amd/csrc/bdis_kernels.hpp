@@ -78,10 +78,16 @@ static_assert(sizeof(Pyr2Job) == 6 * 8 + 10 * 4, "Pyr2Job must have no padding")
 
 struct LkJob {
     const void *L, *R;     // this level's images
-    const void *Uc;        // coarse field (level + 1), pitch Wc; null at coarsest
+    void *Uc;              // coarse field (level + 1), pitch Wc; null at coarsest.
+                           // Read for the initial shifts, or -- when the job
+                           // densifies level + 1 itself (rec_u1 set) -- written
     void *rec_u, *rec_w, *rec_u0;  // per-patch records, arithmetic type
     int8_t *rec_st;        // per-patch outcome
     const int *run_flag;   // non-null: the job runs only if *run_flag != 0
+    // Densification of level + 1 folded into this launch (Bayesian fusion):
+    // its patch records, spatial weights and fallback field (level + 2, null
+    // when level + 1 is the coarsest); rec_u1 null: Uc is read as it is
+    const void *rec_u1, *rec_w1, *gtab1, *U2;
     int pitch;             // image pitch, elements
     int W, H;
     int Wc, Hc;
@@ -90,7 +96,7 @@ struct LkJob {
                            // patch (the level's largest expected disparity)
     int block0;
 };
-static_assert(sizeof(LkJob) == 8 * 8 + 10 * 4, "LkJob must have no padding");
+static_assert(sizeof(LkJob) == 12 * 8 + 10 * 4, "LkJob must have no padding");
 
 struct DenseJob {
     const void *L, *R;     // images (DIS fusion only)
@@ -274,17 +280,32 @@ __device__ __forceinline__ int seg_sum_i(int v) {
 
 // Bilinear read of a coarse field, coordinates clamped to the field.
 template <typename T>
-__device__ __forceinline__ T bilinear(const T *F, int W, int H, T X, T Y) {
+__device__ __forceinline__ void bilinear_taps(int W, int H, T X, T Y, int &mx, int &my, int &mx1, int &my1, T &fx,
+                                              T &fy) {
     X = fmin(fmax(X, T(0)), (T)(W - 1));
     Y = fmin(fmax(Y, T(0)), (T)(H - 1));
-    int mx = (int)floor(X), my = (int)floor(Y);
+    mx = (int)floor(X), my = (int)floor(Y);
     mx = min(mx, W - 2); my = min(my, H - 2);
     mx = max(mx, 0); my = max(my, 0);
-    T fx = W > 1 ? X - (T)mx : T(0), fy = H > 1 ? Y - (T)my : T(0);
-    int mx1 = W > 1 ? mx + 1 : mx, my1 = H > 1 ? my + 1 : my;
-    T a = (T(1) - fx) * F[(size_t)my * W + mx] + fx * F[(size_t)my * W + mx1];
-    T b = (T(1) - fx) * F[(size_t)my1 * W + mx] + fx * F[(size_t)my1 * W + mx1];
+    fx = W > 1 ? X - (T)mx : T(0), fy = H > 1 ? Y - (T)my : T(0);
+    mx1 = W > 1 ? mx + 1 : mx, my1 = H > 1 ? my + 1 : my;
+}
+template <typename T>
+__device__ __forceinline__ T bilinear_mix(T f00, T f01, T f10, T f11, T fx, T fy) {
+    // no contraction into FMAs: the value must not depend on the caller
+    // (the densify kernel and the LK launch that densifies for itself)
+#pragma clang fp contract(off)
+    T a = (T(1) - fx) * f00 + fx * f01;
+    T b = (T(1) - fx) * f10 + fx * f11;
     return (T(1) - fy) * a + fy * b;
+}
+template <typename T>
+__device__ __forceinline__ T bilinear(const T *F, int W, int H, T X, T Y) {
+    int mx, my, mx1, my1;
+    T fx, fy;
+    bilinear_taps<T>(W, H, X, Y, mx, my, mx1, my1, fx, fy);
+    return bilinear_mix<T>(F[(size_t)my * W + mx], F[(size_t)my * W + mx1], F[(size_t)my1 * W + mx],
+                           F[(size_t)my1 * W + mx1], fx, fy);
 }
 
 // Right-image sample at column xi + uf of one row (xi integer, 0 <= uf < 1),
@@ -508,6 +529,122 @@ __global__ __launch_bounds__(kBlock) void k_pyr2(const JobPack<Pyr2Job> pk, KPar
     static_cast<T *>(img ? J.dst_r : J.dst_l)[(size_t)y2 * J.wd + x2] = ok ? acc : -acc;
 }
 
+// ---------------------------------------------------------------- densify: value of one pixel
+
+// The fields of a densification that dense_value reads.
+struct DenseView {
+    const void *L, *R, *rec_u, *rec_w, *gtab, *Uc;
+    int pitch, W, H, patch, stride, nx, ny, Wc, Hc, mode;
+};
+
+// One pixel: kept covering patches in (row, column) order, weight = patch
+// posterior x spatial Gaussian at the pixel's offset in the patch (Bayesian)
+// or 1 / max(residual^2, 1) (DIS eq. (2)); U = sum(w u) / sum(w).  Uncovered:
+// NaN at level 0, zero at the coarsest level, else twice the coarse field.
+// V is a DenseJob or a DenseView: the fields the value needs.  WIDE adds the
+// fast path for three candidates per axis (borders, stride < patch / 2);
+// without it those pixels take the loop, with fewer registers live.
+template <typename T, bool U8, bool WIDE, typename V>
+__device__ __forceinline__ T dense_value(const V &J, const int x, const int y, const KParams &kp) {
+    // no contraction into FMAs: the value must be the same bits wherever it
+    // is evaluated (densify kernel, LK launch, fast path or loop)
+#pragma clang fp contract(off)
+    const int P = J.patch, st = J.stride;
+    const T *rec_u = static_cast<const T *>(J.rec_u);
+    const T *rec_w = static_cast<const T *>(J.rec_w);
+    const T *gtab = static_cast<const T *>(J.gtab);
+    auto range = [&](int v, int n, int cnt, int &lo, int &hi, int &extra) {
+        int t = v - P + 1;
+        lo = t > 0 ? (t + st - 1) / st : 0;
+        hi = min(cnt - 1, v / st);
+        extra = (hi < cnt - 1 && v >= n - P) ? cnt - 1 : -1;
+    };
+    int xlo, xhi, xex, ylo, yhi, yex;
+    range(x, J.W, J.nx, xlo, xhi, xex);
+    range(y, J.H, J.ny, ylo, yhi, yex);
+    // the fallback field's taps go out with the patch records (one round trip)
+    T Uf = 0;
+    if (J.mode == 0) Uf = T(2) * bilinear<T>(static_cast<const T *>(J.Uc), J.Wc, J.Hc, T(0.5) * (T)x, T(0.5) * (T)y);
+    T A = 0, B = 0;
+    auto add = [&](int py, int px, T wk, T uk, T g) {
+        T w;
+        if (kp.fusion == 1) {
+            size_t row0 = (size_t)y * J.pitch;
+            T uc = fmin(fmax(uk, -(T)(J.W + 2)), (T)(J.W + 2));
+            T ui = floor(uc), uf = uc - ui;
+            T res = sample_row<T, U8>(J.R, row0, J.W, x + (int)ui, uf) - pixv<T, U8>(J.L, row0 + x);
+            T q = res * res;
+            w = T(1) / (q > T(1) ? q : T(1));
+        } else {
+            w = wk * g;
+        }
+        A += w;
+        B += w * uk;
+    };
+    // Fast path: at most NC candidate patches per axis (lo .. hi, then the
+    // one snapped to the border), every record and mask load issued before
+    // the sums, which run in the same (row, column) order as the loop below.
+    // NC = 2 covers the interior at stride >= patch / 2, NC = 3 its border.
+    auto fast = [&](auto NC_) {
+        constexpr int NC = decltype(NC_)::value;
+        int px[NC], py[NC], jxs[NC], jys[NC];
+        bool vx[NC], vy[NC];
+#pragma unroll
+        for (int i = 0; i < NC; i++) {
+            int jx = i <= xhi - xlo ? xlo + i : (i == xhi - xlo + 1 ? xex : -1);
+            int jy = i <= yhi - ylo ? ylo + i : (i == yhi - ylo + 1 ? yex : -1);
+            px[i] = jx >= 0 ? grid_pos(jx, J.W, P, st) : 0;
+            py[i] = jy >= 0 ? grid_pos(jy, J.H, P, st) : 0;
+            vx[i] = jx >= 0 && x >= px[i] && x < px[i] + P;
+            vy[i] = jy >= 0 && y >= py[i] && y < py[i] + P;
+            jxs[i] = vx[i] ? jx : 0;
+            jys[i] = vy[i] ? jy : 0;
+        }
+        T wk[NC][NC], uk[NC][NC], g[NC][NC];
+#pragma unroll
+        for (int iy = 0; iy < NC; iy++)
+#pragma unroll
+            for (int ix = 0; ix < NC; ix++) {
+                const bool v = vy[iy] && vx[ix];
+                const int k = v ? jys[iy] * J.nx + jxs[ix] : 0;
+                wk[iy][ix] = rec_w[k];
+                uk[iy][ix] = rec_u[k];
+                g[iy][ix] = gtab[v ? (y - py[iy]) * P + (x - px[ix]) : 0];
+                if (!v) wk[iy][ix] = T(0);
+            }
+#pragma unroll
+        for (int iy = 0; iy < NC; iy++)
+#pragma unroll
+            for (int ix = 0; ix < NC; ix++)
+                if (wk[iy][ix] > T(0)) add(py[iy], px[ix], wk[iy][ix], uk[iy][ix], g[iy][ix]);
+    };
+    const int ncx = xhi - xlo + 1 + (xex >= 0 ? 1 : 0), ncy = yhi - ylo + 1 + (yex >= 0 ? 1 : 0);
+    if (ncx <= 2 && ncy <= 2) {
+        fast(std::integral_constant<int, 2>());
+    } else if (WIDE && ncx <= 3 && ncy <= 3) {
+        fast(std::integral_constant<int, 3>());
+    } else {
+    for (int jy = ylo; jy <= (yex >= 0 ? yex : yhi); jy++) {
+        if (jy > yhi && jy != yex) continue;
+        int py = grid_pos(jy, J.H, P, st);
+        if (y < py || y >= py + P) continue;
+        for (int jx = xlo; jx <= (xex >= 0 ? xex : xhi); jx++) {
+            if (jx > xhi && jx != xex) continue;
+            int px = grid_pos(jx, J.W, P, st);
+            if (x < px || x >= px + P) continue;
+            int k = jy * J.nx + jx;
+            T wk = rec_w[k];
+            if (!(wk > T(0))) continue;
+            add(py, px, wk, rec_u[k], gtab[(y - py) * P + (x - px)]);
+        }
+    }
+    }
+    if (A > T(0)) return B / A;
+    if (J.mode == 2) return (T)__builtin_nan("");
+    if (J.mode == 1) return 0;
+    return Uf;
+}
+
 // ---------------------------------------------------------------- LK + posterior
 
 enum { ST_KEPT = 0, ST_DEGENERATE = 1, ST_DIVERGED = 2, ST_GATED = 3 };
@@ -587,6 +724,15 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
     }
 
     const T ulo = -(T)(W + P + 2), uhi = (T)(W + 2);
+    // densification of level + 1 when this launch does it (J.rec_u1 set)
+    DenseView D;
+    D.L = D.R = nullptr;
+    D.rec_u = J.rec_u1; D.rec_w = J.rec_w1; D.gtab = J.gtab1; D.Uc = J.U2;
+    D.pitch = 0; D.W = J.Wc; D.H = J.Hc; D.patch = P; D.stride = J.stride;
+    D.nx = J.Wc < P ? 0 : (J.Wc - P + J.stride - 1) / J.stride + 1;
+    D.ny = J.Hc < P ? 0 : (J.Hc - P + J.stride - 1) / J.stride + 1;
+    D.Wc = (J.Wc + 1) / 2; D.Hc = (J.Hc + 1) / 2;
+    D.mode = J.U2 ? 0 : 1;
     // Integer part (and fraction) of a shift for the sampler.  The sampler
     // clamps the shift to [ulo, uhi]; beyond that range every column of the
     // patch row lies outside the image and reads its border pixel whatever
@@ -632,7 +778,22 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
         if (r0 == 0 && J.Uc) {
             // initial shift: twice the coarse field at the patch centre (Sec. 2.1)
             T cx = (T)x0 + T(0.5) * (T)(P - 1), cy = (T)y0 + T(0.5) * (T)(P - 1);
-            u0 = T(2) * bilinear<T>(static_cast<const T *>(J.Uc), J.Wc, J.Hc, T(0.5) * cx, T(0.5) * cy);
+            if (!J.rec_u1) {
+                u0 = T(2) * bilinear<T>(static_cast<const T *>(J.Uc), J.Wc, J.Hc, T(0.5) * cx, T(0.5) * cy);
+            } else {
+                // Level + 1 is densified here rather than by a launch of its
+                // own: the block writes its share of that field (the next
+                // level's fallback reads it) and evaluates the four bilinear
+                // taps of each patch centre itself, lane r of a segment tap
+                // r mod 4, with the same arithmetic as the densify kernel.
+                int mx, my, mx1, my1;
+                T fx, fy;
+                bilinear_taps<T>(J.Wc, J.Hc, T(0.5) * cx, T(0.5) * cy, mx, my, mx1, my1, fx, fy);
+                const int tap = r & 3;
+                const T F = dense_value<T, false, false>(D, (tap & 1) ? mx1 : mx, (tap & 2) ? my1 : my, kp);
+                const T f00 = dpp_v<0x00>(F), f01 = dpp_v<0x55>(F), f10 = dpp_v<0xAA>(F), f11 = dpp_v<0xFF>(F);
+                u0 = T(2) * bilinear_mix<T>(f00, f01, f10, f11, fx, fy);
+            }
         }
 #pragma unroll
         for (int rr = 0; rr < 8; rr++)
@@ -865,6 +1026,16 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
         J.rec_st[k] = (int8_t)status;
         static_cast<T *>(J.rec_u0)[k] = u0;
     }
+    if (J.rec_u1) {
+        // this block's share of the level-(l+1) field, which the next finer
+        // level reads where its own patches leave a pixel uncovered
+        const int n1 = J.Wc * J.Hc, nblk = J.ny * bpr, chunk = (n1 + nblk - 1) / nblk;
+        const int i1 = min(n1, (lb + 1) * chunk);
+        for (int i = lb * chunk + (int)threadIdx.x; i < i1; i += kBlock) {
+            const int yy = i / J.Wc, xx = i - yy * J.Wc;
+            static_cast<T *>(J.Uc)[i] = dense_value<T, false, true>(D, xx, yy, kp);
+        }
+    }
 }
 
 // OCC: waves per SIMD the register allocation must allow.  4 is what the
@@ -883,110 +1054,13 @@ __global__ __launch_bounds__(kBlock, OCC) void k_lk(const JobPack<LkJob> pk, KPa
 
 // ---------------------------------------------------------------- densify
 
-// One pixel: kept covering patches in (row, column) order, weight = patch
-// posterior x spatial Gaussian at the pixel's offset in the patch (Bayesian)
-// or 1 / max(residual^2, 1) (DIS eq. (2)); U = sum(w u) / sum(w).  Uncovered:
-// NaN at level 0, zero at the coarsest level, else twice the coarse field.
+// One pixel of a densification job (see dense_value).
 template <typename T, bool U8>
 __device__ __forceinline__ void dense_pixel(const DenseJob &J, const int i, const KParams &kp) {
     if (J.run_flag && *J.run_flag == 0) return;
     if (J.keep && J.keep[i]) return;
     const int y = i / J.W, x = i - y * J.W;
-    const int P = J.patch, st = J.stride;
-    const T *rec_u = static_cast<const T *>(J.rec_u);
-    const T *rec_w = static_cast<const T *>(J.rec_w);
-    const T *gtab = static_cast<const T *>(J.gtab);
-    auto range = [&](int v, int n, int cnt, int &lo, int &hi, int &extra) {
-        int t = v - P + 1;
-        lo = t > 0 ? (t + st - 1) / st : 0;
-        hi = min(cnt - 1, v / st);
-        extra = (hi < cnt - 1 && v >= n - P) ? cnt - 1 : -1;
-    };
-    int xlo, xhi, xex, ylo, yhi, yex;
-    range(x, J.W, J.nx, xlo, xhi, xex);
-    range(y, J.H, J.ny, ylo, yhi, yex);
-    // the fallback field's taps go out with the patch records (one round trip)
-    T Uf = 0;
-    if (J.mode == 0) Uf = T(2) * bilinear<T>(static_cast<const T *>(J.Uc), J.Wc, J.Hc, T(0.5) * (T)x, T(0.5) * (T)y);
-    T A = 0, B = 0;
-    auto add = [&](int py, int px, T wk, T uk, T g) {
-        T w;
-        if (kp.fusion == 1) {
-            size_t row0 = (size_t)y * J.pitch;
-            T uc = fmin(fmax(uk, -(T)(J.W + 2)), (T)(J.W + 2));
-            T ui = floor(uc), uf = uc - ui;
-            T res = sample_row<T, U8>(J.R, row0, J.W, x + (int)ui, uf) - pixv<T, U8>(J.L, row0 + x);
-            T q = res * res;
-            w = T(1) / (q > T(1) ? q : T(1));
-        } else {
-            w = wk * g;
-        }
-        A += w;
-        B += w * uk;
-    };
-    // Fast path: at most NC candidate patches per axis (lo .. hi, then the
-    // one snapped to the border), every record and mask load issued before
-    // the sums, which run in the same (row, column) order as the loop below.
-    // NC = 2 covers the interior at stride >= patch / 2, NC = 3 its border.
-    auto fast = [&](auto NC_) {
-        constexpr int NC = decltype(NC_)::value;
-        int px[NC], py[NC], jxs[NC], jys[NC];
-        bool vx[NC], vy[NC];
-#pragma unroll
-        for (int i = 0; i < NC; i++) {
-            int jx = i <= xhi - xlo ? xlo + i : (i == xhi - xlo + 1 ? xex : -1);
-            int jy = i <= yhi - ylo ? ylo + i : (i == yhi - ylo + 1 ? yex : -1);
-            px[i] = jx >= 0 ? grid_pos(jx, J.W, P, st) : 0;
-            py[i] = jy >= 0 ? grid_pos(jy, J.H, P, st) : 0;
-            vx[i] = jx >= 0 && x >= px[i] && x < px[i] + P;
-            vy[i] = jy >= 0 && y >= py[i] && y < py[i] + P;
-            jxs[i] = vx[i] ? jx : 0;
-            jys[i] = vy[i] ? jy : 0;
-        }
-        T wk[NC][NC], uk[NC][NC], g[NC][NC];
-#pragma unroll
-        for (int iy = 0; iy < NC; iy++)
-#pragma unroll
-            for (int ix = 0; ix < NC; ix++) {
-                const bool v = vy[iy] && vx[ix];
-                const int k = v ? jys[iy] * J.nx + jxs[ix] : 0;
-                wk[iy][ix] = rec_w[k];
-                uk[iy][ix] = rec_u[k];
-                g[iy][ix] = gtab[v ? (y - py[iy]) * P + (x - px[ix]) : 0];
-                if (!v) wk[iy][ix] = T(0);
-            }
-#pragma unroll
-        for (int iy = 0; iy < NC; iy++)
-#pragma unroll
-            for (int ix = 0; ix < NC; ix++)
-                if (wk[iy][ix] > T(0)) add(py[iy], px[ix], wk[iy][ix], uk[iy][ix], g[iy][ix]);
-    };
-    const int ncx = xhi - xlo + 1 + (xex >= 0 ? 1 : 0), ncy = yhi - ylo + 1 + (yex >= 0 ? 1 : 0);
-    if (ncx <= 2 && ncy <= 2) {
-        fast(std::integral_constant<int, 2>());
-    } else if (ncx <= 3 && ncy <= 3) {
-        fast(std::integral_constant<int, 3>());
-    } else {
-    for (int jy = ylo; jy <= (yex >= 0 ? yex : yhi); jy++) {
-        if (jy > yhi && jy != yex) continue;
-        int py = grid_pos(jy, J.H, P, st);
-        if (y < py || y >= py + P) continue;
-        for (int jx = xlo; jx <= (xex >= 0 ? xex : xhi); jx++) {
-            if (jx > xhi && jx != xex) continue;
-            int px = grid_pos(jx, J.W, P, st);
-            if (x < px || x >= px + P) continue;
-            int k = jy * J.nx + jx;
-            T wk = rec_w[k];
-            if (!(wk > T(0))) continue;
-            add(py, px, wk, rec_u[k], gtab[(y - py) * P + (x - px)]);
-        }
-    }
-    }
-    T U;
-    if (A > T(0)) U = B / A;
-    else if (J.mode == 2) U = (T)__builtin_nan("");
-    else if (J.mode == 1) U = 0;
-    else U = Uf;
+    const T U = dense_value<T, U8, true>(J, x, y, kp);
     if (J.out) J.out[(size_t)y * J.out_pitch + x] = (float)(-U);
     if (J.U) static_cast<T *>(J.U)[i] = U;
 }

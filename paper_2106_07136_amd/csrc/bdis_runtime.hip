@@ -237,6 +237,8 @@ struct bdis_ctx {
     // batch execution
     int batch_mode = 0;
     int wgs_per_cu = 0;
+    // densify levels >= 1 inside the next finer level's LK launch
+    bool fold_dense = true;
     hipStream_t cap_stream = nullptr;
     char *p_dev = nullptr;        // tasks | jobs | kparams | counters (+ error flag)
     size_t p_dev_bytes = 0;
@@ -472,6 +474,19 @@ void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<Launch> &l
         append(ls, K_GATE, inj, 0, false, f64, gate, kp0,
                [](const GateJob &j) { return (j.Wi * j.Hi + kBlock - 1) / kBlock; });
     }
+    // Is the densification of level l + 1 of pair p folded into p's LK launch
+    // at level l?  Not for the learned injection level (its densification
+    // completes the gate's field) nor for eq. (2)'s fusion (it reads images).
+    // Only where the LK launch is small (at most four blocks per CU, as for
+    // one pair): there the densify launch it saves costs more than the work
+    // it adds to the LK blocks; a large batch keeps its own densify launches.
+    int lk_blocks[kMaxLevels] = {0};
+    for (auto &p : pairs)
+        for (int l = 0; l < p.g.L; l++) lk_blocks[l] += p.g.ny[l] * lk_bpr(p.patch, p.g.nx[l]);
+    auto folded = [&](const PairIn &p, int l) {
+        return h->fold_dense && l >= 0 && l + 1 < p.g.L && !(lrn && l + 1 == inj) &&
+               h->prm.fusion == BDIS_FUSION_BAYES && lk_blocks[l] <= 4 * h->n_cu;
+    };
     for (int l = Lmax - 1; l >= 0; l--) {
         const bool fallback = lrn && l >= inj;  // plain level kept only as the fallback
         KParams kpl = kp0;
@@ -494,6 +509,12 @@ void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<Launch> &l
                 j.rec_u = p.ws.rec_u[l]; j.rec_w = p.ws.rec_w[l];
                 j.rec_u0 = p.ws.rec_u0[l]; j.rec_st = p.ws.rec_st[l];
                 j.run_flag = fallback ? p.ws.flag : nullptr;
+                if (folded(p, l)) {
+                    j.rec_u1 = p.ws.rec_u[l + 1]; j.rec_w1 = p.ws.rec_w[l + 1];
+                    j.gtab1 = f64 ? (const void *)(h->gtab_d + gtab_offset(p.patch))
+                                  : (const void *)(h->gtab_f + gtab_offset(p.patch));
+                    j.U2 = l + 2 < p.g.L ? p.ws.U[l + 2] : nullptr;
+                }
                 jobs.push_back(j);
             }
             KParams kpp = make_kparams(h->prm, P);
@@ -503,7 +524,7 @@ void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<Launch> &l
         }
         std::vector<DenseJob> jobs;
         for (auto &p : pairs) {
-            if (p.g.L <= l) continue;
+            if (p.g.L <= l || folded(p, l - 1)) continue;
             DenseJob j{};
             j.L = l == 0 ? (const void *)p.left : p.ws.pyr_l[l];
             j.R = l == 0 ? (const void *)p.right : p.ws.pyr_r[l];
@@ -1181,6 +1202,13 @@ bdis_status bdis_set_batch_mode(bdis_t *h, int32_t mode, int32_t wgs_per_cu) {
     h->batch_mode = mode;
     if (h->wgs_per_cu != wgs_per_cu) h->graph_key.clear();
     h->wgs_per_cu = wgs_per_cu;
+    return BDIS_OK;
+}
+
+bdis_status bdis_set_fold_densify(bdis_t *h, int32_t on) {
+    if (!h) { set_err(g_thread_err, "handle is NULL"); return BDIS_E_INVALID_ARG; }
+    if (on != 0 && on != 1) { set_err(h->err, "fold must be 0 or 1"); return BDIS_E_INVALID_ARG; }
+    h->fold_dense = on != 0;
     return BDIS_OK;
 }
 

@@ -175,3 +175,24 @@ def test_wgs_per_cu_setting(torch_cuda):
         assert h.batch_error() == 0
         for g, r in zip(got, ref):
             np.testing.assert_array_equal(_bits(g), _bits(r))
+
+
+@pytest.mark.parametrize("fusion", [0, 1])
+def test_folded_densify_matches_separate_launches(torch_cuda, fusion):
+    """Densifying level l+1 inside the LK launch of level l (the default)
+    gives every level's field and the output of one densify launch per
+    level, bit for bit (eq. (2)'s fusion keeps its own launches: same
+    result by construction)."""
+    from paper_2106_07136_amd import bdis
+    pair = synth.make_pair(640, 480, 64.0, 61)
+    L, R = torch_cuda.from_numpy(pair.left).cuda(), torch_cuda.from_numpy(pair.right).cuda()
+    res = []
+    for fold in (True, False):
+        h = bdis.Bdis(bdis.Params(levels=5, fusion=fusion))
+        h.set_fold_densify(fold)
+        out = h.compute(L, R).cpu().numpy()
+        fields = [h.debug_stage(bdis.STAGE_FIELD, l) for l in range(1, 5)]
+        res.append((out, fields))
+    np.testing.assert_array_equal(_bits(res[0][0]), _bits(res[1][0]))
+    for a, b in zip(res[0][1], res[1][1]):
+        np.testing.assert_array_equal(np.ascontiguousarray(a).view(np.uint64), np.ascontiguousarray(b).view(np.uint64))
