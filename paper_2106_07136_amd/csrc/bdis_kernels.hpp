@@ -683,8 +683,9 @@ __host__ __device__ constexpr int lk_lds_bytes() { return P * (LkShape<P>::NCMAX
 
 // Block lb of an LK job; Rs is the block's LDS staging area of
 // lk_lds_bytes<T, P>() bytes.  WN >= kp.window bounds the window samples
-// (5 for the paper's window, 9 for any allowed one).
-template <typename T, int P, bool U8, int WN = 9>
+// (5 for the paper's window, 9 for any allowed one).  FOLD compiles the
+// densification of level + 1 in (used when J.rec_u1 is set).
+template <typename T, int P, bool U8, int WN = 9, bool FOLD = false>
 __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KParams &kp, T *__restrict__ Rs) {
     using S = LkShape<P>;
     constexpr int SEG = S::SEG, PPB = S::PPB, NCMAX = S::NCMAX;
@@ -778,9 +779,9 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
         if (r0 == 0 && J.Uc) {
             // initial shift: twice the coarse field at the patch centre (Sec. 2.1)
             T cx = (T)x0 + T(0.5) * (T)(P - 1), cy = (T)y0 + T(0.5) * (T)(P - 1);
-            if (!J.rec_u1) {
+            if (!FOLD || !J.rec_u1) {
                 u0 = T(2) * bilinear<T>(static_cast<const T *>(J.Uc), J.Wc, J.Hc, T(0.5) * cx, T(0.5) * cy);
-            } else {
+            } else if constexpr (FOLD) {
                 // Level + 1 is densified here rather than by a launch of its
                 // own: the block writes its share of that field (the next
                 // level's fallback reads it) and evaluates the four bilinear
@@ -791,6 +792,15 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
                 bilinear_taps<T>(J.Wc, J.Hc, T(0.5) * cx, T(0.5) * cy, mx, my, mx1, my1, fx, fy);
                 const int tap = r & 3;
                 const T F = dense_value<T, false, false>(D, (tap & 1) ? mx1 : mx, (tap & 2) ? my1 : my, kp);
+                // this block's share of the level-(l+1) field, which the next
+                // finer level reads where its own patches leave a pixel
+                // uncovered (loads in the same round trip as the taps')
+                const int n1 = J.Wc * J.Hc, nblk = J.ny * bpr, chunk = (n1 + nblk - 1) / nblk;
+                const int i1 = min(n1, (lb + 1) * chunk);
+                for (int i = lb * chunk + (int)threadIdx.x; i < i1; i += kBlock) {
+                    const int yy = i / J.Wc, xx = i - yy * J.Wc;
+                    static_cast<T *>(J.Uc)[i] = dense_value<T, false, false>(D, xx, yy, kp);
+                }
                 const T f00 = dpp_v<0x00>(F), f01 = dpp_v<0x55>(F), f10 = dpp_v<0xAA>(F), f11 = dpp_v<0xFF>(F);
                 u0 = T(2) * bilinear_mix<T>(f00, f01, f10, f11, fx, fy);
             }
@@ -1026,21 +1036,12 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
         J.rec_st[k] = (int8_t)status;
         static_cast<T *>(J.rec_u0)[k] = u0;
     }
-    if (J.rec_u1) {
-        // this block's share of the level-(l+1) field, which the next finer
-        // level reads where its own patches leave a pixel uncovered
-        const int n1 = J.Wc * J.Hc, nblk = J.ny * bpr, chunk = (n1 + nblk - 1) / nblk;
-        const int i1 = min(n1, (lb + 1) * chunk);
-        for (int i = lb * chunk + (int)threadIdx.x; i < i1; i += kBlock) {
-            const int yy = i / J.Wc, xx = i - yy * J.Wc;
-            static_cast<T *>(J.Uc)[i] = dense_value<T, false, true>(D, xx, yy, kp);
-        }
-    }
 }
 
-// OCC: waves per SIMD the register allocation must allow.  4 is what the
-// kernel needs unconstrained; 5 trims registers (a few bytes of spill) and
-// pays off when the launch has many more blocks than the chip holds.
+// OCC: waves per SIMD the register allocation must allow.  3: small launches,
+// which may also densify the next coarser level (few blocks, so the waves fit
+// anyway); 5: launches with many more blocks than the chip holds, where
+// occupancy pays -- they never densify, so that code is left out.
 template <typename T, int P, bool U8, int WN, int OCC>
 __global__ __launch_bounds__(kBlock, OCC) void k_lk(const JobPack<LkJob> pk, KParams kp) {
     __shared__ T Rs[lk_lds_bytes<T, P>() / sizeof(T)];
@@ -1049,7 +1050,7 @@ __global__ __launch_bounds__(kBlock, OCC) void k_lk(const JobPack<LkJob> pk, KPa
     // neighbouring patch rows share an XCD; spread over the XCDs they run
     // faster although more lines come from beyond the L2.
     const LkJob &J = pk.j[find_job(pk, (int)blockIdx.x)];
-    lk_block<T, P, U8, WN>(J, (int)blockIdx.x - J.block0, kp, Rs);
+    lk_block<T, P, U8, WN, (OCC < 5)>(J, (int)blockIdx.x - J.block0, kp, Rs);
 }
 
 // ---------------------------------------------------------------- densify

@@ -25,6 +25,9 @@ constexpr int kMaxLevels = 12;
 constexpr int kSupportedPatch[] = {4, 6, 8, 10, 12, 16};
 constexpr int kMaxTuning = 8;
 constexpr int kNetLevel = 4;  // the proposal network runs on the 1/16 pyramid level
+// LK launches of at most this many blocks per CU are "small": they take the
+// three-waves-per-SIMD register budget and densify the next coarser level
+constexpr int kFoldBlocksPerCU = 3;
 
 thread_local char g_thread_err[512] = "";
 
@@ -477,15 +480,15 @@ void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<Launch> &l
     // Is the densification of level l + 1 of pair p folded into p's LK launch
     // at level l?  Not for the learned injection level (its densification
     // completes the gate's field) nor for eq. (2)'s fusion (it reads images).
-    // Only where the LK launch is small (at most four blocks per CU, as for
-    // one pair): there the densify launch it saves costs more than the work
-    // it adds to the LK blocks; a large batch keeps its own densify launches.
+    // Only where the LK launch is small (at most kFoldBlocksPerCU blocks per
+    // CU, as for one pair): there the densify launch it saves costs more than
+    // the work it adds to the LK blocks; a large batch keeps its own.
     int lk_blocks[kMaxLevels] = {0};
     for (auto &p : pairs)
         for (int l = 0; l < p.g.L; l++) lk_blocks[l] += p.g.ny[l] * lk_bpr(p.patch, p.g.nx[l]);
     auto folded = [&](const PairIn &p, int l) {
         return h->fold_dense && l >= 0 && l + 1 < p.g.L && !(lrn && l + 1 == inj) &&
-               h->prm.fusion == BDIS_FUSION_BAYES && lk_blocks[l] <= 4 * h->n_cu;
+               h->prm.fusion == BDIS_FUSION_BAYES && lk_blocks[l] <= kFoldBlocksPerCU * h->n_cu;
     };
     for (int l = Lmax - 1; l >= 0; l--) {
         const bool fallback = lrn && l >= inj;  // plain level kept only as the fallback
@@ -569,20 +572,21 @@ void launch_lk(const bdis_t *h, const Launch &L, hipStream_t s) {
     const JobPack<LkJob> &pk = pack_of<LkJob>(L);
     // one window bound per kernel (both in one kernel would cost
     // occupancy); the register-trimmed variant for launches of more than
-    // four blocks per CU, where occupancy beats per-wave latency
-    const bool big = L.blocks > 4 * h->n_cu;
+    // three blocks per CU, where occupancy beats per-wave latency (smaller
+    // launches fit at three waves per SIMD)
+    const bool big = L.blocks > kFoldBlocksPerCU * h->n_cu;
     const dim3 g(L.blocks), b(kBlock);
     if (L.kp.window <= 5) {
         if (big) {
             if (L.u8) hipLaunchKernelGGL((k_lk<T, P, true, 5, 5>), g, b, 0, s, pk, L.kp);
             else hipLaunchKernelGGL((k_lk<T, P, false, 5, 5>), g, b, 0, s, pk, L.kp);
         } else {
-            if (L.u8) hipLaunchKernelGGL((k_lk<T, P, true, 5, 4>), g, b, 0, s, pk, L.kp);
-            else hipLaunchKernelGGL((k_lk<T, P, false, 5, 4>), g, b, 0, s, pk, L.kp);
+            if (L.u8) hipLaunchKernelGGL((k_lk<T, P, true, 5, 3>), g, b, 0, s, pk, L.kp);
+            else hipLaunchKernelGGL((k_lk<T, P, false, 5, 3>), g, b, 0, s, pk, L.kp);
         }
     } else {
-        if (L.u8) hipLaunchKernelGGL((k_lk<T, P, true, 9, 4>), g, b, 0, s, pk, L.kp);
-        else hipLaunchKernelGGL((k_lk<T, P, false, 9, 4>), g, b, 0, s, pk, L.kp);
+        if (L.u8) hipLaunchKernelGGL((k_lk<T, P, true, 9, 3>), g, b, 0, s, pk, L.kp);
+        else hipLaunchKernelGGL((k_lk<T, P, false, 9, 3>), g, b, 0, s, pk, L.kp);
     }
 }
 
