@@ -196,3 +196,29 @@ def test_folded_densify_matches_separate_launches(torch_cuda, fusion):
     np.testing.assert_array_equal(_bits(res[0][0]), _bits(res[1][0]))
     for a, b in zip(res[0][1], res[1][1]):
         np.testing.assert_array_equal(np.ascontiguousarray(a).view(np.uint64), np.ascontiguousarray(b).view(np.uint64))
+
+
+def test_batch_beyond_one_job_pack(torch_cuda):
+    """60 pairs: every level's launch holds at most 24 jobs, so the batch is
+    split over several launches per level; each pair still equals its own
+    bdis_compute, in all three executions."""
+    from paper_2106_07136_amd import bdis
+    spec = [((64, 48), (97, 61), (160, 120))[i % 3] + (6.0 + (i % 5), 500 + i) for i in range(60)]
+    pairs = _pairs(torch_cuda, spec)
+    base = bdis.Params(levels=0, iters=8)
+    ref = _single(torch_cuda, base, pairs)
+    for mode in (0, 1, 2):
+        h = bdis.Bdis(base)
+        h.set_batch_mode(mode)
+        got = _run_batch(h, pairs)
+        assert h.batch_error() == 0
+        for g, r in zip(got, ref):
+            np.testing.assert_array_equal(_bits(g), _bits(r))
+
+
+def test_batch_size_limits(torch_cuda):
+    from paper_2106_07136_amd import bdis
+    h = bdis.Bdis(bdis.Params(levels=0))
+    with pytest.raises(bdis.BdisError) as e:
+        h.compute_batch([], [])
+    assert e.value.status == bdis.E_INVALID_ARG

@@ -227,3 +227,15 @@ def test_fp32_option(torch_cuda, ref, name):
     m = parity(gpu, exp)
     print(f"fp32 {name}: {m}", flush=True)
     assert m["agree"] >= 0.998 and m["frac"] >= 0.998
+
+
+def test_e2e_parity_largest_image(torch_cuda, ref):
+    """A 3840x2160 pair (disparity up to 256 px, 7 levels): the largest
+    workload shape here, every pixel against the oracle."""
+    from paper_2106_07136_amd import bdis
+    print("case 3840x2160 seed 77", flush=True)
+    pair = synth.make_pair(3840, 2160, 256.0, 77)
+    gp = bdis.Params(levels=7, iters=12)
+    _, gpu = _run(torch_cuda, gp, pair.left, pair.right)
+    exp = ref.compute(pair.left, pair.right, oracle_params(ref, gp))
+    assert_parity(gpu, exp, "3840x2160")
