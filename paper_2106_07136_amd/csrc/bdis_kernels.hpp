@@ -410,7 +410,10 @@ static_assert(2 * kP2X * kP2Y == kBlock, "one thread per (image, tile pixel)");
 
 template <typename T, bool U8>
 __global__ __launch_bounds__(kBlock) void k_pyr2(const JobPack<Pyr2Job> pk, KParams kp) {
-    __shared__ T Hs[2][kP2HY][kP2MX];
+    // from 8-bit pixels the row sums are multiples of 1/16 below 256: exact in
+    // float, so H takes half the LDS (more blocks per CU) at no cost in bits
+    using HT = std::conditional_t<U8, float, T>;
+    __shared__ HT Hs[2][kP2HY][kP2MX];
     __shared__ uint8_t Vs[2][kP2HY][kP2MX];  // bits: source pixels xc, xc + 1 valid
     __shared__ T mid[2][kP2MY][kP2MX];       // signed: sign bit = validity
     const int bid = xcd_block((int)blockIdx.x, (int)gridDim.x);
@@ -464,8 +467,8 @@ __global__ __launch_bounds__(kBlock) void k_pyr2(const JobPack<Pyr2Job> pk, KPar
         const int q = (int)threadIdx.x + it * kBlock;
         if (q < n1) {
             const int r = q / ncol, c = q - r * ncol;
-            Hs[0][r][c] = hv[it][0];
-            Hs[1][r][c] = hv[it][1];
+            Hs[0][r][c] = (HT)hv[it][0];
+            Hs[1][r][c] = (HT)hv[it][1];
             Vs[0][r][c] = (uint8_t)vb[it][0];
             Vs[1][r][c] = (uint8_t)vb[it][1];
         }
@@ -487,7 +490,7 @@ __global__ __launch_bounds__(kBlock) void k_pyr2(const JobPack<Pyr2Job> pk, KPar
         for (int img = 0; img < 2; img++) {
             T acc = 0;
 #pragma unroll
-            for (int a = 0; a < 5; a++) acc += (T)kBinom5[a] * Hs[img][2 * r + a][c];
+            for (int a = 0; a < 5; a++) acc += (T)kBinom5[a] * (T)Hs[img][2 * r + a][c];
             const bool ok = Vs[img][2 * r + 2][c] == 3u && (!row2 || Vs[img][2 * r + 3][c] == 3u);
             const T v = ok ? acc : -acc;
             mid[img][ym - vy0][xm - vx0] = v;
@@ -541,10 +544,8 @@ struct DenseView {
 // posterior x spatial Gaussian at the pixel's offset in the patch (Bayesian)
 // or 1 / max(residual^2, 1) (DIS eq. (2)); U = sum(w u) / sum(w).  Uncovered:
 // NaN at level 0, zero at the coarsest level, else twice the coarse field.
-// V is a DenseJob or a DenseView: the fields the value needs.  WIDE adds the
-// fast path for three candidates per axis (borders, stride < patch / 2);
-// without it those pixels take the loop, with fewer registers live.
-template <typename T, bool U8, bool WIDE, typename V>
+// V is a DenseJob or a DenseView: the fields the value needs.
+template <typename T, bool U8, typename V>
 __device__ __forceinline__ T dense_value(const V &J, const int x, const int y, const KParams &kp) {
     // no contraction into FMAs: the value must be the same bits wherever it
     // is evaluated (densify kernel, LK launch, fast path or loop)
@@ -581,12 +582,15 @@ __device__ __forceinline__ T dense_value(const V &J, const int x, const int y, c
         A += w;
         B += w * uk;
     };
-    // Fast path: at most NC candidate patches per axis (lo .. hi, then the
-    // one snapped to the border), every record and mask load issued before
-    // the sums, which run in the same (row, column) order as the loop below.
-    // NC = 2 covers the interior at stride >= patch / 2, NC = 3 its border.
-    auto fast = [&](auto NC_) {
-        constexpr int NC = decltype(NC_)::value;
+    // Fast path: at most two candidate patches per axis (lo .. hi, or lo and
+    // the one snapped to the border), every record and mask load issued
+    // before the sums, which run in the same (row, column) order as the loop
+    // below.  It covers the interior at stride >= patch / 2; other pixels
+    // take the loop (a wider fast path would cost occupancy: the kernel is
+    // bound by the latency of its gathers).
+    const int ncx = xhi - xlo + 1 + (xex >= 0 ? 1 : 0), ncy = yhi - ylo + 1 + (yex >= 0 ? 1 : 0);
+    if (ncx <= 2 && ncy <= 2) {
+        constexpr int NC = 2;
         int px[NC], py[NC], jxs[NC], jys[NC];
         bool vx[NC], vy[NC];
 #pragma unroll
@@ -617,12 +621,6 @@ __device__ __forceinline__ T dense_value(const V &J, const int x, const int y, c
 #pragma unroll
             for (int ix = 0; ix < NC; ix++)
                 if (wk[iy][ix] > T(0)) add(py[iy], px[ix], wk[iy][ix], uk[iy][ix], g[iy][ix]);
-    };
-    const int ncx = xhi - xlo + 1 + (xex >= 0 ? 1 : 0), ncy = yhi - ylo + 1 + (yex >= 0 ? 1 : 0);
-    if (ncx <= 2 && ncy <= 2) {
-        fast(std::integral_constant<int, 2>());
-    } else if (WIDE && ncx <= 3 && ncy <= 3) {
-        fast(std::integral_constant<int, 3>());
     } else {
     for (int jy = ylo; jy <= (yex >= 0 ? yex : yhi); jy++) {
         if (jy > yhi && jy != yex) continue;
@@ -791,7 +789,7 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
                 T fx, fy;
                 bilinear_taps<T>(J.Wc, J.Hc, T(0.5) * cx, T(0.5) * cy, mx, my, mx1, my1, fx, fy);
                 const int tap = r & 3;
-                const T F = dense_value<T, false, false>(D, (tap & 1) ? mx1 : mx, (tap & 2) ? my1 : my, kp);
+                const T F = dense_value<T, false>(D, (tap & 1) ? mx1 : mx, (tap & 2) ? my1 : my, kp);
                 // this block's share of the level-(l+1) field, which the next
                 // finer level reads where its own patches leave a pixel
                 // uncovered (loads in the same round trip as the taps')
@@ -799,7 +797,7 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
                 const int i1 = min(n1, (lb + 1) * chunk);
                 for (int i = lb * chunk + (int)threadIdx.x; i < i1; i += kBlock) {
                     const int yy = i / J.Wc, xx = i - yy * J.Wc;
-                    static_cast<T *>(J.Uc)[i] = dense_value<T, false, false>(D, xx, yy, kp);
+                    static_cast<T *>(J.Uc)[i] = dense_value<T, false>(D, xx, yy, kp);
                 }
                 const T f00 = dpp_v<0x00>(F), f01 = dpp_v<0x55>(F), f10 = dpp_v<0xAA>(F), f11 = dpp_v<0xFF>(F);
                 u0 = T(2) * bilinear_mix<T>(f00, f01, f10, f11, fx, fy);
@@ -898,6 +896,11 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
             if (c + 1 < P) jt1 += Jg[c + 1] * Tv[c + 1];
         }
         const T jt = jt0 + jt1;
+        // A and B depend on the integer part of the shift only: while an
+        // iterate stays in the same cell they are reused, and the iteration
+        // is one multiply-add on the new fraction (no LDS read, no dot)
+        int xi_prev = INT_MIN;
+        T A = 0, B = 0;
         for (int t = 0; t < kp.iters; t++) {
             T uf;
             const int xi0 = x0 + ishift(u, uf);
@@ -907,26 +910,31 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
                 // with the same f = uf:  sum_c J_c ((1 - f) R_m+c + f R_m+c+1)
                 // = A + f (B - A) with A, B the dot products of J with the
                 // taps at m + c and m + c + 1
-                const int base = rbase + xi0;
-                T v[P + 1];
+                if (xi0 != xi_prev) {
+                    const int base = rbase + xi0;
+                    T v[P + 1];
 #pragma unroll
-                for (int c = 0; c <= P; c++) {
-                    v[c] = Rs[base + c];
-                    if constexpr (!U8) v[c] = fabs(v[c]);
-                }
-                T a0 = 0, a1 = 0, b0 = 0, b1 = 0;
-#pragma unroll
-                for (int c = 0; c < P; c += 2) {
-                    a0 += Jg[c] * v[c];
-                    b0 += Jg[c] * v[c + 1];
-                    if (c + 1 < P) {
-                        a1 += Jg[c + 1] * v[c + 1];
-                        b1 += Jg[c + 1] * v[c + 2];
+                    for (int c = 0; c <= P; c++) {
+                        v[c] = Rs[base + c];
+                        if constexpr (!U8) v[c] = fabs(v[c]);
                     }
+                    T a0 = 0, a1 = 0, b0 = 0, b1 = 0;
+#pragma unroll
+                    for (int c = 0; c < P; c += 2) {
+                        a0 += Jg[c] * v[c];
+                        b0 += Jg[c] * v[c + 1];
+                        if (c + 1 < P) {
+                            a1 += Jg[c + 1] * v[c + 1];
+                            b1 += Jg[c + 1] * v[c + 2];
+                        }
+                    }
+                    A = a0 + a1;
+                    B = b0 + b1;
+                    xi_prev = xi0;
                 }
-                const T A = a0 + a1, B = b0 + b1;
                 s = A + uf * (B - A) - jt;
             } else {
+                xi_prev = INT_MIN;
                 T I[P];
                 sample(xi0, uf, I);
                 T s0 = 0, s1 = 0;
@@ -1061,7 +1069,7 @@ __device__ __forceinline__ void dense_pixel(const DenseJob &J, const int i, cons
     if (J.run_flag && *J.run_flag == 0) return;
     if (J.keep && J.keep[i]) return;
     const int y = i / J.W, x = i - y * J.W;
-    const T U = dense_value<T, U8, true>(J, x, y, kp);
+    const T U = dense_value<T, U8>(J, x, y, kp);
     if (J.out) J.out[(size_t)y * J.out_pitch + x] = (float)(-U);
     if (J.U) static_cast<T *>(J.U)[i] = U;
 }
