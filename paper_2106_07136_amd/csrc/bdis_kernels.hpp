@@ -896,23 +896,25 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
             if (c + 1 < P) jt1 += Jg[c + 1] * Tv[c + 1];
         }
         const T jt = jt0 + jt1;
-        // A and B depend on the integer part of the shift only: while an
-        // iterate stays in the same cell they are reused, and the iteration
-        // is one multiply-add on the new fraction (no LDS read, no dot)
+        // The residual sum is linear in the fraction within one cell of the
+        // shift: sum_c J_c I_c = A + f (B - A), with A (B) the dot product of
+        // J with the tap each sample takes at f = 0 (f = 1).  Inside the row
+        // those are R[m + c] and R[m + c + 1]; a column clamped to the row's
+        // first (last) pixel takes that pixel at any f, in A and in B alike.
+        // A and B depend on the integer part only, so while an iterate stays
+        // in its cell (the common case once it is within a pixel) they are
+        // reused and the iteration is one multiply-add on the new fraction.
         int xi_prev = INT_MIN;
         T A = 0, B = 0;
         for (int t = 0; t < kp.iters; t++) {
             T uf;
             const int xi0 = x0 + ishift(u, uf);
-            T s;
-            if (xi0 >= col_lo && xi0 + P <= col_hi) {
-                // staged and inside the row, so every sample interpolates
-                // with the same f = uf:  sum_c J_c ((1 - f) R_m+c + f R_m+c+1)
-                // = A + f (B - A) with A, B the dot products of J with the
-                // taps at m + c and m + c + 1
-                if (xi0 != xi_prev) {
+            if (xi0 != xi_prev) {
+                xi_prev = xi0;
+                T v[P + 1];
+                if (xi0 >= col_lo && xi0 + P <= col_hi) {
+                    // staged and inside the row: no clamping
                     const int base = rbase + xi0;
-                    T v[P + 1];
 #pragma unroll
                     for (int c = 0; c <= P; c++) {
                         v[c] = Rs[base + c];
@@ -930,21 +932,26 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
                     }
                     A = a0 + a1;
                     B = b0 + b1;
-                    xi_prev = xi0;
-                }
-                s = A + uf * (B - A) - jt;
-            } else {
-                xi_prev = INT_MIN;
-                T I[P];
-                sample(xi0, uf, I);
-                T s0 = 0, s1 = 0;
+                } else {
+                    // taps of clamped columns (LDS or global memory)
+                    fetch(xi0, v, std::integral_constant<int, P + 1>());
 #pragma unroll
-                for (int c = 0; c < P; c += 2) {
-                    s0 += Jg[c] * (I[c] - Tv[c]);
-                    if (c + 1 < P) s1 += Jg[c + 1] * (I[c + 1] - Tv[c + 1]);
+                    for (int c = 0; c <= P; c++)
+                        if constexpr (!U8) v[c] = fabs(v[c]);
+                    T a0 = 0, b0 = 0;
+#pragma unroll
+                    for (int c = 0; c < P; c++) {
+                        const int xi = xi0 + c;
+                        const T ta = xi >= W - 1 ? v[c + 1] : v[c];
+                        const T tb = xi < 0 ? v[c] : v[c + 1];
+                        a0 += Jg[c] * ta;
+                        b0 += Jg[c] * tb;
+                    }
+                    A = a0;
+                    B = b0;
                 }
-                s = s0 + s1;
             }
+            const T s = A + uf * (B - A) - jt;
             const T b = seg_sum<SEG>(s);
             step = b * invH;
             u = u - step;
