@@ -212,7 +212,8 @@ def batched_leg(batch, calib, steps, warmup, precision):
             "wgs_per_cu": tuned["wgs_per_cu"], **acc,
             "p8s4_level_graph_mpxs": mpx / (modes[0] / 1e3),
             "p8s4_direct_launches_mpxs": mpx / (modes[1] / 1e3),
-            "p8s4_persistent_kernel_mpxs": mpx / (modes[2] / 1e3), "lk_roofline_p8s4": lk_roof}
+            "p8s4_persistent_kernel_mpxs": mpx / (modes[2] / 1e3), "lk_roofline_p8s4": lk_roof,
+            "kernels_us_per_batch_p8s4": {k: t * 1e3 / steps for k, (n, t) in prof.items()}}
 
 
 def learned_leg(pairs, channels, steps, warmup, precision, workload):
