@@ -9,7 +9,9 @@ JSON line also carries:
   cpu_baseline   the FP64 CPU oracle on the host's cores (a baseline only);
   batched        64 mixed-size pairs per call, patch/stride autotuned;
   learned_640    64 held-out 640x480 pairs per call, plain vs learned init;
-  learned_mixed  32 1920x1080 + 32 640x480 pairs per call, plain vs learned.
+  learned_mixed  32 1920x1080 + 32 640x480 pairs per call, plain vs learned;
+  ablation_dis_vs_bdis  BDIS against DIS's fusion on diffuse and
+                 non-Lambertian pairs, with the paper's Table 1 statistics.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -270,6 +272,38 @@ def learned_leg(pairs, channels, steps, warmup, precision, workload):
             "sweep": {str(k): {"ms_per_batch": v[0], **v[1]} for k, v in runs.items()}}
 
 
+def ablation_leg(variants, steps, warmup, precision):
+    """BDIS against DIS's fusion (eq. (2)) on the same pairs, per generator
+    variant, with the error statistics of the paper's Table 1 (median and
+    mean end-point error over estimated pixels visible in the right image,
+    estimated pixels per frame) and the >3 px rate."""
+    import numpy as np
+
+    from paper_2106_07136_amd import bdis
+    res = {}
+    for name, pairs in variants.items():
+        L, R, O, dm = _batch_io(pairs)
+        mpx = sum(p.left.size for p in pairs) / 1e6
+        res[name] = {}
+        for fusion, label in ((0, "bdis"), (1, "dis")):
+            h = bdis.Bdis(bdis.Params(levels=0, iters=12, precision=precision, fusion=fusion))
+            ms = timed(lambda: h.compute_batch(L, R, O, max_disparity=dm), steps, warmup)
+            errs, counts = [], []
+            for o, p in zip(O, pairs):
+                d = o.cpu().numpy()
+                m = np.isfinite(d) & p.valid
+                errs.append(np.abs(d[m] - p.disp[m]))
+                counts.append(int(np.isfinite(d).sum()))
+            e = np.concatenate(errs)
+            res[name][label] = {"median_px": float(np.median(e)), "mean_px": float(e.mean()),
+                                "outliers_3px": float((e > 3).mean()),
+                                "estimated_px_per_frame": float(np.mean(counts)),
+                                "ms_per_batch": ms, "value": mpx / (ms / 1e3), "unit": "Mpixel/s"}
+            log(f"bench: ablation {name} {label}: {res[name][label]}")
+            h.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -305,7 +339,7 @@ def main():
     LEVELS, PATCH, STRIDE, ITERS = 5, 8, 4, 12
     log(f"bench: generating {W}x{H} pair seed {SEED}")
     pair = synth.make_pair(W, H, DMAX, SEED)
-    batch = calib = held = mixed = None
+    batch = calib = held = mixed = ablation = None
     if not args.no_batch:
         log("bench: generating the 64-pair mixed batch and 24 calibration pairs")
         batch = synth.make_pairs(synth.mixed_batch_spec(3000))
@@ -316,6 +350,10 @@ def main():
         held = synth.make_pairs([(640, 480, 64.0, 90000 + i) for i in range(64)])
         mixed = synth.make_pairs([(1920, 1080, 192.0, 50000 + i) for i in range(32)] +
                                  [(640, 480, 64.0, 51000 + i) for i in range(32)])
+        ablation = {
+            "diffuse": synth.make_pairs([(640, 480, 64.0, 95000 + i, dict(gain=False, specular=False))
+                                         for i in range(16)]),
+            "non_lambertian": synth.make_pairs([(640, 480, 64.0, 95100 + i) for i in range(16)])}
     dev = torch.device("cuda:0")
     L = torch.from_numpy(pair.left).to(dev)
     R = torch.from_numpy(pair.right).to(dev)
@@ -403,6 +441,11 @@ def main():
             mixed, 48, args.batch_steps, 2, args.precision,
             "32x1920x1080 (seeds 50000-50031, disparity 0-192 px) + 32x640x480 (seeds 51000-51031) pairs "
             "per call, plain vs learned init (48-channel proposal net)")
+        res["ablation_dis_vs_bdis"] = {
+            "workload": "16 640x480 pairs per variant (diffuse: no gain field, no specular blobs, seeds "
+                        "95000-95015; non-Lambertian: the full generator, seeds 95100-95115), BDIS against "
+                        "DIS's inverse-residual fusion in the same kernels",
+            **ablation_leg(ablation, args.batch_steps, 2, args.precision)}
     if not args.no_cpu:
         import oracle
         log("bench: CPU oracle baseline")

@@ -175,14 +175,15 @@ def random_pair_tiny(W: int, H: int, seed: int, lo=0, hi=256) -> tuple[np.ndarra
 
 
 def _make_one(args):
-    W, H, d, s = args
-    return make_pair(W, H, d, s)
+    W, H, d, s = args[:4]
+    return make_pair(W, H, d, s, **(args[4] if len(args) > 4 else {}))
 
 
 def make_pairs(spec, workers: int = 0):
-    """make_pair for each (W, H, d_max, seed) of spec, in order, on a pool of
-    worker processes (0 = one per CPU, at most 16).  Call it before the GPU
-    is touched in this process: workers are forked."""
+    """make_pair for each (W, H, d_max, seed[, flags]) of spec, in order, on a
+    pool of worker processes (0 = one per CPU, at most 16); flags is a dict of
+    make_pair's keyword switches.  Call it before the GPU is touched in this
+    process: workers are forked."""
     import multiprocessing as mp
     import os
     spec = list(spec)
