@@ -273,11 +273,13 @@ BDIS_API const char *bdisnet_last_error(const bdisnet_t *h);
  * writes the initial field of level learned_fine_levels: u = -4 d (d the
  * network disparity read bilinearly, the factor being the scale between the
  * 1/16 level and that level) where the confidence is >= conf_threshold.  The
- * plain levels from the coarsest down to learned_fine_levels run for a pair
- * only when some network pixel of it is below the threshold, and then
- * replace the initial field only where the confidence is low (plain
- * fallback).  The finer levels run with learned_iters LK iterations.  The
- * handle does not own the network; keep it alive while it is attached.
+ * plain levels from the coarsest down to learned_fine_levels are the
+ * fallback: they replace the initial field where the confidence is low.
+ * They run on the caller's stream while the network runs on a second stream
+ * of the handle (forked from and joined back into the caller's stream, also
+ * inside a captured graph), so the network costs no time on the path.  The
+ * finer levels run with learned_iters LK iterations.  The handle does not own
+ * the network; keep it alive while it is attached.
  * Errors: BDIS_E_INVALID_ARG (network on another device). */
 BDIS_API bdis_status bdis_set_net(bdis_t *h, bdisnet_t *net);
 

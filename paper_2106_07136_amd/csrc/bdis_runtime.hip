@@ -243,6 +243,10 @@ struct bdis_ctx {
     // densify levels >= 1 inside the next finer level's LK launch
     bool fold_dense = true;
     hipStream_t cap_stream = nullptr;
+    // second stream and its fork/join events (learned init: the network
+    // runs beside the plain coarse levels)
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     char *p_dev = nullptr;        // tasks | jobs | kparams | counters (+ error flag)
     size_t p_dev_bytes = 0;
     char *p_host = nullptr;       // pinned staging of the tables
@@ -345,7 +349,9 @@ bdis_status ensure_ws(bdis_t *h, size_t bytes) {
 }
 
 // A launch: kernel kind, template selectors and its jobs (passed by value).
-enum Kind { K_PYR2, K_LK, K_DENSE, K_NETIN, K_NET, K_GATE };
+// K_FORK / K_JOIN launch nothing: work after a fork runs on the side stream
+// (lane 1) until the join makes the main stream wait for it.
+enum Kind { K_PYR2, K_LK, K_DENSE, K_NETIN, K_NET, K_GATE, K_FORK, K_JOIN };
 struct Launch {
     Kind kind;
     int level;
@@ -355,6 +361,7 @@ struct Launch {
     int blocks;
     KParams kp;
     std::vector<char> pack;  // JobPack<Job> bytes
+    int lane = 0;            // 0: the caller's stream, 1: the side stream
 };
 
 // Splits jobs into launches of at most kMaxJobs; `blocks_of` gives a job's
@@ -465,6 +472,12 @@ void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<Launch> &l
             q.sd = -(float)(1 << (kNetLevel - inj));
             gate.push_back(q);
         }
+        // the network, its input and the gate run on the side stream,
+        // concurrently with the plain levels down to the injection level
+        // (which need nothing from it); the join comes before the injection
+        // level's densification, the first launch that reads the gate
+        ls.push_back(Launch{K_FORK, 0, 0, false, f64, 0, kp0, {}});
+        const size_t first_side = ls.size();
         append(ls, K_NETIN, kNetLevel, 0, false, f64, in, kp0,
                [](const NetInJob &j) { return (j.W * j.H + kBlock - 1) / kBlock; });
         for (const NetGroup &G : h->groups) {
@@ -476,6 +489,7 @@ void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<Launch> &l
         }
         append(ls, K_GATE, inj, 0, false, f64, gate, kp0,
                [](const GateJob &j) { return (j.Wi * j.Hi + kBlock - 1) / kBlock; });
+        for (size_t i = first_side; i < ls.size(); i++) ls[i].lane = 1;
     }
     // Is the densification of level l + 1 of pair p folded into p's LK launch
     // at level l?  Not for the learned injection level (its densification
@@ -490,8 +504,12 @@ void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<Launch> &l
         return h->fold_dense && l >= 0 && l + 1 < p.g.L && !(lrn && l + 1 == inj) &&
                h->prm.fusion == BDIS_FUSION_BAYES && lk_blocks[l] <= kFoldBlocksPerCU * h->n_cu;
     };
+    bool joined = false;
     for (int l = Lmax - 1; l >= 0; l--) {
-        const bool fallback = lrn && l >= inj;  // plain level kept only as the fallback
+        // With the learned init the plain levels down to the injection level
+        // are the fallback.  They run whether or not the gate will need them
+        // (so that they overlap the network), except that at the injection
+        // level the densification fills only the pixels the gate left.
         KParams kpl = kp0;
         if (lrn && l < inj) kpl.iters = h->prm.learned_iters;
         for (int P : kSupportedPatch) {
@@ -511,7 +529,7 @@ void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<Launch> &l
                 j.reach = (int)std::ceil(std::max(0.f, p.dmax) / (float)(1 << l)) + 1;
                 j.rec_u = p.ws.rec_u[l]; j.rec_w = p.ws.rec_w[l];
                 j.rec_u0 = p.ws.rec_u0[l]; j.rec_st = p.ws.rec_st[l];
-                j.run_flag = fallback ? p.ws.flag : nullptr;
+                j.run_flag = nullptr;
                 if (folded(p, l)) {
                     j.rec_u1 = p.ws.rec_u[l + 1]; j.rec_w1 = p.ws.rec_w[l + 1];
                     j.gtab1 = f64 ? (const void *)(h->gtab_d + gtab_offset(p.patch))
@@ -524,6 +542,10 @@ void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<Launch> &l
             kpp.iters = kpl.iters;
             append(ls, K_LK, l, P, l == 0, f64, jobs, kpp,
                    [P](const LkJob &j) { return j.ny * lk_bpr(P, j.nx); });
+        }
+        if (lrn && l == inj) {
+            ls.push_back(Launch{K_JOIN, 0, 0, false, f64, 0, kp0, {}});
+            joined = true;
         }
         std::vector<DenseJob> jobs;
         for (auto &p : pairs) {
@@ -546,7 +568,7 @@ void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<Launch> &l
             j.U = l == 0 ? nullptr : p.ws.U[l];
             j.out = l == 0 ? p.disp : nullptr;
             j.out_pitch = p.dpitch;
-            j.run_flag = fallback ? p.ws.flag : nullptr;
+            j.run_flag = nullptr;
             j.keep = (lrn && l == inj) ? p.ws.keep : nullptr;
             j.ppt = 1;
             jobs.push_back(j);
@@ -554,6 +576,7 @@ void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<Launch> &l
         append(ls, K_DENSE, l, 0, l == 0, f64, jobs, kp0,
                [](const DenseJob &j) { return dense_blocks(j.W, j.H, j.ppt); });
     }
+    if (lrn && !joined) ls.push_back(Launch{K_JOIN, 0, 0, false, f64, 0, kp0, {}});  // every fork is joined
 }
 
 // kernel arguments are limited to 4 KiB
@@ -606,6 +629,9 @@ void launch_one(bdis_t *h, const Launch &L, hipStream_t s) {
     case K_GATE:
         hipLaunchKernelGGL(k_gate<T>, dim3(L.blocks), dim3(kBlock), 0, s, pack_of<GateJob>(L));
         break;
+    case K_FORK:
+    case K_JOIN:
+        break;  // stream ordering only (launch_all)
     case K_PYR2: {
         const JobPack<Pyr2Job> &pk = pack_of<Pyr2Job>(L);
         if (L.u8) hipLaunchKernelGGL((k_pyr2<T, true>), dim3(L.blocks), dim3(kBlock), 0, s, pk, L.kp);
@@ -645,7 +671,7 @@ std::string launch_name(const Launch &L) {
     return buf;
 }
 
-void launch_all(bdis_t *h, const std::vector<Launch> &ls, hipStream_t s);
+bdis_status launch_all(bdis_t *h, const std::vector<Launch> &ls, hipStream_t s);
 
 hipEvent_t take_event(bdis_t *h) {
     if (!h->spare.empty()) {
@@ -658,21 +684,36 @@ hipEvent_t take_event(bdis_t *h) {
     return e;
 }
 
-void launch_all(bdis_t *h, const std::vector<Launch> &ls, hipStream_t s) {
+bdis_status launch_all(bdis_t *h, const std::vector<Launch> &ls, hipStream_t s) {
     for (const Launch &L : ls) {
+        if (L.kind == K_FORK || L.kind == K_JOIN) {
+            if (!h->side) HIPCHK(h, hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+            if (!h->ev_fork) HIPCHK(h, hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+            if (!h->ev_join) HIPCHK(h, hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+            if (L.kind == K_FORK) {
+                HIPCHK(h, hipEventRecord(h->ev_fork, s));
+                HIPCHK(h, hipStreamWaitEvent(h->side, h->ev_fork, 0));
+            } else {
+                HIPCHK(h, hipEventRecord(h->ev_join, h->side));
+                HIPCHK(h, hipStreamWaitEvent(s, h->ev_join, 0));
+            }
+            continue;
+        }
+        const hipStream_t ls_ = L.lane ? h->side : s;
         hipEvent_t a = nullptr, b = nullptr;
         if (h->profiling) {
             a = take_event(h);
             b = take_event(h);
-            if (a && b) (void)hipEventRecord(a, s);
+            if (a && b) (void)hipEventRecord(a, ls_);
         }
-        if (L.f64) launch_one<double>(h, L, s);
-        else launch_one<float>(h, L, s);
+        if (L.f64) launch_one<double>(h, L, ls_);
+        else launch_one<float>(h, L, ls_);
         if (h->profiling && a && b) {
-            (void)hipEventRecord(b, s);
+            (void)hipEventRecord(b, ls_);
             h->pending.push_back({launch_name(L), a, b});
         }
     }
+    return BDIS_OK;
 }
 
 void pick_tuning(const bdis_t *h, int W, int &patch, int &stride) {
@@ -925,12 +966,21 @@ bdis_status run_level_graph(bdis_t *h, const std::vector<Launch> &ls, hipStream_
     }
     if (key != h->lv_key || !h->lv_exec) {
         if (!h->cap_stream) HIPCHK(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+        // the fork/join stream and events exist before the capture begins
+        if (!h->side) HIPCHK(h, hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+        if (!h->ev_fork) HIPCHK(h, hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+        if (!h->ev_join) HIPCHK(h, hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
         const bool prof = h->profiling;
         h->profiling = false;  // no event records inside the captured graph
         HIPCHK(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-        launch_all(h, ls, h->cap_stream);
+        const bdis_status la = launch_all(h, ls, h->cap_stream);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+        if (la != BDIS_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            h->profiling = prof;
+            return la;
+        }
         h->profiling = prof;
         if (e != hipSuccess) { set_err(h->err, "graph capture failed: %s", hipGetErrorString(e)); return BDIS_E_HIP; }
         bool updated = false;
@@ -1025,7 +1075,8 @@ bdis_status run(bdis_t *h, std::vector<PairIn> &pairs, hipStream_t s, int mode =
     std::vector<Launch> ls;
     plan_launches(h, pairs, ls);
     if (mode == 0) return run_level_graph(h, ls, s);
-    launch_all(h, ls, s);
+    bdis_status st2 = launch_all(h, ls, s);
+    if (st2 != BDIS_OK) return st2;
     HIPCHK(h, hipGetLastError());
     return BDIS_OK;
 }
@@ -1286,7 +1337,8 @@ bdis_status bdis_net_input(bdis_t *h, const bdis_pair *pairs, int32_t n, uint16_
     }
     append(ls, K_NETIN, kNetLevel, 0, false, f64, in, kp0,
            [](const NetInJob &j) { return (j.W * j.H + kBlock - 1) / kBlock; });
-    launch_all(h, ls, (hipStream_t)stream);
+    bdis_status st3 = launch_all(h, ls, (hipStream_t)stream);
+    if (st3 != BDIS_OK) return st3;
     HIPCHK(h, hipGetLastError());
     return BDIS_OK;
 }
@@ -1391,6 +1443,9 @@ void bdis_destroy(bdis_t *h) {
         if (h->graph) (void)hipGraphDestroy(h->graph);
         if (h->lv_exec) (void)hipGraphExecDestroy(h->lv_exec);
         if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+        if (h->side) (void)hipStreamDestroy(h->side);
+        if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+        if (h->ev_join) (void)hipEventDestroy(h->ev_join);
         if (h->p_dev) (void)hipFree(h->p_dev);
         if (h->p_host) (void)hipHostFree(h->p_host);
         if (h->p_upload_ev) (void)hipEventDestroy(h->p_upload_ev);
