@@ -403,10 +403,10 @@ def main():
         peak = PEAK_FP64_VECTOR if args.precision == 0 else PEAK_FP32_VECTOR
         coarse = info["width"][lvl + 1] * info["height"][lvl + 1] if lvl + 1 < info["levels"] else 0
         # the library folds the next level's densification into small LK
-        # launches (at most four blocks per CU)
+        # launches (at most three blocks per CU)
         bpr = -(-info["nx"][lvl] // (256 // 8))
         fold = None
-        if coarse and info["ny"][lvl] * bpr <= 4 * torch.cuda.get_device_properties(0).multi_processor_count:
+        if coarse and info["ny"][lvl] * bpr <= 3 * torch.cuda.get_device_properties(0).multi_processor_count:
             px2 = info["width"][lvl + 2] * info["height"][lvl + 2] if lvl + 2 < info["levels"] else 0
             fold = (info["nx"][lvl + 1] * info["ny"][lvl + 1], px2)
             fl += dense_flops(coarse, 4 * npatch)

@@ -170,7 +170,7 @@ BDIS_API bdis_status bdis_set_batch_mode(bdis_t *h, int32_t mode, int32_t wgs_pe
  * inside the next finer level's LK launch -- each block writes its share of
  * the coarser field and evaluates its patches' initial-shift taps itself --
  * so a pair of L levels takes L + 1 launches after the pyramid instead of 2 L.
- * It applies to the Bayesian fusion and to LK launches of at most four blocks
+ * It applies to the Bayesian fusion and to LK launches of at most three blocks
  * per compute unit (one pair: latency-bound); large batches, the learned
  * injection level and eq. (2)'s fusion keep their own densify launch.  on = 0:
  * one densify launch per level.  Results are the same either way, bit for bit.  Errors:
