@@ -179,6 +179,15 @@ __device__ __forceinline__ int xcd_block(int bid, int n) {
     return x * q + (x < r ? x : r) + k;
 }
 
+// q / n for 0 <= q < 2^31 and n >= 1, given inv = 1.0 / n (correctly
+// rounded double).  (q + 0.5) / n lies at least 0.5 / n from an integer, and
+// the two roundings move it by at most (q + 0.5) / n * 2^-52 < 0.5 / n, so
+// truncation gives the integer quotient: four full-rate instructions instead
+// of an integer division's expansion.
+__device__ __forceinline__ int div_exact(int q, double inv) {
+    return (int)(((double)q + 0.5) * inv);
+}
+
 // reflect101 for -n < i < 2 n - 1 (one reflection suffices), n >= 2
 __device__ __forceinline__ int reflect101_near(int i, int n) {
     i = i < 0 ? -i : i;
@@ -434,39 +443,51 @@ __global__ __launch_bounds__(kBlock) void k_pyr2(const JobPack<Pyr2Job> pk, KPar
     // every load of the thread is in flight before the first sum.
     constexpr int NQ1 = (kP2HY * kP2MX + kBlock - 1) / kBlock;
     const int n1 = nhrow * ncol;
-    // every tap is within 2 of the image (one reflection) unless a side < 3
-    const bool near = J.ws >= 3 && J.hs >= 3;
-    auto refl = [&](int i, int n) { return near ? reflect101_near(i, n) : reflect101(i, n); };
+    // q / ncol for the region's small indices without an integer division
+    const double inv_ncol = 1.0 / (double)ncol;
+    auto row_of = [&](int q) { return div_exact(q, inv_ncol); };
     T hv[NQ1][2];
     uint32_t vb[NQ1][2];  // validity of the source pixels at columns xc, xc + 1 of the row
+    // every tap is within 2 of the image (one reflection) unless a side < 3:
+    // one uniform branch picks a straight-line copy of the loop, so that
+    // every load of the thread goes out back to back
+    auto pass1 = [&](auto NEAR_) {
+        constexpr bool NEAR = decltype(NEAR_)::value;
+        auto refl = [&](int i, int n) {
+            if constexpr (NEAR) return reflect101_near(i, n);
+            else return reflect101(i, n);
+        };
 #pragma unroll
-    for (int it = 0; it < NQ1; it++) {
-        const int q = min((int)threadIdx.x + it * kBlock, n1 - 1);
-        const int r = q / ncol, c = q - r * ncol;
-        const size_t r0 = (size_t)refl(2 * ya - 2 + r, J.hs) * J.src_pitch;
-        const int xc = 2 * (xa + c);
+        for (int it = 0; it < NQ1; it++) {
+            const int q = min((int)threadIdx.x + it * kBlock, n1 - 1);
+            const int r = row_of(q), c = q - r * ncol;
+            const size_t r0 = (size_t)refl(2 * ya - 2 + r, J.hs) * J.src_pitch;
+            const int xc = 2 * (xa + c);
 #pragma unroll
-        for (int img = 0; img < 2; img++) {
-            const void *src = img ? J.src_r : J.src_l;
-            T h = 0;
-            uint32_t bits = 0;
+            for (int img = 0; img < 2; img++) {
+                const void *src = img ? J.src_r : J.src_l;
+                T h = 0;
+                uint32_t bits = 0;
 #pragma unroll
-            for (int b = 0; b < 5; b++) {
-                bool v;
-                const T x = pix<T, U8>(src, r0 + refl(xc + b - 2, J.ws), kp, v);
-                h += (T)kBinom5[b] * x;
-                if (b == 2) bits |= v ? 1u : 0u;
-                if (b == 3) bits |= (v || xc + 1 >= J.ws) ? 2u : 0u;  // a missing child counts as valid
+                for (int b = 0; b < 5; b++) {
+                    bool v;
+                    const T x = pix<T, U8>(src, r0 + refl(xc + b - 2, J.ws), kp, v);
+                    h += (T)kBinom5[b] * x;
+                    if (b == 2) bits |= v ? 1u : 0u;
+                    if (b == 3) bits |= (v || xc + 1 >= J.ws) ? 2u : 0u;  // a missing child counts as valid
+                }
+                hv[it][img] = h;
+                vb[it][img] = bits;
             }
-            hv[it][img] = h;
-            vb[it][img] = bits;
         }
-    }
+    };
+    if (J.ws >= 3 && J.hs >= 3) pass1(std::true_type());
+    else pass1(std::false_type());
 #pragma unroll
     for (int it = 0; it < NQ1; it++) {
         const int q = (int)threadIdx.x + it * kBlock;
         if (q < n1) {
-            const int r = q / ncol, c = q - r * ncol;
+            const int r = row_of(q), c = q - r * ncol;
             Hs[0][r][c] = (HT)hv[it][0];
             Hs[1][r][c] = (HT)hv[it][1];
             Vs[0][r][c] = (uint8_t)vb[it][0];
@@ -482,7 +503,7 @@ __global__ __launch_bounds__(kBlock) void k_pyr2(const JobPack<Pyr2Job> pk, KPar
     for (int it = 0; it < NQ2; it++) {
         const int q = (int)threadIdx.x + it * kBlock;
         if (q >= n2) continue;
-        const int r = q / ncol, c = q - r * ncol;
+        const int r = row_of(q), c = q - r * ncol;
         const int ym = ya + r, xm = xa + c;
         const bool own = ym >= 2 * y2_0 && ym < 2 * y2_0 + 2 * kP2Y && xm >= 2 * x2_0 && xm < 2 * x2_0 + 2 * kP2X;
         const bool row2 = 2 * ym + 1 < J.hs;
@@ -554,10 +575,11 @@ __device__ __forceinline__ T dense_value(const V &J, const int x, const int y, c
     const T *rec_u = static_cast<const T *>(J.rec_u);
     const T *rec_w = static_cast<const T *>(J.rec_w);
     const T *gtab = static_cast<const T *>(J.gtab);
+    const double inv_st = 1.0 / (double)st;
     auto range = [&](int v, int n, int cnt, int &lo, int &hi, int &extra) {
         int t = v - P + 1;
-        lo = t > 0 ? (t + st - 1) / st : 0;
-        hi = min(cnt - 1, v / st);
+        lo = t > 0 ? div_exact(t + st - 1, inv_st) : 0;
+        hi = min(cnt - 1, div_exact(v, inv_st));
         extra = (hi < cnt - 1 && v >= n - P) ? cnt - 1 : -1;
     };
     int xlo, xhi, xex, ylo, yhi, yex;
@@ -795,8 +817,9 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
                 // uncovered (loads in the same round trip as the taps')
                 const int n1 = J.Wc * J.Hc, nblk = J.ny * bpr, chunk = (n1 + nblk - 1) / nblk;
                 const int i1 = min(n1, (lb + 1) * chunk);
+                const double inv_wc = 1.0 / (double)J.Wc;
                 for (int i = lb * chunk + (int)threadIdx.x; i < i1; i += kBlock) {
-                    const int yy = i / J.Wc, xx = i - yy * J.Wc;
+                    const int yy = div_exact(i, inv_wc), xx = i - yy * J.Wc;
                     static_cast<T *>(J.Uc)[i] = dense_value<T, false>(D, xx, yy, kp);
                 }
                 const T f00 = dpp_v<0x00>(F), f01 = dpp_v<0x55>(F), f10 = dpp_v<0xAA>(F), f11 = dpp_v<0xFF>(F);
@@ -895,23 +918,29 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
             jt0 += Jg[c] * Tv[c];
             if (c + 1 < P) jt1 += Jg[c + 1] * Tv[c + 1];
         }
-        const T jt = jt0 + jt1;
+        // sum J T over the patch (constant over the iterations)
+        const T JT = seg_sum<SEG>(jt0 + jt1);
         // The residual sum is linear in the fraction within one cell of the
-        // shift: sum_c J_c I_c = A + f (B - A), with A (B) the dot product of
-        // J with the tap each sample takes at f = 0 (f = 1).  Inside the row
-        // those are R[m + c] and R[m + c + 1]; a column clamped to the row's
-        // first (last) pixel takes that pixel at any f, in A and in B alike.
-        // A and B depend on the integer part only, so while an iterate stays
-        // in its cell (the common case once it is within a pixel) they are
-        // reused and the iteration is one multiply-add on the new fraction.
+        // shift: sum J I = A + f (B - A) over the patch, with A (B) the dot
+        // product of J with the tap each sample takes at f = 0 (f = 1).
+        // Inside the row those are R[m + c] and R[m + c + 1]; a column
+        // clamped to the row's first (last) pixel takes that pixel at any f,
+        // in A and in B alike.  A and B depend on the integer part only and f
+        // is the same in every row, so they are reduced over the patch when
+        // the iterate enters a cell, SA = A - sum J T and SD = B - A, and
+        // every iteration in that cell (the common case once it is within a
+        // pixel) is sum J e = SA + f SD: no cross-lane step, no LDS read.
+        // The shift is the same in every lane of a segment (it comes from
+        // segment totals), so the cell test is uniform per segment and the
+        // reduction inside it sees its whole segment active.
         int xi_prev = INT_MIN;
-        T A = 0, B = 0;
+        T SA = 0, SD = 0;
         for (int t = 0; t < kp.iters; t++) {
             T uf;
             const int xi0 = x0 + ishift(u, uf);
             if (xi0 != xi_prev) {
                 xi_prev = xi0;
-                T v[P + 1];
+                T v[P + 1], A, B;
                 if (xi0 >= col_lo && xi0 + P <= col_hi) {
                     // staged and inside the row: no clamping
                     const int base = rbase + xi0;
@@ -950,10 +979,12 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
                     A = a0;
                     B = b0;
                 }
+                T ab[2] = {A, B};
+                seg_sum_n<SEG, 2>(ab);
+                SA = ab[0] - JT;
+                SD = ab[1] - ab[0];
             }
-            const T s = A + uf * (B - A) - jt;
-            const T b = seg_sum<SEG>(s);
-            step = b * invH;
+            step = (SA + uf * SD) * invH;
             u = u - step;
         }
         const bool unconverged = kp.conv_tol > 0 && kp.iters > 0 && !(fabs(step) <= (T)kp.conv_tol);
@@ -1075,7 +1106,7 @@ template <typename T, bool U8>
 __device__ __forceinline__ void dense_pixel(const DenseJob &J, const int i, const KParams &kp) {
     if (J.run_flag && *J.run_flag == 0) return;
     if (J.keep && J.keep[i]) return;
-    const int y = i / J.W, x = i - y * J.W;
+    const int y = div_exact(i, 1.0 / (double)J.W), x = i - y * J.W;
     const T U = dense_value<T, U8>(J, x, y, kp);
     if (J.out) J.out[(size_t)y * J.out_pitch + x] = (float)(-U);
     if (J.U) static_cast<T *>(J.U)[i] = U;
