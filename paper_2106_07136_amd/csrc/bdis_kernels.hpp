@@ -673,7 +673,9 @@ enum { ST_KEPT = 0, ST_DEGENERATE = 1, ST_DIVERGED = 2, ST_GATED = 3 };
 template <int P> struct LkShape {
     static constexpr int SEG = P <= 8 ? 8 : 16;  // lanes per patch (one per patch row)
     static constexpr int PPB = kBlock / SEG;     // patches per block, one patch row
-    static constexpr int NCMAX = 384;            // staged columns per image row
+    static constexpr int NCROW = 385;            // LDS row stride, elements
+    static constexpr int PADC = P + 1;           // columns staged beyond each end of the span
+    static constexpr int NCMAX = NCROW - 1 - 2 * PADC;  // widest span of image columns
 };
 
 template <int P>
@@ -686,7 +688,10 @@ __host__ __device__ constexpr int lk_blocks_per_row(int nx) {
 // initial shifts reach, plus a margin of P + 2 (a kept patch ends within P
 // of its start; the window adds 1), so every LK iteration and window sample
 // reads LDS; an iterate outside the staged span reads global memory instead,
-// with the same values.
+// with the same values.  The span is staged with P + 1 more columns at each
+// end, indices clamped to the row: where it meets the image border those
+// hold the border pixel, so a sample that the linear sampler clamps (Sec.
+// 2.1, eq. (1)) reads the same LDS run as any other.
 //
 // One patch per segment of SEG lanes, one patch row per lane (lanes >= P of a
 // 16-lane segment idle).  Per lane: the template row, the mean-normalised
@@ -699,7 +704,7 @@ __host__ __device__ constexpr int lk_blocks_per_row(int nx) {
 // energies E_i = sum (d - mean d)^2 at u + (i - c) step, the posterior
 // p = 1 / sum_i exp(-(E_i - E_c) / tau) (eqs. (3)-(4)) and the gamma gate.
 template <typename T, int P>
-__host__ __device__ constexpr int lk_lds_bytes() { return P * (LkShape<P>::NCMAX + 1) * (int)sizeof(T); }
+__host__ __device__ constexpr int lk_lds_bytes() { return P * LkShape<P>::NCROW * (int)sizeof(T); }
 
 // Block lb of an LK job; Rs is the block's LDS staging area of
 // lk_lds_bytes<T, P>() bytes.  WN >= kp.window bounds the window samples
@@ -708,8 +713,7 @@ __host__ __device__ constexpr int lk_lds_bytes() { return P * (LkShape<P>::NCMAX
 template <typename T, int P, bool U8, int WN = 9, bool FOLD = false>
 __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KParams &kp, T *__restrict__ Rs) {
     using S = LkShape<P>;
-    constexpr int SEG = S::SEG, PPB = S::PPB, NCMAX = S::NCMAX;
-    constexpr int NCPAD = NCMAX + 1;
+    constexpr int SEG = S::SEG, PPB = S::PPB, NCMAX = S::NCMAX, NCROW = S::NCROW, PADC = S::PADC;
     if (J.run_flag && *J.run_flag == 0) return;  // uniform over the block
 
     const int W = J.W;
@@ -770,17 +774,36 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
     // go out with the template and init loads: disparities d >= 0 shift the
     // right sample left (u = -d), so the span reaches `reach` columns left of
     // the first patch and a margin of P + 2 on both sides.
+    // The rest of the NCMAX columns (they cost no extra load instruction:
+    // the chunks are sized for NCMAX) widen the span on both sides, so that
+    // an iterate that wanders beyond the expected disparities on its way
+    // still reads LDS: every iteration outside the span is a round trip to
+    // memory, and one such patch holds up its wave and its block.
     const int xf = grid_pos(jx0, W, P, J.stride);
     const int xl = grid_pos(min(jx0 + PPB, J.nx) - 1, W, P, J.stride);
     int col_hi = min(W - 1, xl + P + (P + 2));
     int col_lo = max(0, xf - J.reach - (P + 2));
     col_lo = max(col_lo, col_hi - NCMAX + 1);
-    const int nc = col_hi - col_lo + 1;
+    {
+        // spare columns: half to each side where the row allows, the rest
+        // to the side that has room (0 <= col_lo <= col_hi <= W - 1 and at
+        // most NCMAX columns hold throughout)
+        const int extra = NCMAX - (col_hi - col_lo + 1);
+        int left = min(col_lo, extra / 2);
+        const int right = min(W - 1 - col_hi, extra - left);
+        left = min(col_lo, extra - right);
+        col_lo -= left;
+        col_hi += right;
+    }
+    // LDS row r holds R[clamp(k, 0, W - 1)] for the virtual columns
+    // k = vlo .. vhi at index k - vlo
+    const int vlo = col_lo - PADC, vhi = col_hi + PADC;
+    const int nst = vhi - vlo + 1;
     // rows in passes of up to 8, columns in chunks of kBlock: every load of a
     // pass is issued before the LDS writes (one memory round trip per pass);
     // the first pass's loads go out before the initial shift waits for its
     // own, so template, staging and init share one round trip
-    constexpr int CH = (NCMAX + kBlock - 1) / kBlock;
+    constexpr int CH = (NCROW - 1 + kBlock - 1) / kBlock;
 #pragma unroll
     for (int r0 = 0; r0 < P; r0 += 8) {
         T buf[8][CH];
@@ -790,8 +813,8 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
             for (int q = 0; q < CH; q++) {
                 int cc = (int)threadIdx.x + q * kBlock;
                 buf[rr][q] = T(0);
-                if (r0 + rr < P && cc < nc) {
-                    size_t g = (size_t)(y0 + r0 + rr) * J.pitch + (size_t)(col_lo + cc);
+                if (r0 + rr < P && cc < nst) {
+                    size_t g = (size_t)(y0 + r0 + rr) * J.pitch + (size_t)min(max(vlo + cc, 0), W - 1);
                     if constexpr (U8) buf[rr][q] = (T) static_cast<const uint8_t *>(J.R)[g];
                     else buf[rr][q] = static_cast<const T *>(J.R)[g];
                 }
@@ -831,61 +854,69 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
 #pragma unroll
             for (int q = 0; q < CH; q++) {
                 int cc = (int)threadIdx.x + q * kBlock;
-                if (r0 + rr < P && cc < nc) Rs[(r0 + rr) * NCPAD + cc] = buf[rr][q];
+                if (r0 + rr < P && cc < nst) Rs[(r0 + rr) * NCROW + cc] = buf[rr][q];
             }
     }
     __syncthreads();
 
-    // LDS index of column c of this lane's staged row is rbase + c, which is
-    // >= 0 exactly for the staged columns c >= col_lo (the array is only ever
-    // indexed, never offset before its start)
-    const int rbase = (row_on ? r : 0) * NCPAD - col_lo;
+    // LDS index of virtual column k of this lane's staged row is rbase + k,
+    // which is >= 0 exactly for k >= vlo (the array is only ever indexed,
+    // never offset before its start)
+    const int rbase = (row_on ? r : 0) * NCROW - vlo;
     // raw right values (sign = validity above level 0) of columns
     // clamp(c0 + c, 0, W-1), c = 0..N-1: all reads issued back to back, from
     // LDS when the whole span is staged, else from global memory
     auto fetch = [&](int c0, T *v, auto N_) {
         constexpr int N = decltype(N_)::value;
-        const bool staged = max(c0, 0) >= col_lo && min(c0 + N - 1, W - 1) <= col_hi;
-        if (staged) {
+        // Every value is read from LDS (indices kept inside the staged span),
+        // and only the columns outside the span are then reloaded from
+        // global memory.  The two reads stay distinct instructions: written as
+        // alternatives, the compiler merges them into one flat load through a
+        // generic pointer, which costs a memory round trip even for LDS.
+        int idx[N];
 #pragma unroll
-            for (int c = 0; c < N; c++) v[c] = Rs[rbase + min(max(c0 + c, 0), W - 1)];
-        } else {
+        for (int c = 0; c < N; c++) {
+            idx[c] = min(max(c0 + c, 0), W - 1);
+            v[c] = Rs[rbase + min(max(idx[c], vlo), vhi)];
+        }
+        const bool staged = max(c0, 0) >= vlo && min(c0 + N - 1, W - 1) <= vhi;
+        if (!staged) {
 #pragma unroll
             for (int c = 0; c < N; c++) {
-                size_t g = row0 + (size_t)min(max(c0 + c, 0), W - 1);
+                if (idx[c] >= vlo && idx[c] <= vhi) continue;
+                const size_t g = row0 + (size_t)idx[c];
                 if constexpr (U8) v[c] = (T) static_cast<const uint8_t *>(J.R)[g];
                 else v[c] = static_cast<const T *>(J.R)[g];
             }
         }
     };
+    // Intensities R[clamp(xi0 + c, 0, W - 1)], c = 0..P, of this lane's row.
+    // A start left of -(P + 1) or right of W - 1 gives the same values as
+    // that bound (every column clamps to the border), so the clamped start
+    // reads one contiguous run of the staged row; only a run that leaves the
+    // staged span takes the per-column path.
+    auto load_run = [&](int xi0, T *v) {
+        const int xc = min(max(xi0, -(P + 1)), W - 1);
+        if (xc >= vlo && xc + P <= vhi) {
+            const int base = rbase + xc;
+#pragma unroll
+            for (int c = 0; c <= P; c++) v[c] = Rs[base + c];
+        } else {
+            fetch(xi0, v, std::integral_constant<int, P + 1>());
+        }
+#pragma unroll
+        for (int c = 0; c <= P; c++)
+            if constexpr (!U8) v[c] = fabs(v[c]);
+    };
     // I_r at x0 + c + shift for the patch row, shift = xi0 - x0 + uf with
-    // 0 <= uf < 1, coordinate clamped to [0, W-1]: left of the row f = 0,
-    // right of it f = 1, inside (1 - f) R[m] + f R[m + 1]
+    // 0 <= uf < 1, coordinate clamped to [0, W-1]: (1 - f) R[m] + f R[m + 1]
+    // on the clamped taps, which for a clamped column are the same pixel
     auto sample = [&](int xi0, T uf, T *out) {
-        if (xi0 >= col_lo && xi0 + P <= col_hi) {
-            // whole span staged and inside the row: f = uf everywhere
-            const int base = rbase + xi0;
-            const T omf = T(1) - uf;
-            T v[P + 1];
-#pragma unroll
-            for (int c = 0; c <= P; c++) {
-                v[c] = Rs[base + c];
-                if constexpr (!U8) v[c] = fabs(v[c]);
-            }
-#pragma unroll
-            for (int c = 0; c < P; c++) out[c] = omf * v[c] + uf * v[c + 1];
-            return;
-        }
         T v[P + 1];
-        fetch(xi0, v, std::integral_constant<int, P + 1>());
+        load_run(xi0, v);
+        const T omf = T(1) - uf;
 #pragma unroll
-        for (int c = 0; c <= P; c++) if constexpr (!U8) v[c] = fabs(v[c]);
-#pragma unroll
-        for (int c = 0; c < P; c++) {
-            int xi = xi0 + c;
-            T f = xi < 0 ? T(0) : (xi >= W - 1 ? T(1) : uf);
-            out[c] = (T(1) - f) * v[c] + f * v[c + 1];
-        }
+        for (int c = 0; c < P; c++) out[c] = omf * v[c] + uf * v[c + 1];
     };
 
     int nloc = 0;
@@ -940,45 +971,20 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
             const int xi0 = x0 + ishift(u, uf);
             if (xi0 != xi_prev) {
                 xi_prev = xi0;
-                T v[P + 1], A, B;
-                if (xi0 >= col_lo && xi0 + P <= col_hi) {
-                    // staged and inside the row: no clamping
-                    const int base = rbase + xi0;
+                // taps R[clamp(m + c)] and R[clamp(m + c + 1)] of the cell m
+                T v[P + 1];
+                load_run(xi0, v);
+                T a0 = 0, a1 = 0, b0 = 0, b1 = 0;
 #pragma unroll
-                    for (int c = 0; c <= P; c++) {
-                        v[c] = Rs[base + c];
-                        if constexpr (!U8) v[c] = fabs(v[c]);
+                for (int c = 0; c < P; c += 2) {
+                    a0 += Jg[c] * v[c];
+                    b0 += Jg[c] * v[c + 1];
+                    if (c + 1 < P) {
+                        a1 += Jg[c + 1] * v[c + 1];
+                        b1 += Jg[c + 1] * v[c + 2];
                     }
-                    T a0 = 0, a1 = 0, b0 = 0, b1 = 0;
-#pragma unroll
-                    for (int c = 0; c < P; c += 2) {
-                        a0 += Jg[c] * v[c];
-                        b0 += Jg[c] * v[c + 1];
-                        if (c + 1 < P) {
-                            a1 += Jg[c + 1] * v[c + 1];
-                            b1 += Jg[c + 1] * v[c + 2];
-                        }
-                    }
-                    A = a0 + a1;
-                    B = b0 + b1;
-                } else {
-                    // taps of clamped columns (LDS or global memory)
-                    fetch(xi0, v, std::integral_constant<int, P + 1>());
-#pragma unroll
-                    for (int c = 0; c <= P; c++)
-                        if constexpr (!U8) v[c] = fabs(v[c]);
-                    T a0 = 0, b0 = 0;
-#pragma unroll
-                    for (int c = 0; c < P; c++) {
-                        const int xi = xi0 + c;
-                        const T ta = xi >= W - 1 ? v[c + 1] : v[c];
-                        const T tb = xi < 0 ? v[c] : v[c + 1];
-                        a0 += Jg[c] * ta;
-                        b0 += Jg[c] * tb;
-                    }
-                    A = a0;
-                    B = b0;
                 }
+                const T A = a0 + a1, B = b0 + b1;
                 T ab[2] = {A, B};
                 seg_sum_n<SEG, 2>(ab);
                 SA = ab[0] - JT;
