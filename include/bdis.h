@@ -197,7 +197,11 @@ BDIS_API bdis_status bdis_set_tuning(bdis_t *h, int32_t n, const int32_t *max_wi
  *   stage 3: per-patch fusion weight (float, ny x nx; 0 = discarded)
  *   stage 4: per-patch outcome (int8: 0 kept, 1 degenerate, 2 diverged,
  *            3 gated by gamma)
- *   stage 5: dense field U_l in level pixels (float, W_l x H_l; level >= 1)
+ *   stage 5: dense field U_l in level pixels (float, W_l x H_l; level >= 1).
+ *            No step of a compute reads U_1 when the level-0 LK launch
+ *            densifies level 1 itself (it needs only its initial shifts), so
+ *            that compute leaves U_1 unwritten; asked for it, this call
+ *            first runs one densify launch of level 1 on the last stream.
  *   stage 6: per-patch initial shift u0 (float, ny x nx)
  * Pyramid values hold validity in the sign bit (negative or -0 = invalid).
  * Errors: BDIS_E_STATE (no single-pair compute yet), BDIS_E_INVALID_ARG. */

@@ -837,13 +837,18 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
                 const T F = dense_value<T, false>(D, (tap & 1) ? mx1 : mx, (tap & 2) ? my1 : my, kp);
                 // this block's share of the level-(l+1) field, which the next
                 // finer level reads where its own patches leave a pixel
-                // uncovered (loads in the same round trip as the taps')
-                const int n1 = J.Wc * J.Hc, nblk = J.ny * bpr, chunk = (n1 + nblk - 1) / nblk;
-                const int i1 = min(n1, (lb + 1) * chunk);
-                const double inv_wc = 1.0 / (double)J.Wc;
-                for (int i = lb * chunk + (int)threadIdx.x; i < i1; i += kBlock) {
-                    const int yy = div_exact(i, inv_wc), xx = i - yy * J.Wc;
-                    static_cast<T *>(J.Uc)[i] = dense_value<T, false>(D, xx, yy, kp);
+                // uncovered (loads in the same round trip as the taps').  At
+                // level 0 (the uint8 launch) there is no finer level: the
+                // output leaves uncovered pixels unestimated, so the level-1
+                // field is not written.
+                if constexpr (!U8) {
+                    const int n1 = J.Wc * J.Hc, nblk = J.ny * bpr, chunk = (n1 + nblk - 1) / nblk;
+                    const int i1 = min(n1, (lb + 1) * chunk);
+                    const double inv_wc = 1.0 / (double)J.Wc;
+                    for (int i = lb * chunk + (int)threadIdx.x; i < i1; i += kBlock) {
+                        const int yy = div_exact(i, inv_wc), xx = i - yy * J.Wc;
+                        static_cast<T *>(J.Uc)[i] = dense_value<T, false>(D, xx, yy, kp);
+                    }
                 }
                 const T f00 = dpp_v<0x00>(F), f01 = dpp_v<0x55>(F), f10 = dpp_v<0xAA>(F), f11 = dpp_v<0xFF>(F);
                 u0 = T(2) * bilinear_mix<T>(f00, f01, f10, f11, fx, fy);

@@ -229,6 +229,10 @@ struct bdis_ctx {
     bool have_last = false;
     PairIn last;
     hipStream_t last_stream = nullptr;
+    // the last plan left the level-1 field unwritten (the level-0 LK launch
+    // densified level 1 for its initial shifts only); bdis_debug_stage
+    // computes it on request
+    bool field1_skipped = false;
     // profiling: events around each launch, resolved in bdis_get_profile
     bool profiling = false;
     struct Rec { std::string name; hipEvent_t a, b; };
@@ -438,6 +442,35 @@ bool learned(const bdis_t *h) { return h->prm.init == BDIS_INIT_LEARNED; }
 // run only for pairs the gate flagged (plain fallback where the network is
 // not confident), the injection level's densification leaves the confident
 // pixels alone, and the finer levels use learned_iters.
+// Densification of level l of pair p (the field U_l, or the output at
+// level 0); keep: the learned injection level, which fills only the pixels
+// the gate left.
+DenseJob make_dense_job(const bdis_t *h, const PairIn &p, int l, bool keep) {
+    const bool f64 = h->prm.precision == 0;
+    DenseJob j{};
+    j.L = l == 0 ? (const void *)p.left : p.ws.pyr_l[l];
+    j.R = l == 0 ? (const void *)p.right : p.ws.pyr_r[l];
+    j.pitch = l == 0 ? p.pitch : p.g.W[l];
+    j.W = p.g.W[l]; j.H = p.g.H[l];
+    j.patch = p.patch; j.stride = p.stride;
+    j.nx = p.g.nx[l]; j.ny = p.g.ny[l];
+    j.rec_u = p.ws.rec_u[l]; j.rec_w = p.ws.rec_w[l];
+    j.gtab = f64 ? (const void *)(h->gtab_d + gtab_offset(p.patch))
+                 : (const void *)(h->gtab_f + gtab_offset(p.patch));
+    bool coarsest = l == p.g.L - 1;
+    j.Uc = coarsest ? nullptr : p.ws.U[l + 1];
+    j.Wc = coarsest ? 0 : p.g.W[l + 1];
+    j.Hc = coarsest ? 0 : p.g.H[l + 1];
+    j.mode = l == 0 ? 2 : (coarsest ? 1 : 0);
+    j.U = l == 0 ? nullptr : p.ws.U[l];
+    j.out = l == 0 ? p.disp : nullptr;
+    j.out_pitch = p.dpitch;
+    j.run_flag = nullptr;
+    j.keep = keep ? p.ws.keep : nullptr;
+    j.ppt = 1;
+    return j;
+}
+
 void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<Launch> &ls) {
     int Lmax = 0, Lpmax = 0;
     const bool f64 = h->prm.precision == 0;
@@ -504,6 +537,9 @@ void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<Launch> &l
         return h->fold_dense && l >= 0 && l + 1 < p.g.L && !(lrn && l + 1 == inj) &&
                h->prm.fusion == BDIS_FUSION_BAYES && lk_blocks[l] <= kFoldBlocksPerCU * h->n_cu;
     };
+    // the level-0 LK launch densifies level 1 for its own initial shifts
+    // only (no finer level reads that field)
+    h->field1_skipped = pairs.size() == 1 && folded(pairs[0], 0);
     bool joined = false;
     for (int l = Lmax - 1; l >= 0; l--) {
         // With the learned init the plain levels down to the injection level
@@ -550,28 +586,7 @@ void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<Launch> &l
         std::vector<DenseJob> jobs;
         for (auto &p : pairs) {
             if (p.g.L <= l || folded(p, l - 1)) continue;
-            DenseJob j{};
-            j.L = l == 0 ? (const void *)p.left : p.ws.pyr_l[l];
-            j.R = l == 0 ? (const void *)p.right : p.ws.pyr_r[l];
-            j.pitch = l == 0 ? p.pitch : p.g.W[l];
-            j.W = p.g.W[l]; j.H = p.g.H[l];
-            j.patch = p.patch; j.stride = p.stride;
-            j.nx = p.g.nx[l]; j.ny = p.g.ny[l];
-            j.rec_u = p.ws.rec_u[l]; j.rec_w = p.ws.rec_w[l];
-            j.gtab = f64 ? (const void *)(h->gtab_d + gtab_offset(p.patch))
-                         : (const void *)(h->gtab_f + gtab_offset(p.patch));
-            bool coarsest = l == p.g.L - 1;
-            j.Uc = coarsest ? nullptr : p.ws.U[l + 1];
-            j.Wc = coarsest ? 0 : p.g.W[l + 1];
-            j.Hc = coarsest ? 0 : p.g.H[l + 1];
-            j.mode = l == 0 ? 2 : (coarsest ? 1 : 0);
-            j.U = l == 0 ? nullptr : p.ws.U[l];
-            j.out = l == 0 ? p.disp : nullptr;
-            j.out_pitch = p.dpitch;
-            j.run_flag = nullptr;
-            j.keep = (lrn && l == inj) ? p.ws.keep : nullptr;
-            j.ppt = 1;
-            jobs.push_back(j);
+            jobs.push_back(make_dense_job(h, p, l, lrn && l == inj));
         }
         append(ls, K_DENSE, l, 0, l == 0, f64, jobs, kp0,
                [](const DenseJob &j) { return dense_blocks(j.W, j.H, j.ppt); });
@@ -1382,6 +1397,21 @@ bdis_status bdis_debug_stage(bdis_t *h, int32_t stage, int32_t level, void *dst,
     if (!src) { set_err(h->err, "stage %d has no level %d", stage, level); return BDIS_E_INVALID_ARG; }
     if (bytes < need) { set_err(h->err, "dst holds %zu bytes, need %zu", bytes, need); return BDIS_E_INVALID_ARG; }
     DeviceGuard dg(h->device);
+    if (stage == 5 && level == 1 && h->field1_skipped) {
+        // the last compute never wrote this field: densify level 1 now from
+        // its records and the level-2 field, which are still in place
+        std::vector<Launch> ls;
+        std::vector<DenseJob> jobs{make_dense_job(h, p, 1, false)};
+        append(ls, K_DENSE, 1, 0, false, h->prm.precision == 0, jobs, make_kparams(h->prm, h->prm.patch),
+               [](const DenseJob &j) { return dense_blocks(j.W, j.H, j.ppt); });
+        const bool prof = h->profiling;
+        h->profiling = false;
+        bdis_status st = launch_all(h, ls, h->last_stream);
+        h->profiling = prof;
+        if (st != BDIS_OK) return st;
+        HIPCHK(h, hipGetLastError());
+        h->field1_skipped = false;
+    }
     HIPCHK(h, hipStreamSynchronize(h->last_stream));
     HIPCHK(h, hipMemcpy(dst, src, need, hipMemcpyDeviceToHost));
     return BDIS_OK;
