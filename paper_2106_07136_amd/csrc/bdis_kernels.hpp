@@ -114,7 +114,7 @@ struct DenseJob {
     int out_pitch;
     int ppt;               // pixels per thread (block = ppt * kBlock pixels)
     int block0;
-    int pad_;
+    int strip;             // > 1: one strip of this many pixels of a row per thread (ppt unused)
 };
 static_assert(sizeof(DenseJob) == 10 * 8 + 14 * 4, "DenseJob must have no padding");
 
@@ -1123,12 +1123,121 @@ __device__ __forceinline__ void dense_pixel(const DenseJob &J, const int i, cons
     if (J.U) static_cast<T *>(J.U)[i] = U;
 }
 
+// The pixels xs .. xs + strip - 1 of row y, strip = J.strip (the grid
+// stride, strips aligned to it).  Where every pixel of the strip has the same
+// candidate patches (the interior at most strides), the records of those
+// patches are loaded once for the strip; each pixel then takes dense_value's
+// fast path with its own spatial weights, in the same order and arithmetic,
+// so the values are the same bits.  Other strips, and eq. (2)'s fusion, go
+// pixel by pixel through dense_value.
+template <typename T, bool U8>
+__device__ __forceinline__ void dense_strip(const DenseJob &J, const int xs, const int y, const KParams &kp) {
+#pragma clang fp contract(off)
+    if (J.run_flag && *J.run_flag == 0) return;
+    const int P = J.patch, st = J.stride, xe = min(xs + J.strip, J.W);
+    auto put = [&](int x, T U) {
+        if (J.out) J.out[(size_t)y * J.out_pitch + x] = (float)(-U);
+        if (J.U) static_cast<T *>(J.U)[(size_t)y * J.W + x] = U;
+    };
+    const double inv_st = 1.0 / (double)st;
+    auto range = [&](int v, int n, int cnt, int &lo, int &hi, int &extra) {
+        int t = v - P + 1;
+        lo = t > 0 ? div_exact(t + st - 1, inv_st) : 0;
+        hi = min(cnt - 1, div_exact(v, inv_st));
+        extra = (hi < cnt - 1 && v >= n - P) ? cnt - 1 : -1;
+    };
+    int xlo, xhi, xex, xlo1, xhi1, xex1, ylo, yhi, yex;
+    range(xs, J.W, J.nx, xlo, xhi, xex);
+    range(xe - 1, J.W, J.nx, xlo1, xhi1, xex1);
+    range(y, J.H, J.ny, ylo, yhi, yex);
+    const int ncx = xhi - xlo + 1 + (xex >= 0 ? 1 : 0), ncy = yhi - ylo + 1 + (yex >= 0 ? 1 : 0);
+    // lo, hi and the snapped extra move monotonically with x (extra as the
+    // pair (hi, extra) does), so equal at both ends means equal throughout
+    const bool shared = kp.fusion == 0 && xlo == xlo1 && xhi == xhi1 && xex == xex1 && ncx <= 2 && ncy <= 2;
+    if (!shared) {
+        for (int x = xs; x < xe; x++)
+            if (!(J.keep && J.keep[(size_t)y * J.W + x])) put(x, dense_value<T, U8>(J, x, y, kp));
+        return;
+    }
+    const T *rec_u = static_cast<const T *>(J.rec_u);
+    const T *rec_w = static_cast<const T *>(J.rec_w);
+    const T *gtab = static_cast<const T *>(J.gtab);
+    constexpr int NC = 2;
+    int px[NC], py[NC], jxc[NC], jyc[NC];
+    bool vy[NC];
+#pragma unroll
+    for (int i = 0; i < NC; i++) {
+        jxc[i] = i <= xhi - xlo ? xlo + i : (i == xhi - xlo + 1 ? xex : -1);
+        jyc[i] = i <= yhi - ylo ? ylo + i : (i == yhi - ylo + 1 ? yex : -1);
+        px[i] = jxc[i] >= 0 ? grid_pos(jxc[i], J.W, P, st) : 0;
+        py[i] = jyc[i] >= 0 ? grid_pos(jyc[i], J.H, P, st) : 0;
+        vy[i] = jyc[i] >= 0 && y >= py[i] && y < py[i] + P;
+    }
+    // records of the (at most) 2 x 2 candidates, loaded once
+    T wk[NC][NC], uk[NC][NC];
+#pragma unroll
+    for (int iy = 0; iy < NC; iy++)
+#pragma unroll
+        for (int ix = 0; ix < NC; ix++) {
+            const bool v = vy[iy] && jxc[ix] >= 0;
+            const int k = v ? jyc[iy] * J.nx + jxc[ix] : 0;
+            wk[iy][ix] = rec_w[k];
+            uk[iy][ix] = rec_u[k];
+            if (!v) wk[iy][ix] = T(0);
+        }
+    for (int x = xs; x < xe; x++) {
+        if (J.keep && J.keep[(size_t)y * J.W + x]) continue;
+        T Uf = 0;
+        if (J.mode == 0) Uf = T(2) * bilinear<T>(static_cast<const T *>(J.Uc), J.Wc, J.Hc, T(0.5) * (T)x, T(0.5) * (T)y);
+        bool vx[NC];
+        T g[NC][NC];
+#pragma unroll
+        for (int ix = 0; ix < NC; ix++) vx[ix] = jxc[ix] >= 0 && x >= px[ix] && x < px[ix] + P;
+#pragma unroll
+        for (int iy = 0; iy < NC; iy++)
+#pragma unroll
+            for (int ix = 0; ix < NC; ix++)
+                g[iy][ix] = gtab[vy[iy] && vx[ix] ? (y - py[iy]) * P + (x - px[ix]) : 0];
+        T A = 0, B = 0;
+#pragma unroll
+        for (int iy = 0; iy < NC; iy++)
+#pragma unroll
+            for (int ix = 0; ix < NC; ix++) {
+                const T w0 = vx[ix] ? wk[iy][ix] : T(0);
+                if (w0 > T(0)) {
+                    const T w = w0 * g[iy][ix];
+                    A += w;
+                    B += w * uk[iy][ix];
+                }
+            }
+        T U;
+        if (A > T(0)) U = B / A;
+        else if (J.mode == 2) U = (T)__builtin_nan("");
+        else if (J.mode == 1) U = 0;
+        else U = Uf;
+        put(x, U);
+    }
+}
+
 __host__ __device__ constexpr int dense_blocks(int w, int h, int ppt) {
     return (w * h + kBlock * ppt - 1) / (kBlock * ppt);
+}
+// Blocks of a densification job: one pixel per thread (ppt per thread in the
+// persistent kernel's tasks), or one strip per thread.
+__host__ __device__ constexpr int dense_job_blocks(const DenseJob &j) {
+    return j.strip > 1 ? ((j.W + j.strip - 1) / j.strip * j.H + kBlock - 1) / kBlock : dense_blocks(j.W, j.H, j.ppt);
 }
 
 template <typename T, bool U8>
 __device__ __forceinline__ void dense_block(const DenseJob &J, int lb, const KParams &kp) {
+    if (J.strip > 1) {
+        const int nsr = (J.W + J.strip - 1) / J.strip;
+        const int s = lb * kBlock + (int)threadIdx.x;
+        if (s >= nsr * J.H) return;
+        const int y = div_exact(s, 1.0 / (double)nsr), xs = (s - y * nsr) * J.strip;
+        dense_strip<T, U8>(J, xs, y, kp);
+        return;
+    }
     const int n = J.W * J.H;
     for (int q = 0; q < J.ppt; q++) {
         int i = (lb * J.ppt + q) * kBlock + (int)threadIdx.x;

@@ -28,6 +28,9 @@ constexpr int kNetLevel = 4;  // the proposal network runs on the 1/16 pyramid l
 // LK launches of at most this many blocks per CU are "small": they take the
 // three-waves-per-SIMD register budget and densify the next coarser level
 constexpr int kFoldBlocksPerCU = 3;
+// a densification launch takes one pixel strip per thread only when the
+// strips fill at least this many blocks per CU
+constexpr int kStripBlocksPerCU = 4;
 
 thread_local char g_thread_err[512] = "";
 
@@ -468,6 +471,9 @@ DenseJob make_dense_job(const bdis_t *h, const PairIn &p, int l, bool keep) {
     j.run_flag = nullptr;
     j.keep = keep ? p.ws.keep : nullptr;
     j.ppt = 1;
+    // a strip of pixels per thread shares the candidate patches' records
+    // (Bayesian fusion; eq. (2)'s weights depend on each pixel's residual)
+    j.strip = h->prm.fusion == BDIS_FUSION_BAYES && p.stride > 1 ? p.stride : 1;
     return j;
 }
 
@@ -588,8 +594,15 @@ void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<Launch> &l
             if (p.g.L <= l || folded(p, l - 1)) continue;
             jobs.push_back(make_dense_job(h, p, l, lrn && l == inj));
         }
+        // Strips pay where they still leave several blocks per CU; a small
+        // densification (one pair, the coarse levels of a batch) is bound by
+        // the latency of its gathers and keeps one pixel per thread.
+        long long strip_threads = 0;
+        for (const DenseJob &j : jobs) strip_threads += (long long)((j.W + j.strip - 1) / j.strip) * j.H;
+        if (strip_threads < (long long)kStripBlocksPerCU * kBlock * h->n_cu)
+            for (DenseJob &j : jobs) j.strip = 1;
         append(ls, K_DENSE, l, 0, l == 0, f64, jobs, kp0,
-               [](const DenseJob &j) { return dense_blocks(j.W, j.H, j.ppt); });
+               [](const DenseJob &j) { return dense_job_blocks(j); });
     }
     if (lrn && !joined) ls.push_back(Launch{K_JOIN, 0, 0, false, f64, 0, kp0, {}});  // every fork is joined
 }
@@ -1403,7 +1416,7 @@ bdis_status bdis_debug_stage(bdis_t *h, int32_t stage, int32_t level, void *dst,
         std::vector<Launch> ls;
         std::vector<DenseJob> jobs{make_dense_job(h, p, 1, false)};
         append(ls, K_DENSE, 1, 0, false, h->prm.precision == 0, jobs, make_kparams(h->prm, h->prm.patch),
-               [](const DenseJob &j) { return dense_blocks(j.W, j.H, j.ppt); });
+               [](const DenseJob &j) { return dense_job_blocks(j); });
         const bool prof = h->profiling;
         h->profiling = false;
         bdis_status st = launch_all(h, ls, h->last_stream);
