@@ -585,9 +585,19 @@ __device__ __forceinline__ T dense_value(const V &J, const int x, const int y, c
     int xlo, xhi, xex, ylo, yhi, yex;
     range(x, J.W, J.nx, xlo, xhi, xex);
     range(y, J.H, J.ny, ylo, yhi, yex);
-    // the fallback field's taps go out with the patch records (one round trip)
-    T Uf = 0;
-    if (J.mode == 0) Uf = T(2) * bilinear<T>(static_cast<const T *>(J.Uc), J.Wc, J.Hc, T(0.5) * (T)x, T(0.5) * (T)y);
+    // The fallback field's taps are loaded here and mixed only at the end,
+    // so that they go out with the patch records (one round trip): mixed
+    // here, they would be waited for before the records' loads are issued.
+    T f00 = 0, f01 = 0, f10 = 0, f11 = 0, ffx = 0, ffy = 0;
+    if (J.mode == 0) {
+        const T *Uc = static_cast<const T *>(J.Uc);
+        int mx, my, mx1, my1;
+        bilinear_taps<T>(J.Wc, J.Hc, T(0.5) * (T)x, T(0.5) * (T)y, mx, my, mx1, my1, ffx, ffy);
+        f00 = Uc[(size_t)my * J.Wc + mx];
+        f01 = Uc[(size_t)my * J.Wc + mx1];
+        f10 = Uc[(size_t)my1 * J.Wc + mx];
+        f11 = Uc[(size_t)my1 * J.Wc + mx1];
+    }
     T A = 0, B = 0;
     auto add = [&](int py, int px, T wk, T uk, T g) {
         T w;
@@ -662,7 +672,7 @@ __device__ __forceinline__ T dense_value(const V &J, const int x, const int y, c
     if (A > T(0)) return B / A;
     if (J.mode == 2) return (T)__builtin_nan("");
     if (J.mode == 1) return 0;
-    return Uf;
+    return T(2) * bilinear_mix<T>(f00, f01, f10, f11, ffx, ffy);
 }
 
 // ---------------------------------------------------------------- LK + posterior
@@ -806,17 +816,20 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
     constexpr int CH = (NCROW - 1 + kBlock - 1) / kBlock;
 #pragma unroll
     for (int r0 = 0; r0 < P; r0 += 8) {
-        T buf[8][CH];
+        // Every lane loads (the column clamped into the staged span), with no
+        // branch around the load and the uint8 -> T conversion left to the
+        // LDS write: a load inside a branch, or converted inside one, is
+        // waited for there, one memory round trip per load.
+        using RawT = std::conditional_t<U8, uint8_t, T>;
+        RawT buf[8][CH];
 #pragma unroll
         for (int rr = 0; rr < 8; rr++)
 #pragma unroll
             for (int q = 0; q < CH; q++) {
-                int cc = (int)threadIdx.x + q * kBlock;
-                buf[rr][q] = T(0);
-                if (r0 + rr < P && cc < nst) {
-                    size_t g = (size_t)(y0 + r0 + rr) * J.pitch + (size_t)min(max(vlo + cc, 0), W - 1);
-                    if constexpr (U8) buf[rr][q] = (T) static_cast<const uint8_t *>(J.R)[g];
-                    else buf[rr][q] = static_cast<const T *>(J.R)[g];
+                const int cc = min((int)threadIdx.x + q * kBlock, nst - 1);
+                if (r0 + rr < P) {
+                    const size_t g = (size_t)(y0 + r0 + rr) * J.pitch + (size_t)min(max(vlo + cc, 0), W - 1);
+                    buf[rr][q] = static_cast<const RawT *>(J.R)[g];
                 }
             }
         if (r0 == 0 && J.Uc) {
@@ -859,7 +872,7 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
 #pragma unroll
             for (int q = 0; q < CH; q++) {
                 int cc = (int)threadIdx.x + q * kBlock;
-                if (r0 + rr < P && cc < nst) Rs[(r0 + rr) * NCROW + cc] = buf[rr][q];
+                if (r0 + rr < P && cc < nst) Rs[(r0 + rr) * NCROW + cc] = (T)buf[rr][q];
             }
     }
     __syncthreads();
@@ -1187,8 +1200,17 @@ __device__ __forceinline__ void dense_strip(const DenseJob &J, const int xs, con
         }
     for (int x = xs; x < xe; x++) {
         if (J.keep && J.keep[(size_t)y * J.W + x]) continue;
-        T Uf = 0;
-        if (J.mode == 0) Uf = T(2) * bilinear<T>(static_cast<const T *>(J.Uc), J.Wc, J.Hc, T(0.5) * (T)x, T(0.5) * (T)y);
+        // fallback taps loaded with the spatial weights, mixed at the end
+        T f00 = 0, f01 = 0, f10 = 0, f11 = 0, ffx = 0, ffy = 0;
+        if (J.mode == 0) {
+            const T *Uc = static_cast<const T *>(J.Uc);
+            int mx, my, mx1, my1;
+            bilinear_taps<T>(J.Wc, J.Hc, T(0.5) * (T)x, T(0.5) * (T)y, mx, my, mx1, my1, ffx, ffy);
+            f00 = Uc[(size_t)my * J.Wc + mx];
+            f01 = Uc[(size_t)my * J.Wc + mx1];
+            f10 = Uc[(size_t)my1 * J.Wc + mx];
+            f11 = Uc[(size_t)my1 * J.Wc + mx1];
+        }
         bool vx[NC];
         T g[NC][NC];
 #pragma unroll
@@ -1214,7 +1236,7 @@ __device__ __forceinline__ void dense_strip(const DenseJob &J, const int xs, con
         if (A > T(0)) U = B / A;
         else if (J.mode == 2) U = (T)__builtin_nan("");
         else if (J.mode == 1) U = 0;
-        else U = Uf;
+        else U = T(2) * bilinear_mix<T>(f00, f01, f10, f11, ffx, ffy);
         put(x, U);
     }
 }
