@@ -675,6 +675,93 @@ __device__ __forceinline__ T dense_value(const V &J, const int x, const int y, c
     return T(2) * bilinear_mix<T>(f00, f01, f10, f11, ffx, ffy);
 }
 
+// dense_value for the Bayesian fusion in two halves, so that the loads of
+// several pixels go out together: dense_gather issues a pixel's loads (the
+// fast path's records, spatial weights and fallback taps), dense_finish sums
+// them with dense_value's arithmetic in its order, or calls dense_value for a
+// pixel outside the fast path.
+template <typename T>
+struct DenseG {
+    T wk[2][2], uk[2][2], g[2][2];
+    T f00, f01, f10, f11, ffx, ffy;
+    bool fast;
+};
+template <typename T, typename V>
+__device__ __forceinline__ void dense_gather(const V &J, const int x, const int y, DenseG<T> &G) {
+#pragma clang fp contract(off)
+    const int P = J.patch, st = J.stride;
+    const T *rec_u = static_cast<const T *>(J.rec_u);
+    const T *rec_w = static_cast<const T *>(J.rec_w);
+    const T *gtab = static_cast<const T *>(J.gtab);
+    const double inv_st = 1.0 / (double)st;
+    auto range = [&](int v, int n, int cnt, int &lo, int &hi, int &extra) {
+        int t = v - P + 1;
+        lo = t > 0 ? div_exact(t + st - 1, inv_st) : 0;
+        hi = min(cnt - 1, div_exact(v, inv_st));
+        extra = (hi < cnt - 1 && v >= n - P) ? cnt - 1 : -1;
+    };
+    int xlo, xhi, xex, ylo, yhi, yex;
+    range(x, J.W, J.nx, xlo, xhi, xex);
+    range(y, J.H, J.ny, ylo, yhi, yex);
+    G.f00 = G.f01 = G.f10 = G.f11 = G.ffx = G.ffy = T(0);
+    if (J.mode == 0) {
+        const T *Uc = static_cast<const T *>(J.Uc);
+        int mx, my, mx1, my1;
+        bilinear_taps<T>(J.Wc, J.Hc, T(0.5) * (T)x, T(0.5) * (T)y, mx, my, mx1, my1, G.ffx, G.ffy);
+        G.f00 = Uc[(size_t)my * J.Wc + mx];
+        G.f01 = Uc[(size_t)my * J.Wc + mx1];
+        G.f10 = Uc[(size_t)my1 * J.Wc + mx];
+        G.f11 = Uc[(size_t)my1 * J.Wc + mx1];
+    }
+    const int ncx = xhi - xlo + 1 + (xex >= 0 ? 1 : 0), ncy = yhi - ylo + 1 + (yex >= 0 ? 1 : 0);
+    G.fast = ncx <= 2 && ncy <= 2;
+    constexpr int NC = 2;
+    int px[NC], py[NC], jxs[NC], jys[NC];
+    bool vx[NC], vy[NC];
+#pragma unroll
+    for (int i = 0; i < NC; i++) {
+        int jx = i <= xhi - xlo ? xlo + i : (i == xhi - xlo + 1 ? xex : -1);
+        int jy = i <= yhi - ylo ? ylo + i : (i == yhi - ylo + 1 ? yex : -1);
+        px[i] = jx >= 0 ? grid_pos(jx, J.W, P, st) : 0;
+        py[i] = jy >= 0 ? grid_pos(jy, J.H, P, st) : 0;
+        vx[i] = G.fast && jx >= 0 && x >= px[i] && x < px[i] + P;
+        vy[i] = G.fast && jy >= 0 && y >= py[i] && y < py[i] + P;
+        jxs[i] = vx[i] ? jx : 0;
+        jys[i] = vy[i] ? jy : 0;
+    }
+#pragma unroll
+    for (int iy = 0; iy < NC; iy++)
+#pragma unroll
+        for (int ix = 0; ix < NC; ix++) {
+            const bool v = vy[iy] && vx[ix];
+            const int k = v ? jys[iy] * J.nx + jxs[ix] : 0;
+            G.wk[iy][ix] = rec_w[k];
+            G.uk[iy][ix] = rec_u[k];
+            G.g[iy][ix] = gtab[v ? (y - py[iy]) * P + (x - px[ix]) : 0];
+            if (!v) G.wk[iy][ix] = T(0);
+        }
+}
+template <typename T, bool U8, typename V>
+__device__ __forceinline__ T dense_finish(const V &J, const int x, const int y, const KParams &kp,
+                                          const DenseG<T> &G) {
+#pragma clang fp contract(off)
+    if (!G.fast) return dense_value<T, U8>(J, x, y, kp);
+    T A = 0, B = 0;
+#pragma unroll
+    for (int iy = 0; iy < 2; iy++)
+#pragma unroll
+        for (int ix = 0; ix < 2; ix++)
+            if (G.wk[iy][ix] > T(0)) {
+                const T w = G.wk[iy][ix] * G.g[iy][ix];
+                A += w;
+                B += w * G.uk[iy][ix];
+            }
+    if (A > T(0)) return B / A;
+    if (J.mode == 2) return (T)__builtin_nan("");
+    if (J.mode == 1) return 0;
+    return T(2) * bilinear_mix<T>(G.f00, G.f01, G.f10, G.f11, G.ffx, G.ffy);
+}
+
 // ---------------------------------------------------------------- LK + posterior
 
 enum { ST_KEPT = 0, ST_DEGENERATE = 1, ST_DIVERGED = 2, ST_GATED = 3 };
@@ -719,8 +806,10 @@ __host__ __device__ constexpr int lk_lds_bytes() { return P * LkShape<P>::NCROW 
 // Block lb of an LK job; Rs is the block's LDS staging area of
 // lk_lds_bytes<T, P>() bytes.  WN >= kp.window bounds the window samples
 // (5 for the paper's window, 9 for any allowed one).  FOLD compiles the
-// densification of level + 1 in (used when J.rec_u1 is set).
-template <typename T, int P, bool U8, int WN = 9, bool FOLD = false>
+// densification of level + 1 in (used when J.rec_u1 is set); MERGE gathers
+// the first pixel of the block's share of that field with the taps (more
+// registers: for launches of at most two blocks per CU).
+template <typename T, int P, bool U8, int WN = 9, bool FOLD = false, bool MERGE = false>
 __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KParams &kp, T *__restrict__ Rs) {
     using S = LkShape<P>;
     constexpr int SEG = S::SEG, PPB = S::PPB, NCMAX = S::NCMAX, NCROW = S::NCROW, PADC = S::PADC;
@@ -846,21 +935,44 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
                 int mx, my, mx1, my1;
                 T fx, fy;
                 bilinear_taps<T>(J.Wc, J.Hc, T(0.5) * cx, T(0.5) * cy, mx, my, mx1, my1, fx, fy);
-                const int tap = r & 3;
-                const T F = dense_value<T, false>(D, (tap & 1) ? mx1 : mx, (tap & 2) ? my1 : my, kp);
+                const int tap = r & 3, tx = (tap & 1) ? mx1 : mx, ty = (tap & 2) ? my1 : my;
+                T F;
                 // this block's share of the level-(l+1) field, which the next
                 // finer level reads where its own patches leave a pixel
-                // uncovered (loads in the same round trip as the taps').  At
-                // level 0 (the uint8 launch) there is no finer level: the
-                // output leaves uncovered pixels unestimated, so the level-1
-                // field is not written.
-                if constexpr (!U8) {
+                // uncovered.  Its first pixel per thread is gathered with the
+                // tap, so that both go out in one round trip.  At level 0 (the
+                // uint8 launch) there is no finer level: the output leaves
+                // uncovered pixels unestimated, so the level-1 field is not
+                // written.
+                if constexpr (!U8 && MERGE) {
                     const int n1 = J.Wc * J.Hc, nblk = J.ny * bpr, chunk = (n1 + nblk - 1) / nblk;
-                    const int i1 = min(n1, (lb + 1) * chunk);
+                    const int i0 = lb * chunk, i1 = min(n1, (lb + 1) * chunk);
                     const double inv_wc = 1.0 / (double)J.Wc;
-                    for (int i = lb * chunk + (int)threadIdx.x; i < i1; i += kBlock) {
+                    const int ia = i0 + (int)threadIdx.x;
+                    // lanes past the share gather a pixel of it anyway (i0 < i1:
+                    // every block has a share) and do not store it
+                    const int ic = min(ia, i1 - 1);
+                    const int ya = div_exact(ic, inv_wc), xa = ic - ya * J.Wc;
+                    DenseG<T> Gt, Gs;
+                    dense_gather<T>(D, tx, ty, Gt);
+                    dense_gather<T>(D, xa, ya, Gs);
+                    F = dense_finish<T, false>(D, tx, ty, kp, Gt);
+                    const T Us = dense_finish<T, false>(D, xa, ya, kp, Gs);
+                    if (ia < i1) static_cast<T *>(J.Uc)[ia] = Us;
+                    for (int i = ia + kBlock; i < i1; i += kBlock) {
                         const int yy = div_exact(i, inv_wc), xx = i - yy * J.Wc;
                         static_cast<T *>(J.Uc)[i] = dense_value<T, false>(D, xx, yy, kp);
+                    }
+                } else {
+                    F = dense_value<T, false>(D, tx, ty, kp);
+                    if constexpr (!U8) {
+                        const int n1 = J.Wc * J.Hc, nblk = J.ny * bpr, chunk = (n1 + nblk - 1) / nblk;
+                        const int i1 = min(n1, (lb + 1) * chunk);
+                        const double inv_wc = 1.0 / (double)J.Wc;
+                        for (int i = lb * chunk + (int)threadIdx.x; i < i1; i += kBlock) {
+                            const int yy = div_exact(i, inv_wc), xx = i - yy * J.Wc;
+                            static_cast<T *>(J.Uc)[i] = dense_value<T, false>(D, xx, yy, kp);
+                        }
                     }
                 }
                 const T f00 = dpp_v<0x00>(F), f01 = dpp_v<0x55>(F), f10 = dpp_v<0xAA>(F), f11 = dpp_v<0xFF>(F);
@@ -1110,8 +1222,9 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
 
 // OCC: waves per SIMD the register allocation must allow.  3: small launches,
 // which may also densify the next coarser level (few blocks, so the waves fit
-// anyway); 5: launches with many more blocks than the chip holds, where
-// occupancy pays -- they never densify, so that code is left out.
+// anyway); 2: the smallest, whose densification also gathers its first share
+// pixel with the taps; 5: launches with many more blocks than the chip
+// holds, where occupancy pays -- they never densify, so that code is left out.
 template <typename T, int P, bool U8, int WN, int OCC>
 __global__ __launch_bounds__(kBlock, OCC) void k_lk(const JobPack<LkJob> pk, KParams kp) {
     __shared__ T Rs[lk_lds_bytes<T, P>() / sizeof(T)];
@@ -1120,7 +1233,7 @@ __global__ __launch_bounds__(kBlock, OCC) void k_lk(const JobPack<LkJob> pk, KPa
     // neighbouring patch rows share an XCD; spread over the XCDs they run
     // faster although more lines come from beyond the L2.
     const LkJob &J = pk.j[find_job(pk, (int)blockIdx.x)];
-    lk_block<T, P, U8, WN, (OCC < 5)>(J, (int)blockIdx.x - J.block0, kp, Rs);
+    lk_block<T, P, U8, WN, (OCC < 5), (OCC <= 2)>(J, (int)blockIdx.x - J.block0, kp, Rs);
 }
 
 // ---------------------------------------------------------------- densify

@@ -631,6 +631,10 @@ void launch_lk(const bdis_t *h, const Launch &L, hipStream_t s) {
         if (big) {
             if (L.u8) hipLaunchKernelGGL((k_lk<T, P, true, 5, 5>), g, b, 0, s, pk, L.kp);
             else hipLaunchKernelGGL((k_lk<T, P, false, 5, 5>), g, b, 0, s, pk, L.kp);
+        } else if (!L.u8 && L.blocks <= 2 * h->n_cu) {
+            // two waves per SIMD at most: room to gather the densified
+            // level's first share pixel with the initial-shift taps
+            hipLaunchKernelGGL((k_lk<T, P, false, 5, 2>), g, b, 0, s, pk, L.kp);
         } else {
             if (L.u8) hipLaunchKernelGGL((k_lk<T, P, true, 5, 3>), g, b, 0, s, pk, L.kp);
             else hipLaunchKernelGGL((k_lk<T, P, false, 5, 3>), g, b, 0, s, pk, L.kp);
