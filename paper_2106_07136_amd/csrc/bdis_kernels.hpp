@@ -1149,12 +1149,17 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
                         const int xi0 = x0 + ishift(ud, uf);
                         T d[P];
                         sample(xi0, uf, d);
+                        // two interleaved chains per sum: half the dependent
+                        // adds (one wave per SIMD at the small levels)
+                        T s0 = 0, s1 = 0, e0 = 0, e1 = 0;
 #pragma unroll
                         for (int c = 0; c < P; c++) {
-                            T q = ((vmask >> c) & 1u) ? d[c] - Tv[c] : T(0);
-                            acc[2 * i] += q;
-                            acc[2 * i + 1] += q * q;
+                            const T q = ((vmask >> c) & 1u) ? d[c] - Tv[c] : T(0);
+                            if (c & 1) { s1 += q; e1 += q * q; }
+                            else { s0 += q; e0 += q * q; }
                         }
+                        acc[2 * i] = s0 + s1;
+                        acc[2 * i + 1] = e0 + e1;
                     }
                 }
                 seg_sum_n<SEG, 2 * WN>(acc);
