@@ -566,7 +566,7 @@ struct DenseView {
 // or 1 / max(residual^2, 1) (DIS eq. (2)); U = sum(w u) / sum(w).  Uncovered:
 // NaN at level 0, zero at the coarsest level, else twice the coarse field.
 // V is a DenseJob or a DenseView: the fields the value needs.
-template <typename T, bool U8, typename V>
+template <typename T, bool U8, int NC = 2, typename V>
 __device__ __forceinline__ T dense_value(const V &J, const int x, const int y, const KParams &kp) {
     // no contraction into FMAs: the value must be the same bits wherever it
     // is evaluated (densify kernel, LK launch, fast path or loop)
@@ -614,19 +614,21 @@ __device__ __forceinline__ T dense_value(const V &J, const int x, const int y, c
         A += w;
         B += w * uk;
     };
-    // Fast path: at most two candidate patches per axis (lo .. hi, or lo and
-    // the one snapped to the border), every record and mask load issued
-    // before the sums, which run in the same (row, column) order as the loop
-    // below.  It covers the interior at stride >= patch / 2; other pixels
-    // take the loop (a wider fast path would cost occupancy: the kernel is
-    // bound by the latency of its gathers).
+    // Fast paths: at most 2 (or, with NC = 3, 3) candidate patches per axis
+    // (lo .. hi, then the one snapped to the border), every record and mask
+    // load issued before the sums, which run in the same (row, column) order
+    // as the loop below.  Two per axis covers the interior at stride >= patch
+    // / 2; three also the rows and columns next to a snapped border patch,
+    // for the LK launches that densify (registers are free there, and one
+    // slow block sets the launch time).  The densify kernel keeps NC = 2: a
+    // wider path would cost occupancy, and it is bound by its gathers.
     const int ncx = xhi - xlo + 1 + (xex >= 0 ? 1 : 0), ncy = yhi - ylo + 1 + (yex >= 0 ? 1 : 0);
-    if (ncx <= 2 && ncy <= 2) {
-        constexpr int NC = 2;
-        int px[NC], py[NC], jxs[NC], jys[NC];
-        bool vx[NC], vy[NC];
+    auto fast = [&](auto M_) {
+        constexpr int M = decltype(M_)::value;
+        int px[M], py[M], jxs[M], jys[M];
+        bool vx[M], vy[M];
 #pragma unroll
-        for (int i = 0; i < NC; i++) {
+        for (int i = 0; i < M; i++) {
             int jx = i <= xhi - xlo ? xlo + i : (i == xhi - xlo + 1 ? xex : -1);
             int jy = i <= yhi - ylo ? ylo + i : (i == yhi - ylo + 1 ? yex : -1);
             px[i] = jx >= 0 ? grid_pos(jx, J.W, P, st) : 0;
@@ -636,11 +638,11 @@ __device__ __forceinline__ T dense_value(const V &J, const int x, const int y, c
             jxs[i] = vx[i] ? jx : 0;
             jys[i] = vy[i] ? jy : 0;
         }
-        T wk[NC][NC], uk[NC][NC], g[NC][NC];
+        T wk[M][M], uk[M][M], g[M][M];
 #pragma unroll
-        for (int iy = 0; iy < NC; iy++)
+        for (int iy = 0; iy < M; iy++)
 #pragma unroll
-            for (int ix = 0; ix < NC; ix++) {
+            for (int ix = 0; ix < M; ix++) {
                 const bool v = vy[iy] && vx[ix];
                 const int k = v ? jys[iy] * J.nx + jxs[ix] : 0;
                 wk[iy][ix] = rec_w[k];
@@ -649,10 +651,15 @@ __device__ __forceinline__ T dense_value(const V &J, const int x, const int y, c
                 if (!v) wk[iy][ix] = T(0);
             }
 #pragma unroll
-        for (int iy = 0; iy < NC; iy++)
+        for (int iy = 0; iy < M; iy++)
 #pragma unroll
-            for (int ix = 0; ix < NC; ix++)
+            for (int ix = 0; ix < M; ix++)
                 if (wk[iy][ix] > T(0)) add(py[iy], px[ix], wk[iy][ix], uk[iy][ix], g[iy][ix]);
+    };
+    if (ncx <= 2 && ncy <= 2) {
+        fast(std::integral_constant<int, 2>());
+    } else if (NC >= 3 && ncx <= 3 && ncy <= 3) {
+        fast(std::integral_constant<int, (NC >= 3 ? 3 : 2)>());
     } else {
     for (int jy = ylo; jy <= (yex >= 0 ? yex : yhi); jy++) {
         if (jy > yhi && jy != yex) continue;
@@ -680,14 +687,14 @@ __device__ __forceinline__ T dense_value(const V &J, const int x, const int y, c
 // fast path's records, spatial weights and fallback taps), dense_finish sums
 // them with dense_value's arithmetic in its order, or calls dense_value for a
 // pixel outside the fast path.
-template <typename T>
+template <typename T, int NC = 2>
 struct DenseG {
-    T wk[2][2], uk[2][2], g[2][2];
+    T wk[NC][NC], uk[NC][NC], g[NC][NC];
     T f00, f01, f10, f11, ffx, ffy;
     bool fast;
 };
-template <typename T, typename V>
-__device__ __forceinline__ void dense_gather(const V &J, const int x, const int y, DenseG<T> &G) {
+template <typename T, int NC, typename V>
+__device__ __forceinline__ void dense_gather(const V &J, const int x, const int y, DenseG<T, NC> &G) {
 #pragma clang fp contract(off)
     const int P = J.patch, st = J.stride;
     const T *rec_u = static_cast<const T *>(J.rec_u);
@@ -714,8 +721,7 @@ __device__ __forceinline__ void dense_gather(const V &J, const int x, const int 
         G.f11 = Uc[(size_t)my1 * J.Wc + mx1];
     }
     const int ncx = xhi - xlo + 1 + (xex >= 0 ? 1 : 0), ncy = yhi - ylo + 1 + (yex >= 0 ? 1 : 0);
-    G.fast = ncx <= 2 && ncy <= 2;
-    constexpr int NC = 2;
+    G.fast = ncx <= NC && ncy <= NC;
     int px[NC], py[NC], jxs[NC], jys[NC];
     bool vx[NC], vy[NC];
 #pragma unroll
@@ -741,16 +747,16 @@ __device__ __forceinline__ void dense_gather(const V &J, const int x, const int 
             if (!v) G.wk[iy][ix] = T(0);
         }
 }
-template <typename T, bool U8, typename V>
+template <typename T, bool U8, int NC, typename V>
 __device__ __forceinline__ T dense_finish(const V &J, const int x, const int y, const KParams &kp,
-                                          const DenseG<T> &G) {
+                                          const DenseG<T, NC> &G) {
 #pragma clang fp contract(off)
-    if (!G.fast) return dense_value<T, U8>(J, x, y, kp);
+    if (!G.fast) return dense_value<T, U8, 3>(J, x, y, kp);
     T A = 0, B = 0;
 #pragma unroll
-    for (int iy = 0; iy < 2; iy++)
+    for (int iy = 0; iy < NC; iy++)
 #pragma unroll
-        for (int ix = 0; ix < 2; ix++)
+        for (int ix = 0; ix < NC; ix++)
             if (G.wk[iy][ix] > T(0)) {
                 const T w = G.wk[iy][ix] * G.g[iy][ix];
                 A += w;
@@ -953,25 +959,25 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
                     // every block has a share) and do not store it
                     const int ic = min(ia, i1 - 1);
                     const int ya = div_exact(ic, inv_wc), xa = ic - ya * J.Wc;
-                    DenseG<T> Gt, Gs;
-                    dense_gather<T>(D, tx, ty, Gt);
-                    dense_gather<T>(D, xa, ya, Gs);
-                    F = dense_finish<T, false>(D, tx, ty, kp, Gt);
-                    const T Us = dense_finish<T, false>(D, xa, ya, kp, Gs);
+                    DenseG<T, 2> Gt, Gs;
+                    dense_gather<T, 2>(D, tx, ty, Gt);
+                    dense_gather<T, 2>(D, xa, ya, Gs);
+                    F = dense_finish<T, false, 2>(D, tx, ty, kp, Gt);
+                    const T Us = dense_finish<T, false, 2>(D, xa, ya, kp, Gs);
                     if (ia < i1) static_cast<T *>(J.Uc)[ia] = Us;
                     for (int i = ia + kBlock; i < i1; i += kBlock) {
                         const int yy = div_exact(i, inv_wc), xx = i - yy * J.Wc;
-                        static_cast<T *>(J.Uc)[i] = dense_value<T, false>(D, xx, yy, kp);
+                        static_cast<T *>(J.Uc)[i] = dense_value<T, false, 3>(D, xx, yy, kp);
                     }
                 } else {
-                    F = dense_value<T, false>(D, tx, ty, kp);
+                    F = dense_value<T, false, 3>(D, tx, ty, kp);
                     if constexpr (!U8) {
                         const int n1 = J.Wc * J.Hc, nblk = J.ny * bpr, chunk = (n1 + nblk - 1) / nblk;
                         const int i1 = min(n1, (lb + 1) * chunk);
                         const double inv_wc = 1.0 / (double)J.Wc;
                         for (int i = lb * chunk + (int)threadIdx.x; i < i1; i += kBlock) {
                             const int yy = div_exact(i, inv_wc), xx = i - yy * J.Wc;
-                            static_cast<T *>(J.Uc)[i] = dense_value<T, false>(D, xx, yy, kp);
+                            static_cast<T *>(J.Uc)[i] = dense_value<T, false, 3>(D, xx, yy, kp);
                         }
                     }
                 }
