@@ -495,40 +495,54 @@ __global__ __launch_bounds__(kBlock) void k_pyr2(const JobPack<Pyr2Job> pk, KPar
         }
     }
     __syncthreads();
-    // pass 2: the in-image level-(l+1) values, their validity (the 2 x 2
-    // children: rows 2 r + 2, 2 r + 3 of H), the owned writes
+    // pass 2: the level-(l+1) values, their validity (the 2 x 2 children:
+    // rows 2 r + 2, 2 r + 3 of H) and the owned writes.  Without level l+2,
+    // the in-image entries; with it, every entry of the mid region, an
+    // out-of-image one computed at its reflected position (always inside the
+    // region): the same value as a copy of that entry, without a second pass
+    // and barrier.
+    auto mid_value = [&](int img, int r, int c, int ym) -> T {
+        const bool row2 = 2 * ym + 1 < J.hs;
+        T acc = 0;
+#pragma unroll
+        for (int a = 0; a < 5; a++) acc += (T)kBinom5[a] * (T)Hs[img][2 * r + a][c];
+        const bool ok = Vs[img][2 * r + 2][c] == 3u && (!row2 || Vs[img][2 * r + 3][c] == 3u);
+        return ok ? acc : -acc;
+    };
     constexpr int NQ2 = (kP2MY * kP2MX + kBlock - 1) / kBlock;
-    const int n2 = (yb - ya) * ncol;
+    if (!J.has2) {
+        const int n2 = (yb - ya) * ncol;
+#pragma unroll
+        for (int it = 0; it < NQ2; it++) {
+            const int q = (int)threadIdx.x + it * kBlock;
+            if (q >= n2) continue;
+            const int r = row_of(q), c = q - r * ncol;
+            const int ym = ya + r, xm = xa + c;
+            const bool own = ym >= 2 * y2_0 && ym < 2 * y2_0 + 2 * kP2Y && xm >= 2 * x2_0 && xm < 2 * x2_0 + 2 * kP2X;
+#pragma unroll
+            for (int img = 0; img < 2; img++)
+                if (own) static_cast<T *>(img ? J.mid_r : J.mid_l)[(size_t)ym * J.wm + xm] = mid_value(img, r, c, ym);
+        }
+        return;  // uniform over the block
+    }
+    const bool nearm = J.wm >= 3 && J.hm >= 3;
 #pragma unroll
     for (int it = 0; it < NQ2; it++) {
         const int q = (int)threadIdx.x + it * kBlock;
-        if (q >= n2) continue;
-        const int r = row_of(q), c = q - r * ncol;
-        const int ym = ya + r, xm = xa + c;
-        const bool own = ym >= 2 * y2_0 && ym < 2 * y2_0 + 2 * kP2Y && xm >= 2 * x2_0 && xm < 2 * x2_0 + 2 * kP2X;
-        const bool row2 = 2 * ym + 1 < J.hs;
+        const int t = q / kP2MX, cc = q - t * kP2MX;
+        const int vy = vy0 + t, vx = vx0 + cc;
+        if (q >= kP2MY * kP2MX || vy >= vy_end || vx >= vx_end) continue;
+        const int ym = nearm ? reflect101_near(vy, J.hm) : reflect101(vy, J.hm);
+        const int xm = nearm ? reflect101_near(vx, J.wm) : reflect101(vx, J.wm);
+        const int r = ym - ya, c = xm - xa;
+        const bool own = vy == ym && vx == xm && ym >= 2 * y2_0 && ym < 2 * y2_0 + 2 * kP2Y &&
+                         xm >= 2 * x2_0 && xm < 2 * x2_0 + 2 * kP2X;
 #pragma unroll
         for (int img = 0; img < 2; img++) {
-            T acc = 0;
-#pragma unroll
-            for (int a = 0; a < 5; a++) acc += (T)kBinom5[a] * (T)Hs[img][2 * r + a][c];
-            const bool ok = Vs[img][2 * r + 2][c] == 3u && (!row2 || Vs[img][2 * r + 3][c] == 3u);
-            const T v = ok ? acc : -acc;
-            mid[img][ym - vy0][xm - vx0] = v;
+            const T v = mid_value(img, r, c, ym);
+            mid[img][t][cc] = v;
             if (own) static_cast<T *>(img ? J.mid_r : J.mid_l)[(size_t)ym * J.wm + xm] = v;
         }
-    }
-    if (!J.has2) return;  // uniform over the block
-    __syncthreads();
-    // out-of-image mid entries: copies of their reflected positions
-    for (int q = (int)threadIdx.x; q < kP2MY * kP2MX; q += kBlock) {
-        const int t = q / kP2MX, c = q - t * kP2MX;
-        const int vy = vy0 + t, vx = vx0 + c;
-        if (vy >= vy_end || vx >= vx_end) continue;
-        if (vy >= 0 && vy < J.hm && vx >= 0 && vx < J.wm) continue;
-        const int ym = reflect101(vy, J.hm), xm = reflect101(vx, J.wm);
-#pragma unroll
-        for (int img = 0; img < 2; img++) mid[img][t][c] = mid[img][ym - vy0][xm - vx0];
     }
     __syncthreads();
     // level l+2: thread = (image, pixel of the kP2X x kP2Y tile)
