@@ -439,15 +439,18 @@ __global__ __launch_bounds__(kBlock) void k_pyr2(const JobPack<Pyr2Job> pk, KPar
     const int ya = J.has2 ? max(vy0, 0) : 2 * y2_0, yb = min(vy_end, J.hm);
     const int ncol = xb - xa, nhrow = 2 * (yb - ya - 1) + 5;
     // pass 1: H[r][c] = sum_b w_b src(row(2 ya - 2 + r), col(2 (xa + c) + b - 2)).
-    // Fixed trip count and clamped indices keep the loop one basic block, so
-    // every load of the thread is in flight before the first sum.
-    constexpr int NQ1 = (kP2HY * kP2MX + kBlock - 1) / kBlock;
-    const int n1 = nhrow * ncol;
-    // q / ncol for the region's small indices without an integer division
-    const double inv_ncol = 1.0 / (double)ncol;
+    // A thread takes the entries c, c + 1 of a row together: their taps
+    // overlap in three columns, so 7 loads serve both (the loads pass through
+    // the compute unit's address unit one instruction at a time).  Fixed trip
+    // count and clamped indices keep the loop one basic block, so every load
+    // of the thread is in flight before the first sum.
+    const int npr = (ncol + 1) / 2, np = nhrow * npr;  // entry pairs per row, in all
+    constexpr int NP1 = (kP2HY * ((kP2MX + 1) / 2) + kBlock - 1) / kBlock;
+    // q / n for the region's small indices without an integer division
+    const double inv_ncol = 1.0 / (double)ncol, inv_npr = 1.0 / (double)npr;
     auto row_of = [&](int q) { return div_exact(q, inv_ncol); };
-    T hv[NQ1][2];
-    uint32_t vb[NQ1][2];  // validity of the source pixels at columns xc, xc + 1 of the row
+    T hv[NP1][2][2];
+    uint32_t vb[NP1][2][2];  // validity of the source pixels at columns xc, xc + 1 of the row
     // every tap is within 2 of the image (one reflection) unless a side < 3:
     // one uniform branch picks a straight-line copy of the loop, so that
     // every load of the thread goes out back to back
@@ -458,40 +461,46 @@ __global__ __launch_bounds__(kBlock) void k_pyr2(const JobPack<Pyr2Job> pk, KPar
             else return reflect101(i, n);
         };
 #pragma unroll
-        for (int it = 0; it < NQ1; it++) {
-            const int q = min((int)threadIdx.x + it * kBlock, n1 - 1);
-            const int r = row_of(q), c = q - r * ncol;
+        for (int it = 0; it < NP1; it++) {
+            const int pq = min((int)threadIdx.x + it * kBlock, np - 1);
+            const int r = div_exact(pq, inv_npr), c = 2 * (pq - r * npr);
             const size_t r0 = (size_t)refl(2 * ya - 2 + r, J.hs) * J.src_pitch;
             const int xc = 2 * (xa + c);
 #pragma unroll
             for (int img = 0; img < 2; img++) {
                 const void *src = img ? J.src_r : J.src_l;
-                T h = 0;
-                uint32_t bits = 0;
+                T x[7];
+                bool v[7];
 #pragma unroll
-                for (int b = 0; b < 5; b++) {
-                    bool v;
-                    const T x = pix<T, U8>(src, r0 + refl(xc + b - 2, J.ws), kp, v);
-                    h += (T)kBinom5[b] * x;
-                    if (b == 2) bits |= v ? 1u : 0u;
-                    if (b == 3) bits |= (v || xc + 1 >= J.ws) ? 2u : 0u;  // a missing child counts as valid
+                for (int k = 0; k < 7; k++) x[k] = pix<T, U8>(src, r0 + refl(xc + k - 2, J.ws), kp, v[k]);
+#pragma unroll
+                for (int e = 0; e < 2; e++) {
+                    T h = 0;
+#pragma unroll
+                    for (int b = 0; b < 5; b++) h += (T)kBinom5[b] * x[2 * e + b];
+                    hv[it][e][img] = h;
+                    // a missing child counts as valid
+                    vb[it][e][img] = (v[2 * e + 2] ? 1u : 0u) | ((v[2 * e + 3] || xc + 2 * e + 1 >= J.ws) ? 2u : 0u);
                 }
-                hv[it][img] = h;
-                vb[it][img] = bits;
             }
         }
     };
     if (J.ws >= 3 && J.hs >= 3) pass1(std::true_type());
     else pass1(std::false_type());
 #pragma unroll
-    for (int it = 0; it < NQ1; it++) {
-        const int q = (int)threadIdx.x + it * kBlock;
-        if (q < n1) {
-            const int r = row_of(q), c = q - r * ncol;
-            Hs[0][r][c] = (HT)hv[it][0];
-            Hs[1][r][c] = (HT)hv[it][1];
-            Vs[0][r][c] = (uint8_t)vb[it][0];
-            Vs[1][r][c] = (uint8_t)vb[it][1];
+    for (int it = 0; it < NP1; it++) {
+        const int pq = (int)threadIdx.x + it * kBlock;
+        if (pq < np) {
+            const int r = div_exact(pq, inv_npr), c = 2 * (pq - r * npr);
+#pragma unroll
+            for (int e = 0; e < 2; e++) {
+                if (c + e >= ncol) continue;
+#pragma unroll
+                for (int img = 0; img < 2; img++) {
+                    Hs[img][r][c + e] = (HT)hv[it][e][img];
+                    Vs[img][r][c + e] = (uint8_t)vb[it][e][img];
+                }
+            }
         }
     }
     __syncthreads();
