@@ -58,14 +58,15 @@ def lk_bytes(W, H, patches, esz, level0, coarse_px, fold=None):
     written (u, w, u0 in esz bytes and a status byte) and the coarser level's
     field that seeds the initial shifts (coarse_px elements, 0 at the
     coarsest level): read, or -- when the launch densifies that level itself,
-    fold = (its patches, the pixels of the level below it) -- written, with
-    that level's records (u, w) and its own fallback field read."""
+    fold = (its patches, the pixels of the level below it) -- that level's
+    records (u, w) and its own fallback field read, and the field written
+    except at level 0 (no finer level reads the level-1 field)."""
     img = 2 * W * H * (1 if level0 else esz)
     b = img + patches * (3 * esz + 1)
     if fold is None:
         return b + coarse_px * esz
     patches1, px2 = fold
-    return b + coarse_px * esz + patches1 * 2 * esz + px2 * esz
+    return b + (0 if level0 else coarse_px * esz) + patches1 * 2 * esz + px2 * esz
 
 
 def dense_flops(pixels, taps):
@@ -79,7 +80,7 @@ def dense_flops(pixels, taps):
 # WRITE_SIZE, scaled by a 256 MiB device copy (fetch x 1.9998, write x 1.0);
 # valid only for the kernel source they were taken on (sha256 prefix).
 KERNEL_SRC = os.path.join(ROOT, "paper_2106_07136_amd", "csrc", "bdis_kernels.hpp")
-MEASURED_TRAFFIC = {("lk_f64_p8_l0", "601649da07519739"): 6581659}
+MEASURED_TRAFFIC = {("lk_f64_p8_l0", "844ab7a3bce6660c"): 5597021}
 
 
 def measured_traffic(kernel):
@@ -409,7 +410,7 @@ def main():
         if coarse and info["ny"][lvl] * bpr <= 3 * torch.cuda.get_device_properties(0).multi_processor_count:
             px2 = info["width"][lvl + 2] * info["height"][lvl + 2] if lvl + 2 < info["levels"] else 0
             fold = (info["nx"][lvl + 1] * info["ny"][lvl + 1], px2)
-            fl += dense_flops(coarse, 4 * npatch)
+            fl += dense_flops(0 if lvl == 0 else coarse, 4 * npatch)
         nbytes = lk_bytes(info["width"][lvl], info["height"][lvl], npatch, esz, lvl == 0, coarse, fold)
         roof = {"kernel": dom, "bound": "alu", "achieved": fl / avg_s / 1e12, "peak": peak / 1e12,
                 "unit": "TFLOP/s", "frac": fl / avg_s / peak, "traffic": measured_traffic(dom),
