@@ -1067,16 +1067,6 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
         for (int c = 0; c <= P; c++)
             if constexpr (!U8) v[c] = fabs(v[c]);
     };
-    // I_r at x0 + c + shift for the patch row, shift = xi0 - x0 + uf with
-    // 0 <= uf < 1, coordinate clamped to [0, W-1]: (1 - f) R[m] + f R[m + 1]
-    // on the clamped taps, which for a clamped column are the same pixel
-    auto sample = [&](int xi0, T uf, T *out) {
-        T v[P + 1];
-        load_run(xi0, v);
-        const T omf = T(1) - uf;
-#pragma unroll
-        for (int c = 0; c < P; c++) out[c] = omf * v[c] + uf * v[c + 1];
-    };
 
     int nloc = 0;
     T gsum = 0;
@@ -1164,26 +1154,74 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
             // sum d^2 - (sum d)^2 / n with every window sum reduced at once
             // (in double precision the two forms agree to ~1e-13 relative)
             const int cw = (kp.window - 1) / 2;
+            // The launches of at most two blocks per CU (MERGE) have the
+            // registers to read every window sample's run, and the gate's
+            // taps, in one batch (WBATCH); the others read them one by one.
+            constexpr bool WBATCH = MERGE && P <= 12;
             // WN: compile-time bound on the window count (kp.window <= WN),
             // so that only the sums of samples that exist are reduced
             auto window_post = [&]() -> T {
+                // With WBATCH the runs R[clamp(xi0 + c, 0, W-1)], c = 0..P,
+                // of every sample are read before any is used: one LDS round
+                // trip for all rather than one per sample.  A run inside the
+                // staged span is read as is; any other is read with its start
+                // clamped into the span and then again per column (load_run's
+                // slow path).
+                constexpr int WB = WBATCH ? WN : 1;
+                int wxi[WB];
+                T wuf[WB], wv[WB][P + 1];
+                if constexpr (WBATCH) {
+                    bool staged = true;
+#pragma unroll
+                    for (int i = 0; i < WN; i++) {
+                        wxi[i] = 0;
+                        wuf[i] = 0;
+                        if (i < kp.window) {
+                            const T ud = u + (T)(i - cw) * (T)kp.window_step;
+                            wxi[i] = x0 + ishift(ud, wuf[i]);
+                            const int xc = min(max(wxi[i], -(P + 1)), W - 1);
+                            const int xs = min(max(xc, vlo), vhi - P);
+                            staged = staged && xs == xc;
+#pragma unroll
+                            for (int c = 0; c <= P; c++) wv[i][c] = Rs[rbase + xs + c];
+                        }
+                    }
+                    if (!staged) {
+#pragma unroll
+                        for (int i = 0; i < WN; i++) {
+                            const int xc = min(max(wxi[i], -(P + 1)), W - 1);
+                            if (i < kp.window && (xc < vlo || xc + P > vhi))
+                                fetch(wxi[i], wv[i], std::integral_constant<int, P + 1>());
+                        }
+                    }
+                }
                 T acc[2 * WN];
 #pragma unroll
                 for (int i = 0; i < WN; i++) {
                     acc[2 * i] = 0;
                     acc[2 * i + 1] = 0;
                     if (i < kp.window) {
-                        T ud = u + (T)(i - cw) * (T)kp.window_step;
-                        T uf;
-                        const int xi0 = x0 + ishift(ud, uf);
-                        T d[P];
-                        sample(xi0, uf, d);
+                        // I_r at x0 + c + shift, shift = xi0 - x0 + uf with
+                        // 0 <= uf < 1, coordinate clamped to [0, W-1]:
+                        // (1 - f) R[m] + f R[m + 1] on the clamped taps, which
+                        // for a clamped column are the same pixel
+                        T uf, v[P + 1];
+                        if constexpr (WBATCH) {
+                            uf = wuf[i];
+#pragma unroll
+                            for (int c = 0; c <= P; c++) v[c] = U8 ? wv[i][c] : T(fabs(wv[i][c]));
+                        } else {
+                            const T ud = u + (T)(i - cw) * (T)kp.window_step;
+                            load_run(x0 + ishift(ud, uf), v);
+                        }
+                        const T omf = T(1) - uf;
                         // two interleaved chains per sum: half the dependent
                         // adds (one wave per SIMD at the small levels)
                         T s0 = 0, s1 = 0, e0 = 0, e1 = 0;
 #pragma unroll
                         for (int c = 0; c < P; c++) {
-                            const T q = ((vmask >> c) & 1u) ? d[c] - Tv[c] : T(0);
+                            const T d = omf * v[c] + uf * v[c + 1];
+                            const T q = ((vmask >> c) & 1u) ? d - Tv[c] : T(0);
                             if (c & 1) { s1 += q; e1 += q * q; }
                             else { s0 += q; e0 += q * q; }
                         }
@@ -1212,16 +1250,18 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
                 }
                 return T(1) / seg_sum<SEG>(term);
             };
-            post = window_post();
             // gamma gate at the final shift: left valid, sample inside the
-            // row, both right taps valid (Sec. 3, Sec. 3.2)
+            // row, both right taps valid (Sec. 3, Sec. 3.2).  With WBATCH its
+            // taps are read first, so that they arrive with the window's.
             T uc = fmin(fmax(u, ulo), uhi);
             T ui = floor(uc), uf = uc - ui;
             int xi0 = x0 + (int)ui;
             // taps m = min(xi, W-2) and m + 1 for xi = xi0 .. xi0+P-1
             int m0 = min(max(xi0, 0), W - 2);
             T v[P + 2];
-            fetch(m0, v, std::integral_constant<int, P + 2>());
+            if constexpr (WBATCH) fetch(m0, v, std::integral_constant<int, P + 2>());
+            post = window_post();
+            if constexpr (!WBATCH) fetch(m0, v, std::integral_constant<int, P + 2>());
             uint32_t rmask = 0;  // bit j: right tap m0 + j is valid
 #pragma unroll
             for (int j = 0; j < P + 2; j++) {
