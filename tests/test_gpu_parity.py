@@ -71,6 +71,43 @@ def test_e2e_parity_large(torch_cuda, ref, W, H, dmax, seed, levels):
     assert_parity(gpu, exp, f"{W}x{H}")
 
 
+def _shifted(left, shift):
+    """Right image whose pixel x is the left image's x + shift (border
+    column repeated): disparity `shift` everywhere."""
+    right = np.empty_like(left)
+    if shift > 0:
+        right[:, :-shift] = left[:, shift:]
+        right[:, -shift:] = left[:, -1:]
+    else:
+        s = -shift
+        right[:, s:] = left[:, :-s]
+        right[:, :s] = left[:, :1]
+    return right
+
+
+@pytest.mark.parametrize("shift,dmax", [(160, 4.0), (-80, 1000.0)])
+def test_iterates_outside_staged_span(torch_cuda, ref, shift, dmax):
+    """A 1920x1080 pair shifted by a whole number of pixels, with a
+    max_disparity hint that stages each LK block's right-image columns away
+    from where its iterates go: 160 px against a hint of 4 (samples left of
+    the staged span at level 0), and -80 px, the right image moved the other
+    way, against a hint of 1000 (no column staged beyond the block's right
+    margin, at levels 0 to 2; level 2 runs in the launches that read the
+    window samples in one batch).  Those patches' iterations, window samples
+    and gate taps read the image from global memory instead of LDS, with the
+    same values."""
+    from paper_2106_07136_amd import bdis
+    print(f"case shift {shift} max_disparity {dmax}", flush=True)
+    left = synth.make_pair(1920, 1080, 192.0, 61).left
+    right = _shifted(left, shift)
+    gp = bdis.Params(levels=7, iters=12, max_disparity=dmax)
+    _, gpu = _run(torch_cuda, gp, left, right)
+    exp = ref.compute(left, right, oracle_params(ref, gp))
+    # the iterates do sit at the shift (so outside the staged columns)
+    assert abs(np.median(exp[np.isfinite(exp)]) - shift) < 0.5
+    assert_parity(gpu, exp, f"shift {shift}")
+
+
 def test_stage_parity_small(torch_cuda, ref):
     """Per level: pyramid values and validity, initial and final patch
     shifts, posteriors, patch outcomes and dense fields."""
