@@ -163,6 +163,32 @@ def _batch_io(pairs):
     return L, R, O, [p.d_max for p in pairs]
 
 
+def profile_leg(name, calls, precision):
+    """One batched workload alone, for a profiler run: 'batch' is the 64-pair
+    mixed batch at patch 8 / stride 4 in the level graph; 'learned640' the 64
+    held-out 640x480 pairs with the learned init (32 channels, 8 fine-level
+    iterations), also in the level graph.  Prints one JSON line with the
+    time per call."""
+    from paper_2106_07136_amd import bdis, net, synth, train
+    if name == "batch":
+        pairs = synth.make_pairs(synth.mixed_batch_spec(3000))
+        h = bdis.Bdis(bdis.Params(levels=0, iters=12, precision=precision))
+    elif name == "learned640":
+        pairs = synth.make_pairs([(640, 480, 64.0, 90000 + i) for i in range(64)])
+        flat, C, _ = train.load(WEIGHTS.format(C=32))
+        pn = net.ProposalNet(C)
+        pn.set_params(flat)
+        h = bdis.Bdis(bdis.Params(levels=0, iters=12, precision=precision, init=1, learned_iters=8))
+        h.set_net(pn)
+    else:
+        raise SystemExit(f"unknown --profile-leg {name!r}: batch or learned640")
+    L, R, O, dm = _batch_io(pairs)
+    ms = timed(lambda: h.compute_batch(L, R, O, max_disparity=dm), calls, 2)
+    mpx = sum(p.left.size for p in pairs) / 1e6
+    print(json.dumps({"profile_leg": name, "calls": calls, "warmup": 2, "ms_per_call": ms,
+                      "mpixel_per_call": mpx, **accuracy(O, pairs)}), flush=True)
+
+
 def batched_leg(batch, calib, steps, warmup, precision):
     """Mixed batch of 64 pairs per call, patch/stride autotuned first; the
     three batch executions are timed at the paper's patch 8 / stride 4."""
@@ -316,6 +342,9 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (scale for HBM byte counters) and exit")
+    ap.add_argument("--profile-leg", choices=("batch", "learned640"), default=None,
+                    help="only run this batched workload (for a profiler run) and exit")
+    ap.add_argument("--profile-calls", type=int, default=50)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); stereo pairs are "
@@ -332,6 +361,9 @@ def main():
             dst_t.copy_(src_t)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "copies": 5}), flush=True)
+        return
+    if args.profile_leg:
+        profile_leg(args.profile_leg, args.profile_calls, args.precision)
         return
 
     from paper_2106_07136_amd import bdis, synth
