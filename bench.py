@@ -80,7 +80,7 @@ def dense_flops(pixels, taps):
 # WRITE_SIZE, scaled by a 256 MiB device copy (fetch x 1.9998, write x 1.0);
 # valid only for the kernel source they were taken on (sha256 prefix).
 KERNEL_SRC = os.path.join(ROOT, "paper_2106_07136_amd", "csrc", "bdis_kernels.hpp")
-MEASURED_TRAFFIC = {("lk_f64_p8_l0", "273a73a99d8e6593"): 5604700}
+MEASURED_TRAFFIC = {("lk_f64_p8_l0", "9930ccb6c3c41b92"): 5579106}
 
 
 def measured_traffic(kernel):

@@ -1053,16 +1053,15 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
     // A start left of -(P + 1) or right of W - 1 gives the same values as
     // that bound (every column clamps to the border), so the clamped start
     // reads one contiguous run of the staged row; only a run that leaves the
-    // staged span takes the per-column path.
+    // staged span takes the per-column path.  The run is read from LDS in
+    // any case, its start clamped into the span (no branch before the reads),
+    // and read again per column only if that clamp moved it.
     auto load_run = [&](int xi0, T *v) {
         const int xc = min(max(xi0, -(P + 1)), W - 1);
-        if (xc >= vlo && xc + P <= vhi) {
-            const int base = rbase + xc;
+        const int xs = min(max(xc, vlo), vhi - P);
 #pragma unroll
-            for (int c = 0; c <= P; c++) v[c] = Rs[base + c];
-        } else {
-            fetch(xi0, v, std::integral_constant<int, P + 1>());
-        }
+        for (int c = 0; c <= P; c++) v[c] = Rs[rbase + xs + c];
+        if (xs != xc) fetch(xi0, v, std::integral_constant<int, P + 1>());
 #pragma unroll
         for (int c = 0; c <= P; c++)
             if constexpr (!U8) v[c] = fabs(v[c]);
