@@ -40,3 +40,17 @@ def oracle_params(ref, gp):
                       window_step=gp.window_step, gamma=gp.gamma, s_mode=gp.s_mode,
                       fusion=gp.fusion, valid_lo=gp.valid_lo, valid_hi=gp.valid_hi,
                       eps_h=float(np.float32(gp.eps_h)), conv_tol=float(np.float32(gp.conv_tol)))
+
+
+def shifted_right(left, shift):
+    """Right image whose pixel x is the left image's x + shift (border
+    column repeated): disparity `shift` everywhere."""
+    right = np.empty_like(left)
+    if shift > 0:
+        right[:, :-shift] = left[:, shift:]
+        right[:, -shift:] = left[:, -1:]
+    else:
+        s = -shift
+        right[:, s:] = left[:, :-s]
+        right[:, :s] = left[:, :1]
+    return right

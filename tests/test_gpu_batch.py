@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 from paper_2106_07136_amd import synth
-from tests.parity_util import assert_parity, oracle_params
+from tests.parity_util import assert_parity, oracle_params, shifted_right
 
 pytestmark = pytest.mark.gpu
 
@@ -65,6 +65,30 @@ def test_batch_equals_single(torch_cuda, mode):
     base = bdis.Params(levels=0, iters=10)
     pairs = _pairs(torch_cuda, MIXED)
     ref = _single(torch_cuda, base, pairs)
+    h = bdis.Bdis(base)
+    h.set_batch_mode(mode)
+    got = _run_batch(h, pairs)
+    assert h.batch_error() == 0
+    for i, (g, r) in enumerate(zip(got, ref)):
+        np.testing.assert_array_equal(_bits(g), _bits(r), err_msg=f"pair {i} mode {mode}")
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_batch_outside_staged_span_equals_single(torch_cuda, mode):
+    """The shifted 1920x1080 pairs whose iterates leave the LK blocks'
+    staged columns (160 px against a max_disparity of 4, -80 px against
+    1000), batched with two ordinary pairs: every execution gives what
+    bdis_compute gives on each pair alone, bit for bit.  Their fallback
+    reads then run in the batch's larger launches and, in mode 2, in the
+    persistent kernel."""
+    from paper_2106_07136_amd import bdis
+    torch = torch_cuda
+    left = synth.make_pair(1920, 1080, 192.0, 61).left
+    pairs = [(None, torch.from_numpy(left).cuda(), torch.from_numpy(shifted_right(left, s)).cuda(), d)
+             for s, d in ((160, 4.0), (-80, 1000.0))]
+    pairs += _pairs(torch, [(640, 480, 64.0, 7), (320, 240, 32.0, 2)])
+    base = bdis.Params(levels=7, iters=12)
+    ref = _single(torch, base, pairs)
     h = bdis.Bdis(base)
     h.set_batch_mode(mode)
     got = _run_batch(h, pairs)

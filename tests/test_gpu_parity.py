@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 from paper_2106_07136_amd import synth
-from tests.parity_util import assert_parity, oracle_params, parity
+from tests.parity_util import assert_parity, oracle_params, parity, shifted_right
 
 pytestmark = pytest.mark.gpu
 
@@ -71,20 +71,6 @@ def test_e2e_parity_large(torch_cuda, ref, W, H, dmax, seed, levels):
     assert_parity(gpu, exp, f"{W}x{H}")
 
 
-def _shifted(left, shift):
-    """Right image whose pixel x is the left image's x + shift (border
-    column repeated): disparity `shift` everywhere."""
-    right = np.empty_like(left)
-    if shift > 0:
-        right[:, :-shift] = left[:, shift:]
-        right[:, -shift:] = left[:, -1:]
-    else:
-        s = -shift
-        right[:, s:] = left[:, :-s]
-        right[:, :s] = left[:, :1]
-    return right
-
-
 @pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("shift,dmax", [(160, 4.0), (-80, 1000.0)])
 def test_iterates_outside_staged_span(torch_cuda, ref, shift, dmax, precision):
@@ -100,7 +86,7 @@ def test_iterates_outside_staged_span(torch_cuda, ref, shift, dmax, precision):
     from paper_2106_07136_amd import bdis
     print(f"case shift {shift} max_disparity {dmax} precision {precision}", flush=True)
     left = synth.make_pair(1920, 1080, 192.0, 61).left
-    right = _shifted(left, shift)
+    right = shifted_right(left, shift)
     gp = bdis.Params(levels=7, iters=12, max_disparity=dmax, precision=precision)
     _, gpu = _run(torch_cuda, gp, left, right)
     exp = ref.compute(left, right, oracle_params(ref, gp))
