@@ -71,9 +71,10 @@ def test_e2e_parity_large(torch_cuda, ref, W, H, dmax, seed, levels):
     assert_parity(gpu, exp, f"{W}x{H}")
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-@pytest.mark.parametrize("shift,dmax", [(160, 4.0), (-80, 1000.0)])
-def test_iterates_outside_staged_span(torch_cuda, ref, shift, dmax, precision):
+@pytest.mark.parametrize("shift,dmax,precision,patch", [
+    (160, 4.0, 0, 8), (160, 4.0, 1, 8), (-80, 1000.0, 0, 8), (-80, 1000.0, 1, 8),
+    (160, 4.0, 0, 12), (-80, 1000.0, 0, 12)])
+def test_iterates_outside_staged_span(torch_cuda, ref, shift, dmax, precision, patch):
     """A 1920x1080 pair shifted by a whole number of pixels, with a
     max_disparity hint that stages each LK block's right-image columns away
     from where its iterates go: 160 px against a hint of 4 (samples left of
@@ -82,12 +83,15 @@ def test_iterates_outside_staged_span(torch_cuda, ref, shift, dmax, precision):
     margin, at levels 0 to 2; level 2 runs in the launches that read the
     window samples in one batch).  Those patches' iterations, window samples
     and gate taps read the image from global memory instead of LDS, with the
-    same values.  In FP32 (precision = 1) the bar is test_fp32_option's."""
+    same values.  In FP32 (precision = 1) the bar is test_fp32_option's.
+    Patch 12 (16 patches per block, 16-lane segments) moves the span edges:
+    there -80 px leaves it at levels 0 and 1, 160 px only for the first
+    patch of each level-0 block."""
     from paper_2106_07136_amd import bdis
-    print(f"case shift {shift} max_disparity {dmax} precision {precision}", flush=True)
+    print(f"case shift {shift} max_disparity {dmax} precision {precision} patch {patch}", flush=True)
     left = synth.make_pair(1920, 1080, 192.0, 61).left
     right = shifted_right(left, shift)
-    gp = bdis.Params(levels=7, iters=12, max_disparity=dmax, precision=precision)
+    gp = bdis.Params(levels=7, iters=12, max_disparity=dmax, precision=precision, patch=patch)
     _, gpu = _run(torch_cuda, gp, left, right)
     exp = ref.compute(left, right, oracle_params(ref, gp))
     # the iterates do sit at the shift (so outside the staged columns)
