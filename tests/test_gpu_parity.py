@@ -159,6 +159,9 @@ EDGE = {
     "gamma_025": (160, 120, dict(levels=3, gamma=0.25)),
     "no_iters": (96, 64, dict(levels=2, iters=0)),
     "valid_band": (128, 96, dict(levels=2, valid_lo=90, valid_hi=160)),
+    # stride 8: the level-1 launch densifies 320 level-2 pixels per block, so
+    # the folded densification's share loop runs past its first pixel
+    "stride8_640x480": (640, 480, dict(levels=5, stride=8)),
 }
 
 
