@@ -60,7 +60,10 @@ def test_e2e_parity_configs(torch_cuda, ref, name):
     assert_parity(gpu, exp, name)
 
 
-@pytest.mark.parametrize("W,H,dmax,seed,levels", [(1280, 720, 128.0, 3001, 6), (1920, 1080, 192.0, 50000, 7)])
+# 1536x864: its level-1 launch has 642 blocks, between two and three per CU,
+# so it runs the three-blocks-per-CU build with the folded densification
+@pytest.mark.parametrize("W,H,dmax,seed,levels", [(1280, 720, 128.0, 3001, 6), (1920, 1080, 192.0, 50000, 7),
+                                                  (1536, 864, 154.0, 3002, 6)])
 def test_e2e_parity_large(torch_cuda, ref, W, H, dmax, seed, levels):
     from paper_2106_07136_amd import bdis
     print(f"case {W}x{H} seed {seed}", flush=True)
