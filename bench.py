@@ -34,6 +34,8 @@ PAPER_MPXS = 10 * 640 * 480 / 1e6  # 10 Hz at 640x480, one i5-9400 core (Sec. 3.
 PEAK_FP64_VECTOR = 78.6e12
 PEAK_FP32_VECTOR = 157.3e12
 PEAK_HBM = 8.0e12
+# LDS: 128 bytes per clock per CU (the CDNA3 rate) x 256 CUs x 2.4 GHz
+PEAK_LDS = 128 * 256 * 2.4e9
 PEAK_BF16_MFMA = 2.5e15
 
 WEIGHTS = os.path.join(ROOT, "paper_2106_07136_amd", "weights", "proposal_c{C}.npz")
@@ -81,13 +83,23 @@ def dense_flops(pixels, taps):
 # valid only for the kernel source they were taken on (sha256 prefix).
 KERNEL_SRC = os.path.join(ROOT, "paper_2106_07136_amd", "csrc", "bdis_kernels.hpp")
 MEASURED_TRAFFIC = {("lk_f64_p8_l0", "9930ccb6c3c41b92"): 5579106}
+# LDS bytes read + written per launch: rocprofv3 SQ_INSTS_LDS_LOAD_BANDWIDTH
+# + SQ_INSTS_LDS_STORE_BANDWIDTH (64-byte units), same validity rule.
+MEASURED_LDS = {("lk_f64_p8_l0", "9930ccb6c3c41b92"): (1333382 + 228480) * 64}
+
+
+def _kernel_sha():
+    import hashlib
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
 def measured_traffic(kernel):
-    import hashlib
-    with open(KERNEL_SRC, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()[:16]
-    return MEASURED_TRAFFIC.get((kernel, sha))
+    return MEASURED_TRAFFIC.get((kernel, _kernel_sha()))
+
+
+def measured_lds(kernel):
+    return MEASURED_LDS.get((kernel, _kernel_sha()))
 
 
 def cpu_baseline(pair, oparams, budget_s=20.0):
@@ -449,6 +461,10 @@ def main():
                 "algorithmic_flops": fl, "algorithmic_bytes": nbytes, "folds_densify": fold is not None,
                 "avg_us": avg_s * 1e6,
                 "hbm_GBs_algorithmic": nbytes / avg_s / 1e9, "hbm_frac_algorithmic": nbytes / avg_s / PEAK_HBM}
+        lds = measured_lds(dom)
+        roof["lds_bytes"] = lds
+        roof["lds_GBs"] = lds / avg_s / 1e9 if lds is not None else None
+        roof["lds_frac"] = lds / avg_s / PEAK_LDS if lds is not None else None
     log(f"bench: dominant kernel {dom} avg {avg_s * 1e6:.1f} us")
 
     res = {
