@@ -82,10 +82,10 @@ def dense_flops(pixels, taps):
 # WRITE_SIZE, scaled by a 256 MiB device copy (fetch x 1.9998, write x 1.0);
 # valid only for the kernel source they were taken on (sha256 prefix).
 KERNEL_SRC = os.path.join(ROOT, "paper_2106_07136_amd", "csrc", "bdis_kernels.hpp")
-MEASURED_TRAFFIC = {("lk_f64_p8_l0", "9930ccb6c3c41b92"): 5579106}
+MEASURED_TRAFFIC = {("lk_f64_p8_l0", "02f26ecdffb1884f"): 5579097}
 # LDS bytes read + written per launch: rocprofv3 SQ_INSTS_LDS_LOAD_BANDWIDTH
 # + SQ_INSTS_LDS_STORE_BANDWIDTH (64-byte units), same validity rule.
-MEASURED_LDS = {("lk_f64_p8_l0", "9930ccb6c3c41b92"): (1333382 + 228480) * 64}
+MEASURED_LDS = {("lk_f64_p8_l0", "02f26ecdffb1884f"): (1333382 + 228480) * 64}
 
 
 def _kernel_sha():
@@ -179,11 +179,14 @@ def profile_leg(name, calls, precision):
     """One batched workload alone, for a profiler run: 'batch' is the 64-pair
     mixed batch at patch 8 / stride 4 in the level graph; 'learned640' the 64
     held-out 640x480 pairs with the learned init (32 channels, 8 fine-level
-    iterations), also in the level graph.  Prints one JSON line with the
-    time per call."""
+    iterations), also in the level graph; 'plain640' the same pairs with the
+    plain init.  Prints one JSON line with the time per call."""
     from paper_2106_07136_amd import bdis, net, synth, train
     if name == "batch":
         pairs = synth.make_pairs(synth.mixed_batch_spec(3000))
+        h = bdis.Bdis(bdis.Params(levels=0, iters=12, precision=precision))
+    elif name == "plain640":
+        pairs = synth.make_pairs([(640, 480, 64.0, 90000 + i) for i in range(64)])
         h = bdis.Bdis(bdis.Params(levels=0, iters=12, precision=precision))
     elif name == "learned640":
         pairs = synth.make_pairs([(640, 480, 64.0, 90000 + i) for i in range(64)])
@@ -193,7 +196,7 @@ def profile_leg(name, calls, precision):
         h = bdis.Bdis(bdis.Params(levels=0, iters=12, precision=precision, init=1, learned_iters=8))
         h.set_net(pn)
     else:
-        raise SystemExit(f"unknown --profile-leg {name!r}: batch or learned640")
+        raise SystemExit(f"unknown --profile-leg {name!r}: batch, plain640 or learned640")
     L, R, O, dm = _batch_io(pairs)
     ms = timed(lambda: h.compute_batch(L, R, O, max_disparity=dm), calls, 2)
     mpx = sum(p.left.size for p in pairs) / 1e6
@@ -354,7 +357,7 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (scale for HBM byte counters) and exit")
-    ap.add_argument("--profile-leg", choices=("batch", "learned640"), default=None,
+    ap.add_argument("--profile-leg", choices=("batch", "plain640", "learned640"), default=None,
                     help="only run this batched workload (for a profiler run) and exit")
     ap.add_argument("--profile-calls", type=int, default=50)
     args = ap.parse_args()

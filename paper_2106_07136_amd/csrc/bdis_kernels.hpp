@@ -148,13 +148,18 @@ static_assert(sizeof(GateJob) == 4 * 8 + 8 * 4, "GateJob must have no padding");
 
 // Jobs of one launch, passed by value as the kernel argument (read through
 // the scalar path from the kernel-argument segment: no dependent load of a
-// table).  A launch carries at most kMaxJobs jobs; larger sets are split.
+// table).  A launch carries at most PackCap<Job> jobs (kMaxJobs, or more for
+// the small records of the network input and the gate, whose packs stay
+// within the same kernel-argument size); larger sets are split.
 constexpr int kMaxJobs = 24;
+template <typename Job> struct PackCap { static constexpr int value = kMaxJobs; };
+template <> struct PackCap<NetInJob> { static constexpr int value = 62; };
+template <> struct PackCap<GateJob> { static constexpr int value = 62; };
 template <typename Job>
 struct JobPack {
     int n;
     int pad_;
-    Job j[kMaxJobs];
+    Job j[PackCap<Job>::value];
 };
 
 template <typename Job>

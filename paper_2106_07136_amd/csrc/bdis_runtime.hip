@@ -371,17 +371,18 @@ struct Launch {
     int lane = 0;            // 0: the caller's stream, 1: the side stream
 };
 
-// Splits jobs into launches of at most kMaxJobs; `blocks_of` gives a job's
-// block count.
+// Splits jobs into launches of at most PackCap<Job> jobs; `blocks_of` gives
+// a job's block count.
 template <typename Job, typename F>
 void append(std::vector<Launch> &ls, Kind kind, int level, int patch, bool u8, bool f64,
             std::vector<Job> &jobs, const KParams &kp, F blocks_of) {
-    for (size_t s0 = 0; s0 < jobs.size(); s0 += kMaxJobs) {
+    constexpr size_t cap = PackCap<Job>::value;
+    for (size_t s0 = 0; s0 < jobs.size(); s0 += cap) {
         JobPack<Job> pk;
         memset(&pk, 0, sizeof pk);  // padding included: packs are compared byte for byte
         pk.n = 0;
         int blocks = 0;
-        for (size_t i = s0; i < jobs.size() && i < s0 + kMaxJobs; i++) {
+        for (size_t i = s0; i < jobs.size() && i < s0 + cap; i++) {
             memcpy(&pk.j[pk.n], &jobs[i], sizeof(Job));
             pk.j[pk.n].block0 = blocks;
             blocks += blocks_of(pk.j[pk.n]);
