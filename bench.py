@@ -102,14 +102,37 @@ def measured_lds(kernel):
     return MEASURED_LDS.get((kernel, _kernel_sha()))
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads():
+    """Threads for the CPU leg: every core this process may run on, capped by
+    the job's thread budget (OMP_NUM_THREADS when set)."""
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    cap = os.environ.get("OMP_NUM_THREADS", "")
+    return max(1, min(usable, int(cap))) if cap.isdigit() and int(cap) > 0 else usable
+
+
 def cpu_baseline(pair, oparams, budget_s=20.0):
-    """The FP64 oracle as it stands, one pair per thread, on the host's cores.
-    ctypes releases the GIL during the C call, so threads run in parallel."""
+    """The FP64 oracle as it stands, one pair per thread, on the host's usable
+    cores, plus one thread alone.  ctypes releases the GIL during the C call,
+    so the threads run in parallel."""
     from concurrent.futures import ThreadPoolExecutor
 
     import oracle
     oracle.build()
-    cores = min(16, os.cpu_count() or 1)
+    cores = host_threads()
     t0 = time.perf_counter()
     oracle.compute(pair.left, pair.right, oparams)
     t1 = time.perf_counter() - t0
@@ -123,7 +146,9 @@ def cpu_baseline(pair, oparams, budget_s=20.0):
     H = pair.left.shape[0]
     return {"value": n * W * H / wall / 1e6, "unit": "Mpixel/s", "cores": cores, "kind": "oracle",
             "sample": f"{n} runs of the 640x480 pair (seed 2) on {cores} threads, "
-                      f"{n * t1:.1f} s of CPU work; single-thread {W * H / t1 / 1e6:.3f} Mpixel/s"}
+                      f"{n * t1:.1f} s of CPU work",
+            "single_thread_value": W * H / t1 / 1e6, "nproc": os.cpu_count(),
+            "cpu_model": _cpu_model()}
 
 
 def net_flops(channels, pixels):
@@ -180,16 +205,19 @@ def profile_leg(name, calls, precision):
     mixed batch at patch 8 / stride 4 in the level graph; 'learned640' the 64
     held-out 640x480 pairs with the learned init (32 channels, 8 fine-level
     iterations), also in the level graph; 'plain640' the same pairs with the
-    plain init.  Prints one JSON line with the time per call."""
+    plain init.  Prints one JSON line with the time per call.  The pairs are
+    generated in this process, one after another: under a profiler the GPU
+    is initialised before this function runs, and a forked worker pool would
+    copy that state."""
     from paper_2106_07136_amd import bdis, net, synth, train
     if name == "batch":
-        pairs = synth.make_pairs(synth.mixed_batch_spec(3000))
+        pairs = synth.make_pairs(synth.mixed_batch_spec(3000), workers=1)
         h = bdis.Bdis(bdis.Params(levels=0, iters=12, precision=precision))
     elif name == "plain640":
-        pairs = synth.make_pairs([(640, 480, 64.0, 90000 + i) for i in range(64)])
+        pairs = synth.make_pairs([(640, 480, 64.0, 90000 + i) for i in range(64)], workers=1)
         h = bdis.Bdis(bdis.Params(levels=0, iters=12, precision=precision))
     elif name == "learned640":
-        pairs = synth.make_pairs([(640, 480, 64.0, 90000 + i) for i in range(64)])
+        pairs = synth.make_pairs([(640, 480, 64.0, 90000 + i) for i in range(64)], workers=1)
         flat, C, _ = train.load(WEIGHTS.format(C=32))
         pn = net.ProposalNet(C)
         pn.set_params(flat)
@@ -312,6 +340,29 @@ def learned_leg(pairs, channels, steps, warmup, precision, workload):
                         "channels": C, **acc_l},
             "speedup": ms_plain / ms_l, "net_mfma": mfma,
             "sweep": {str(k): {"ms_per_batch": v[0], **v[1]} for k, v in runs.items()}}
+
+
+def conv_tol_leg(pair, held, precision):
+    """Sec. 3.2's "does not converge" read as a settled last LK step
+    (conv_tol = 0.05 level px, the default) against the test switched off
+    (conv_tol = 0: only a non-finite shift or one that moved more than a
+    patch side is discarded): accuracy and coverage on the headline pair and
+    on the 64 held-out 640x480 pairs."""
+    from paper_2106_07136_amd import bdis
+    res = {"workload": "the headline 640x480 pair (seed 2, 5 levels) and 64 held-out 640x480 pairs "
+                       "(seeds 90000-90063, automatic levels), plain BDIS, 12 iterations"}
+    for tol, label in ((0.05, "conv_tol_0.05"), (0.0, "conv_tol_0")):
+        h1 = bdis.Bdis(bdis.Params(levels=5, iters=12, precision=precision, conv_tol=tol))
+        L1, R1, O1, _ = _batch_io([pair])
+        h1.compute(L1[0], R1[0], O1[0])
+        hb = bdis.Bdis(bdis.Params(levels=0, iters=12, precision=precision, conv_tol=tol))
+        L, R, O, dm = _batch_io(held)
+        hb.compute_batch(L, R, O, max_disparity=dm)
+        res[label] = {"headline_pair": accuracy(O1, [pair]), "held_out_64": accuracy(O, held)}
+        log(f"bench: {label}: {res[label]}")
+        h1.close()
+        hb.close()
+    return res
 
 
 def ablation_leg(variants, steps, warmup, precision):
@@ -493,6 +544,7 @@ def main():
             mixed, 48, args.batch_steps, 2, args.precision,
             "32x1920x1080 (seeds 50000-50031, disparity 0-192 px) + 32x640x480 (seeds 51000-51031) pairs "
             "per call, plain vs learned init (48-channel proposal net)")
+        res["convergence_test"] = conv_tol_leg(pair, held, args.precision)
         res["ablation_dis_vs_bdis"] = {
             "workload": "16 640x480 pairs per variant (diffuse: no gain field, no specular blobs, seeds "
                         "95000-95015; non-Lambertian: the full generator, seeds 95100-95115), BDIS against "

@@ -84,7 +84,9 @@ typedef struct {
                                  is discarded; <= 0 turns the test off       */
     int32_t precision;        /* arithmetic of the GPU path: 0 = FP64 (the
                                  default: matches the FP64 reference to
-                                 rounding), 1 = FP32                          */
+                                 rounding), 1 = FP32 (faster, but rounding
+                                 flips some discrete patch decisions, so its
+                                 output is not held to that agreement)       */
     int32_t init;             /* bdis_init                                    */
     float conf_threshold;     /* learned init: confidence gate               */
     int32_t learned_fine_levels; /* learned init: levels run below the net   */
@@ -203,7 +205,12 @@ BDIS_API bdis_status bdis_set_tuning(bdis_t *h, int32_t n, const int32_t *max_wi
  *            that compute leaves U_1 unwritten; asked for it, this call
  *            first runs one densify launch of level 1 on the last stream.
  *   stage 6: per-patch initial shift u0 (float, ny x nx)
- * Pyramid values hold validity in the sign bit (negative or -0 = invalid).
+ *   stage 7: learned init only: the gate's keep mask at the injection level
+ *            (uint8, W_l x H_l, level = learned_fine_levels; 1 = the
+ *            network's proposal was kept, 0 = the plain field was used)
+ * Stages 0-3, 5 and 6 are in the handle's arithmetic type (double with
+ * precision 0, float with precision 1).  Pyramid values hold validity in the
+ * sign bit (negative or -0 = invalid).
  * Errors: BDIS_E_STATE (no single-pair compute yet), BDIS_E_INVALID_ARG. */
 BDIS_API bdis_status bdis_debug_stage(bdis_t *h, int32_t stage, int32_t level, void *dst, size_t bytes);
 

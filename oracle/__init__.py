@@ -114,6 +114,13 @@ def lib():
         L.ref_compute_init.restype = C.c_int
         L.ref_compute_init.argtypes = [C.POINTER(_Params), _PU8, _PU8, C.c_int, C.c_int, C.c_int,
                                        C.c_int, _PD, C.c_int, _PD]
+        L.ref_gate.restype = None
+        L.ref_gate.argtypes = [_PD, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double,
+                               _PD, _PU8]
+        L.ref_compute_learned.restype = C.c_int
+        L.ref_compute_learned.argtypes = [C.POINTER(_Params), _PU8, _PU8, C.c_int, C.c_int,
+                                          C.c_int, _PD, C.c_int, C.c_int, C.c_double, C.c_int,
+                                          _PD, _PD, _PU8]
         L.ref_num_levels.restype = C.c_int
         L.ref_grid_count.restype = C.c_int
         L.ref_grid_pos.restype = C.c_int
@@ -312,3 +319,45 @@ def compute_init(left, right, params: Params, init_level: int, U_init, init_iter
     if rc != 0:
         raise ValueError(f"ref_compute_init failed: {rc}")
     return disp
+
+
+# ---- learned initial field (network output as an input) ---------------------
+
+def gate(net_out, Wi, Hi, scale, thr=0.5):
+    """Proposal read at the injection level (Wi x Hi, `scale` times the
+    network level): returns (U, keep) with U = -scale * bilinear(d) and keep
+    = bilinear(logistic(logit)) >= thr.  net_out: (H4, W4, 2)."""
+    net = np.ascontiguousarray(net_out, np.float64)
+    H4, W4, two = net.shape
+    if two != 2:
+        raise ValueError("net_out must be (H4, W4, 2)")
+    U = np.empty((Hi, Wi))
+    keep = np.empty((Hi, Wi), np.uint8)
+    lib().ref_gate(_d(net), W4, H4, Wi, Hi, int(scale), float(thr), _d(U), _u8(keep))
+    return U, keep
+
+
+def compute_learned(left, right, params: Params, net_out, net_level=4, inj_level=2, thr=0.5,
+                    fine_iters=None):
+    """Learned-init pipeline: plain levels down to inj_level, the gate's
+    proposal merged into that level's field where kept, then the finer levels
+    with fine_iters iterations.  net_out: network output on net_level,
+    (H4, W4, 2).  Returns (disp, merged field at inj_level, keep mask)."""
+    left = np.ascontiguousarray(left, np.uint8)
+    right = np.ascontiguousarray(right, np.uint8)
+    H, W = left.shape
+    net = np.ascontiguousarray(net_out, np.float64)
+    w4, h4 = level_dims(W, H, net_level)
+    if net.shape != (h4, w4, 2):
+        raise ValueError(f"net_out must be ({h4}, {w4}, 2)")
+    wi, hi = level_dims(W, H, inj_level)
+    disp = np.empty((H, W))
+    field = np.empty((hi, wi))
+    keep = np.empty((hi, wi), np.uint8)
+    p = params._c()
+    it = params.iters if fine_iters is None else fine_iters
+    rc = lib().ref_compute_learned(C.byref(p), _u8(left), _u8(right), W, H, W, _d(net), net_level,
+                                   inj_level, float(thr), int(it), _d(disp), _d(field), _u8(keep))
+    if rc != 0:
+        raise ValueError(f"ref_compute_learned failed: {rc}")
+    return disp, field, keep

@@ -476,17 +476,92 @@ void ref_densify(const ref_params *P, int W, int H, int nx, int ny, const double
 /* Whole pair, coarse to fine (Sec. 2.1, Fig. 1).                            */
 /* ------------------------------------------------------------------------ */
 
+/* ------------------------------------------------------------------------ */
+/* Learned initial field (an added serving pattern, not in the paper).       */
+/* A proposal network gives, on a coarse pyramid level, a disparity d (in    */
+/* that level's pixels) and a confidence logit per pixel.  Read at a finer   */
+/* "injection" level that is `scale` times larger, pixel (x, y) takes the    */
+/* network values bilinearly at (x / scale, y / scale) (the sampler of        */
+/* ref_bilinear, coordinates clamped); the confidence is the logistic        */
+/* function of the logit, taken at the four taps before the interpolation.   */
+/* The proposal is the shift u = -scale * d (eq. (1)'s sign: d = -u), kept   */
+/* where the confidence is at least thr.                                     */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    const double *net;   /* H4 x W4 x 2, row-major: (disparity, confidence logit) */
+    int W4, H4;          /* size of the network level                           */
+    int scale;           /* network level -> injection level size ratio (2^k)   */
+    int level;           /* injection level (>= 1)                              */
+    double thr;          /* confidence gate                                     */
+    int fine_iters;      /* LK iterations of the levels below the injection level */
+    double *field_out;   /* optional: merged field at the injection level       */
+    uint8_t *keep_out;   /* optional: 1 where the proposal is kept              */
+} ref_learned;
+
+void ref_gate(const double *net, int W4, int H4, int Wi, int Hi, int scale, double thr,
+              double *U, uint8_t *keep)
+{
+    double *d = (double *)malloc(sizeof(double) * (size_t)W4 * H4);
+    double *c = (double *)malloc(sizeof(double) * (size_t)W4 * H4);
+    if (!d || !c) {
+        free(d);
+        free(c);
+        return;
+    }
+    for (size_t i = 0; i < (size_t)W4 * H4; i++) {
+        d[i] = net[2 * i];
+        c[i] = 1.0 / (1.0 + exp(-net[2 * i + 1]));
+    }
+    for (int y = 0; y < Hi; y++)
+        for (int x = 0; x < Wi; x++) {
+            double X = (double)x / scale, Y = (double)y / scale;
+            size_t i = (size_t)y * Wi + x;
+            U[i] = -(double)scale * ref_bilinear(d, W4, H4, X, Y);
+            keep[i] = (uint8_t)(ref_bilinear(c, W4, H4, X, Y) >= thr);
+        }
+    free(d);
+    free(c);
+}
+
 /* Returns 0 on success, -1 on bad arguments, -2 on allocation failure.
  * disp: W*H doubles, row-major, d = -U_0, NaN where no patch covered the
  * pixel (Sec. 3.2: such pixels are not estimated). */
 static int ref_compute_impl(const ref_params *P, const uint8_t *Limg, const uint8_t *Rimg, int W,
                             int H, int pitch, double *disp, ref_trace *trace, int init_level,
-                            const double *U_init, int init_iters);
+                            const double *U_init, int init_iters, const ref_learned *lrn);
 
 int ref_compute(const ref_params *P, const uint8_t *Limg, const uint8_t *Rimg, int W, int H,
                 int pitch, double *disp, ref_trace *trace)
 {
-    return ref_compute_impl(P, Limg, Rimg, W, H, pitch, disp, trace, -1, NULL, 0);
+    return ref_compute_impl(P, Limg, Rimg, W, H, pitch, disp, trace, -1, NULL, 0, NULL);
+}
+
+/* Learned-init pipeline with the network output as an input.  The plain
+ * method runs from the coarsest level down to the injection level (it is
+ * the fallback); there its dense field is replaced by the proposal wherever
+ * the gate keeps it (ref_gate), and the finer levels start from that merged
+ * field with fine_iters LK iterations.  net: the network output on level
+ * net_level (H4 x W4 x 2, the sizes of that level).  field_out (merged
+ * field, injection-level size) and keep_out may be NULL. */
+int ref_compute_learned(const ref_params *P, const uint8_t *Limg, const uint8_t *Rimg, int W,
+                        int H, int pitch, const double *net, int net_level, int inj_level,
+                        double thr, int fine_iters, double *disp, double *field_out,
+                        uint8_t *keep_out)
+{
+    if (!net || inj_level < 1 || net_level <= inj_level || net_level >= 30 || fine_iters < 0 ||
+        fine_iters > 1000)
+        return -1;
+    ref_learned g;
+    g.net = net;
+    ref_level_dims(W, H, net_level, &g.W4, &g.H4);
+    g.scale = 1 << (net_level - inj_level);
+    g.level = inj_level;
+    g.thr = thr;
+    g.fine_iters = fine_iters;
+    g.field_out = field_out;
+    g.keep_out = keep_out;
+    return ref_compute_impl(P, Limg, Rimg, W, H, pitch, disp, NULL, -1, NULL, 0, &g);
 }
 
 /* The fine levels only, from a given initial field: U_init is the dense
@@ -499,19 +574,19 @@ int ref_compute_init(const ref_params *P, const uint8_t *Limg, const uint8_t *Ri
 {
     if (!U_init || init_level < 1 || init_iters < 0 || init_iters > 1000)
         return -1;
-    return ref_compute_impl(P, Limg, Rimg, W, H, pitch, disp, NULL, init_level, U_init, init_iters);
+    return ref_compute_impl(P, Limg, Rimg, W, H, pitch, disp, NULL, init_level, U_init, init_iters, NULL);
 }
 
 static int ref_compute_impl(const ref_params *P, const uint8_t *Limg, const uint8_t *Rimg, int W,
                             int H, int pitch, double *disp, ref_trace *trace, int init_level,
-                            const double *U_init, int init_iters)
+                            const double *U_init, int init_iters, const ref_learned *lrn)
 {
     if (!P || !Limg || !Rimg || !disp || W < 1 || H < 1 || pitch < W || P->patch < 1 ||
         P->stride < 1 || P->iters < 0 || P->iters > 1000 || P->window < 1 || (P->window % 2) == 0 ||
         P->window > 63 || W < P->patch || H < P->patch)
         return -1;
     int NL = ref_num_levels(W, H, P->patch, P->levels);
-    if (NL < 1 || (init_level >= 0 && init_level >= NL))
+    if (NL < 1 || (init_level >= 0 && init_level >= NL) || (lrn && lrn->level >= NL))
         return -1;
 
     double *pl[REF_MAX_LEVELS], *pr[REF_MAX_LEVELS], *gl[REF_MAX_LEVELS], *U[REF_MAX_LEVELS];
@@ -570,6 +645,8 @@ static int ref_compute_impl(const ref_params *P, const uint8_t *Limg, const uint
         Pl.iters = init_iters;
     for (int l = top; l >= 0; l--) {
         int w = Ws[l], h = Hs[l], p = P->patch;
+        if (lrn && l < lrn->level)
+            Pl.iters = lrn->fine_iters;
         int nx = ref_grid_count(w, p, P->stride), ny = ref_grid_count(h, p, P->stride);
         size_t np = (size_t)nx * ny;
         double *pu = (double *)malloc(np * sizeof(double));
@@ -613,6 +690,24 @@ static int ref_compute_impl(const ref_params *P, const uint8_t *Limg, const uint
                     v = 2.0 * ref_bilinear(U[l + 1], Ws[l + 1], Hs[l + 1], 0.5 * x, 0.5 * y);
                 U[l][i] = v;
             }
+        if (lrn && l == lrn->level) {
+            /* the proposal replaces the plain field where the gate keeps it */
+            double *Ug = (double *)malloc((size_t)w * h * sizeof(double));
+            uint8_t *keep = (uint8_t *)malloc((size_t)w * h);
+            if (!Ug || !keep) {
+                free(Ug); free(keep); free(pu); free(pp); free(ps);
+                rc = -2;
+                goto done;
+            }
+            ref_gate(lrn->net, lrn->W4, lrn->H4, w, h, lrn->scale, lrn->thr, Ug, keep);
+            for (size_t i = 0; i < (size_t)w * h; i++)
+                if (keep[i])
+                    U[l][i] = Ug[i];
+            if (lrn->field_out) memcpy(lrn->field_out, U[l], (size_t)w * h * sizeof(double));
+            if (lrn->keep_out) memcpy(lrn->keep_out, keep, (size_t)w * h);
+            free(Ug);
+            free(keep);
+        }
         if (trace) {
             if (trace->u_final[l]) memcpy(trace->u_final[l], pu, np * sizeof(double));
             if (trace->post[l]) memcpy(trace->post[l], pp, np * sizeof(double));

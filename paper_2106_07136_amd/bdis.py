@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbdis.so")
 
 OK, E_INVALID_ARG, E_NO_DEVICE, E_OOM, E_HIP, E_UNSUPPORTED, E_STATE = 0, -1, -2, -3, -4, -5, -6
-STAGE_PYR_L, STAGE_PYR_R, STAGE_U, STAGE_W, STAGE_STATUS, STAGE_FIELD, STAGE_U0 = range(7)
+STAGE_PYR_L, STAGE_PYR_R, STAGE_U, STAGE_W, STAGE_STATUS, STAGE_FIELD, STAGE_U0, STAGE_KEEP = range(8)
 
 
 class BdisError(RuntimeError):
@@ -270,11 +270,16 @@ class Bdis:
         """Host numpy copy of one stage tap of the last single-pair compute."""
         import numpy as np
         info = plan(self.params, *self._last_shape)
-        if stage in (STAGE_PYR_L, STAGE_PYR_R, STAGE_FIELD):
+        if stage in (STAGE_PYR_L, STAGE_PYR_R, STAGE_FIELD, STAGE_KEEP):
             shape = (info["height"][level], info["width"][level])
         else:
             shape = (info["ny"][level], info["nx"][level])
-        dt = np.int8 if stage == STAGE_STATUS else (np.float64 if self.params.precision == 0 else np.float32)
+        if stage == STAGE_STATUS:
+            dt = np.int8
+        elif stage == STAGE_KEEP:
+            dt = np.uint8
+        else:
+            dt = np.float64 if self.params.precision == 0 else np.float32
         a = np.empty(shape, dt)
         _check(lib().bdis_debug_stage(self._h, stage, level, a.ctypes.data, a.nbytes), self._h)
         return a

@@ -83,7 +83,6 @@ struct LkJob {
                            // densifies level + 1 itself (rec_u1 set) -- written
     void *rec_u, *rec_w, *rec_u0;  // per-patch records, arithmetic type
     int8_t *rec_st;        // per-patch outcome
-    const int *run_flag;   // non-null: the job runs only if *run_flag != 0
     // Densification of level + 1 folded into this launch (Bayesian fusion):
     // its patch records, spatial weights and fallback field (level + 2, null
     // when level + 1 is the coarsest); rec_u1 null: Uc is read as it is
@@ -96,7 +95,7 @@ struct LkJob {
                            // patch (the level's largest expected disparity)
     int block0;
 };
-static_assert(sizeof(LkJob) == 12 * 8 + 10 * 4, "LkJob must have no padding");
+static_assert(sizeof(LkJob) == 11 * 8 + 10 * 4, "LkJob must have no padding");
 
 struct DenseJob {
     const void *L, *R;     // images (DIS fusion only)
@@ -105,7 +104,6 @@ struct DenseJob {
     const void *Uc;        // fallback source (0 < l < L-1)
     void *U;               // level field out (pitch W), or null
     float *out;            // level 0: disparity out (= -U), or null
-    const int *run_flag;   // non-null: the job runs only if *run_flag != 0
     const uint8_t *keep;   // non-null: pixels with keep[i] != 0 are left as they are
     int pitch;
     int W, H, patch, stride, nx, ny;
@@ -116,7 +114,7 @@ struct DenseJob {
     int block0;
     int strip;             // > 1: one strip of this many pixels of a row per thread (ppt unused)
 };
-static_assert(sizeof(DenseJob) == 10 * 8 + 14 * 4, "DenseJob must have no padding");
+static_assert(sizeof(DenseJob) == 9 * 8 + 14 * 4, "DenseJob must have no padding");
 
 // Input of the proposal network for one pair at its level (NHWC bfloat16,
 // 16 channels).
@@ -135,14 +133,13 @@ struct GateJob {
     const float *net;      // network output (H4 x W4 x 2: disparity, confidence logit)
     void *U;               // field at the injection level (arithmetic type), Wi x Hi
     uint8_t *keep;         // 1 where the learned value is kept (confident)
-    int *flag;             // set to 1 when some network pixel is not confident
     int W4, H4, Wi, Hi;
     int block0;
     float thr;             // confidence threshold
     float sxy;             // injection-level pixel -> network-level coordinate
     float sd;              // network disparity -> shift u at the injection level
 };
-static_assert(sizeof(GateJob) == 4 * 8 + 8 * 4, "GateJob must have no padding");
+static_assert(sizeof(GateJob) == 3 * 8 + 8 * 4, "GateJob must have no padding");
 
 // ---------------------------------------------------------------- helpers
 
@@ -847,7 +844,6 @@ template <typename T, int P, bool U8, int WN = 9, bool FOLD = false, bool MERGE 
 __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KParams &kp, T *__restrict__ Rs) {
     using S = LkShape<P>;
     constexpr int SEG = S::SEG, PPB = S::PPB, NCMAX = S::NCMAX, NCROW = S::NCROW, PADC = S::PADC;
-    if (J.run_flag && *J.run_flag == 0) return;  // uniform over the block
 
     const int W = J.W;
     const int bpr = lk_blocks_per_row<P>(J.nx);
@@ -1319,7 +1315,6 @@ __global__ __launch_bounds__(kBlock, OCC) void k_lk(const JobPack<LkJob> pk, KPa
 // One pixel of a densification job (see dense_value).
 template <typename T, bool U8>
 __device__ __forceinline__ void dense_pixel(const DenseJob &J, const int i, const KParams &kp) {
-    if (J.run_flag && *J.run_flag == 0) return;
     if (J.keep && J.keep[i]) return;
     const int y = div_exact(i, 1.0 / (double)J.W), x = i - y * J.W;
     const T U = dense_value<T, U8>(J, x, y, kp);
@@ -1337,7 +1332,6 @@ __device__ __forceinline__ void dense_pixel(const DenseJob &J, const int i, cons
 template <typename T, bool U8>
 __device__ __forceinline__ void dense_strip(const DenseJob &J, const int xs, const int y, const KParams &kp) {
 #pragma clang fp contract(off)
-    if (J.run_flag && *J.run_flag == 0) return;
     const int P = J.patch, st = J.stride, xe = min(xs + J.strip, J.W);
     auto put = [&](int x, T U) {
         if (J.out) J.out[(size_t)y * J.out_pitch + x] = (float)(-U);
@@ -1497,47 +1491,40 @@ __global__ __launch_bounds__(kBlock) void k_net_input(const JobPack<NetInJob> pk
     }
 }
 
-// Bilinear read of channel ch of an interleaved 2-channel map, coordinates
-// clamped; SIG applies the logistic function to the four taps first.
-template <bool SIG>
-__device__ inline float bilinear2(const float *F, int W, int H, int ch, float X, float Y) {
-    X = fminf(fmaxf(X, 0.f), (float)(W - 1));
-    Y = fminf(fmaxf(Y, 0.f), (float)(H - 1));
-    int mx = min(max((int)floorf(X), 0), max(W - 2, 0));
-    int my = min(max((int)floorf(Y), 0), max(H - 2, 0));
-    float fx = W > 1 ? X - (float)mx : 0.f, fy = H > 1 ? Y - (float)my : 0.f;
+// Bilinear read of channel ch of an interleaved 2-channel FP32 map, in the
+// arithmetic type, coordinates clamped; SIG applies the logistic function to
+// the four taps first.
+template <typename T, bool SIG>
+__device__ inline T bilinear2(const float *F, int W, int H, int ch, T X, T Y) {
+    X = fmin(fmax(X, T(0)), (T)(W - 1));
+    Y = fmin(fmax(Y, T(0)), (T)(H - 1));
+    int mx = min(max((int)floor(X), 0), max(W - 2, 0));
+    int my = min(max((int)floor(Y), 0), max(H - 2, 0));
+    T fx = W > 1 ? X - (T)mx : T(0), fy = H > 1 ? Y - (T)my : T(0);
     int mx1 = W > 1 ? mx + 1 : mx, my1 = H > 1 ? my + 1 : my;
     auto at = [&](int yy, int xx) {
-        float v = F[((size_t)yy * W + xx) * 2 + ch];
-        return SIG ? 1.f / (1.f + expf(-v)) : v;
+        T v = (T)F[((size_t)yy * W + xx) * 2 + ch];
+        return SIG ? T(1) / (T(1) + exp(-v)) : v;
     };
-    float a = (1.f - fx) * at(my, mx) + fx * at(my, mx1);
-    float b = (1.f - fx) * at(my1, mx) + fx * at(my1, mx1);
-    return (1.f - fy) * a + fy * b;
+    T a = (T(1) - fx) * at(my, mx) + fx * at(my, mx1);
+    T b = (T(1) - fx) * at(my1, mx) + fx * at(my1, mx1);
+    return (T(1) - fy) * a + fy * b;
 }
 
 // Learned field at the injection level: u = sd * disparity(x * sxy) and
-// keep = confidence(x * sxy) >= thr.  Block 0 of each pair also sets the
-// pair's fallback flag: 1 when any network pixel is below the threshold.
+// keep = confidence(x * sxy) >= thr, in the arithmetic type (sxy and sd are
+// powers of two, exact in either).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_gate(const JobPack<GateJob> pk) {
     const GateJob &J = pk.j[find_job(pk, (int)blockIdx.x)];
-    const int lb = (int)blockIdx.x - J.block0;
-    if (lb == 0) {
-        int low = 0;
-        for (int q = (int)threadIdx.x; q < J.W4 * J.H4; q += kBlock)
-            low |= (1.f / (1.f + expf(-J.net[(size_t)q * 2 + 1]))) < J.thr;
-        low = __syncthreads_or(low);
-        if (threadIdx.x == 0) *J.flag = low ? 1 : 0;
-    }
-    const int i = lb * kBlock + (int)threadIdx.x;
+    const int i = ((int)blockIdx.x - J.block0) * kBlock + (int)threadIdx.x;
     if (i >= J.Wi * J.Hi) return;
     const int y = i / J.Wi, x = i - y * J.Wi;
-    const float X = (float)x * J.sxy, Y = (float)y * J.sxy;
-    const float d = bilinear2<false>(J.net, J.W4, J.H4, 0, X, Y);
-    const float c = bilinear2<true>(J.net, J.W4, J.H4, 1, X, Y);
-    static_cast<T *>(J.U)[i] = (T)(J.sd * d);
-    J.keep[i] = c >= J.thr ? 1 : 0;
+    const T X = (T)x * (T)J.sxy, Y = (T)y * (T)J.sxy;
+    const T d = bilinear2<T, false>(J.net, J.W4, J.H4, 0, X, Y);
+    const T c = bilinear2<T, true>(J.net, J.W4, J.H4, 1, X, Y);
+    static_cast<T *>(J.U)[i] = (T)J.sd * d;
+    J.keep[i] = c >= (T)J.thr ? 1 : 0;
 }
 
 }  // namespace bdis

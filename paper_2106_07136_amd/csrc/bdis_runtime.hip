@@ -142,13 +142,12 @@ size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
 // Workspace of one pair, elements of the arithmetic type (esz bytes):
 // pyramid levels >= 1 (2 images), fields U_l for LK levels l >= 1, per-level
 // patch records (u, w, u0 + a status byte), and for the learned init the
-// keep mask at the injection level and the fallback flag.
+// keep mask at the injection level.
 struct PairWs {
     void *pyr_l[kMaxLevels], *pyr_r[kMaxLevels], *U[kMaxLevels];
     void *rec_u[kMaxLevels], *rec_w[kMaxLevels], *rec_u0[kMaxLevels];
     int8_t *rec_st[kMaxLevels];
     uint8_t *keep;
-    int *flag;
 };
 
 // inj: injection level of the learned init (0 = no learned buffers)
@@ -160,7 +159,7 @@ size_t pair_ws_bytes(const Geo &g, size_t esz, int inj = 0) {
         if (l >= 1 && l < g.L) b += align_up(px * esz);
         if (l < g.L) b += 3 * align_up(np * esz) + align_up(np);
     }
-    if (inj > 0) b += align_up((size_t)g.W[inj] * g.H[inj]) + align_up(sizeof(int));
+    if (inj > 0) b += align_up((size_t)g.W[inj] * g.H[inj]);
     return b;
 }
 
@@ -182,10 +181,7 @@ void carve(char *base, const Geo &g, size_t esz, PairWs &w, int inj = 0) {
             w.rec_st[l] = (int8_t *)take(np);
         }
     }
-    if (inj > 0) {
-        w.keep = (uint8_t *)take((size_t)g.W[inj] * g.H[inj]);
-        w.flag = (int *)take(sizeof(int));
-    }
+    if (inj > 0) w.keep = (uint8_t *)take((size_t)g.W[inj] * g.H[inj]);
 }
 
 // Same-size pairs whose network input, hidden activations and output share
@@ -434,18 +430,8 @@ void plan_pyramid(std::vector<Launch> &ls, const std::vector<PairIn> &pairs, int
     }
 }
 
-// Build every launch for a set of pairs: pyramid levels 1..Lmax-1, then for
-// each level from the coarsest down, LK (per patch size) and the
-// densification.
 bool learned(const bdis_t *h) { return h->prm.init == BDIS_INIT_LEARNED; }
 
-// Build every launch for a set of pairs: pyramid levels 1..Lp-1, then for
-// each level from the coarsest down, LK (per patch size) and the
-// densification.  With the learned init, the network input, forward and
-// gate come after the pyramid; the levels at and above the injection level
-// run only for pairs the gate flagged (plain fallback where the network is
-// not confident), the injection level's densification leaves the confident
-// pixels alone, and the finer levels use learned_iters.
 // Densification of level l of pair p (the field U_l, or the output at
 // level 0); keep: the learned injection level, which fills only the pixels
 // the gate left.
@@ -469,7 +455,6 @@ DenseJob make_dense_job(const bdis_t *h, const PairIn &p, int l, bool keep) {
     j.U = l == 0 ? nullptr : p.ws.U[l];
     j.out = l == 0 ? p.disp : nullptr;
     j.out_pitch = p.dpitch;
-    j.run_flag = nullptr;
     j.keep = keep ? p.ws.keep : nullptr;
     j.ppt = 1;
     // a strip of pixels per thread shares the candidate patches' records
@@ -478,6 +463,13 @@ DenseJob make_dense_job(const bdis_t *h, const PairIn &p, int l, bool keep) {
     return j;
 }
 
+// Build every launch for a set of pairs: pyramid levels 1..Lp-1, then for
+// each level from the coarsest down, LK (per patch size) and the
+// densification.  With the learned init, the network input, forward and
+// gate run on the side stream beside the plain levels down to the injection
+// level (the fallback, which needs nothing from them); the injection level's
+// densification fills only the pixels the gate did not keep, and the finer
+// levels use learned_iters.
 void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<Launch> &ls) {
     int Lmax = 0, Lpmax = 0;
     const bool f64 = h->prm.precision == 0;
@@ -504,7 +496,6 @@ void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<Launch> &l
             q.net = G.out + (size_t)p.gindex * G.W4 * G.H4 * 2;
             q.U = p.ws.U[inj];
             q.keep = p.ws.keep;
-            q.flag = p.ws.flag;
             q.W4 = G.W4; q.H4 = G.H4;
             q.Wi = p.g.W[inj]; q.Hi = p.g.H[inj];
             q.thr = h->prm.conf_threshold;
@@ -550,9 +541,9 @@ void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<Launch> &l
     bool joined = false;
     for (int l = Lmax - 1; l >= 0; l--) {
         // With the learned init the plain levels down to the injection level
-        // are the fallback.  They run whether or not the gate will need them
-        // (so that they overlap the network), except that at the injection
-        // level the densification fills only the pixels the gate left.
+        // are the fallback.  They run whatever the gate decides (so that they
+        // overlap the network); at the injection level the densification
+        // fills only the pixels the gate left.
         KParams kpl = kp0;
         if (lrn && l < inj) kpl.iters = h->prm.learned_iters;
         for (int P : kSupportedPatch) {
@@ -572,7 +563,6 @@ void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<Launch> &l
                 j.reach = (int)std::ceil(std::max(0.f, p.dmax) / (float)(1 << l)) + 1;
                 j.rec_u = p.ws.rec_u[l]; j.rec_w = p.ws.rec_w[l];
                 j.rec_u0 = p.ws.rec_u0[l]; j.rec_st = p.ws.rec_st[l];
-                j.run_flag = nullptr;
                 if (folded(p, l)) {
                     j.rec_u1 = p.ws.rec_u[l + 1]; j.rec_w1 = p.ws.rec_w[l + 1];
                     j.gtab1 = f64 ? (const void *)(h->gtab_d + gtab_offset(p.patch))
@@ -1085,22 +1075,23 @@ bdis_status run(bdis_t *h, std::vector<PairIn> &pairs, hipStream_t s, int mode =
     }
     bdis_status st = ensure_ws(h, total + net_bytes);
     if (st != BDIS_OK) return st;
+    char *base = h->ws;
     size_t off = 0;
     for (auto &p : pairs) {
-        carve(h->ws + off, p.g, esz, p.ws, inj);
+        carve(base + off, p.g, esz, p.ws, inj);
         off += align_up(pair_ws_bytes(p.g, esz, inj));
     }
     if (lrn) {
         const int C = bdisnet::channels(h->net);
         for (NetGroup &G : h->groups) {
             size_t px = (size_t)G.pairs.size() * G.W4 * G.H4;
-            G.x = (uint16_t *)(h->ws + off);
+            G.x = (uint16_t *)(base + off);
             off += align_up(px * kNetIn * 2);
             for (int a = 0; a < 3; a++) {
-                G.a[a] = (uint16_t *)(h->ws + off);
+                G.a[a] = (uint16_t *)(base + off);
                 off += align_up(px * C * 2);
             }
-            G.out = (float *)(h->ws + off);
+            G.out = (float *)(base + off);
             off += align_up(px * 2 * 4);
         }
     }
@@ -1410,6 +1401,10 @@ bdis_status bdis_debug_stage(bdis_t *h, int32_t stage, int32_t level, void *dst,
     case 4: src = p.ws.rec_st[level]; need = np; break;
     case 5: src = p.ws.U[level]; need = px; break;
     case 6: src = p.ws.rec_u0[level]; need = np * esz; break;
+    case 7:
+        if (level == h->prm.learned_fine_levels) src = p.ws.keep;
+        need = (size_t)p.g.W[level] * p.g.H[level];
+        break;
     default: set_err(h->err, "unknown stage %d", stage); return BDIS_E_INVALID_ARG;
     }
     if (!src) { set_err(h->err, "stage %d has no level %d", stage, level); return BDIS_E_INVALID_ARG; }

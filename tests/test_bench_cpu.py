@@ -52,3 +52,16 @@ def test_net_flops_per_layer():
 
 def test_lds_peak_from_unit_counts():
     assert bench.PEAK_LDS == 128 * 256 * 2.4e9
+
+
+def test_cpu_leg_threads_follow_affinity_and_budget(monkeypatch):
+    """The CPU leg uses every core the process may run on, capped by the
+    job's thread budget when OMP_NUM_THREADS is set."""
+    usable = len(os.sched_getaffinity(0))
+    monkeypatch.delenv("OMP_NUM_THREADS", raising=False)
+    assert bench.host_threads() == usable
+    monkeypatch.setenv("OMP_NUM_THREADS", "1")
+    assert bench.host_threads() == 1
+    monkeypatch.setenv("OMP_NUM_THREADS", str(usable + 100))
+    assert bench.host_threads() == usable
+    assert bench._cpu_model()

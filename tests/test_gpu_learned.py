@@ -21,32 +21,58 @@ def torch_cuda():
     return torch
 
 
-def _const_net(C, d, logit):
+def _const_layers(C, d, logit):
     from paper_2106_07136_amd import net
     layers = [(np.zeros((3, 3, ci, co)), np.zeros(co)) for ci, co in net.layer_dims(C)]
     layers[3] = (layers[3][0], np.array([d, logit]))
-    pn = net.ProposalNet(C)
-    pn.set_params(net.flatten(layers))
-    return pn
+    return layers
 
 
-def _varying_net(C, d, gain, offset):
-    """logit = gain * relu((L - 128) / 64) + offset, disparity d."""
+def _varying_layers(C, d0, d_gain, c_gain, c_offset):
+    """Disparity d0 + d_gain * relu((L - 128) / 64) and confidence logit
+    c_gain * relu((R - 128) / 64) + c_offset at the 1/16 level: both vary in
+    space, each with its own image.  Every weight is exact in bfloat16."""
     from paper_2106_07136_amd import net
     layers = [(np.zeros((3, 3, ci, co)), np.zeros(co)) for ci, co in net.layer_dims(C)]
-    w0 = layers[0][0].copy()
-    w0[1, 1, 0, 0] = 1.0
-    layers[0] = (w0, layers[0][1])
-    for li in (1, 2):
+    for li in range(3):
         w = layers[li][0].copy()
         w[1, 1, 0, 0] = 1.0
+        w[1, 1, 1, 1] = 1.0
         layers[li] = (w, layers[li][1])
     w3 = layers[3][0].copy()
-    w3[1, 1, 0, 1] = gain
-    layers[3] = (w3, np.array([d, offset]))
+    w3[1, 1, 0, 0] = d_gain
+    w3[1, 1, 1, 1] = c_gain
+    layers[3] = (w3, np.array([d0, c_offset]))
+    return layers
+
+
+def _net(layers, C=32):
+    from paper_2106_07136_amd import net
     pn = net.ProposalNet(C)
     pn.set_params(net.flatten(layers))
     return pn
+
+
+def _const_net(C, d, logit):
+    return _net(_const_layers(C, d, logit), C)
+
+
+def _oracle_net_out(ref, pair, layers):
+    """The network output at the 1/16 level, all in the oracle: its pyramid,
+    the input channels rounded to bfloat16, the FP64 network on bfloat16
+    weights with bfloat16 hidden activations."""
+    _, tr = ref.compute(pair.left, pair.right, ref.Params(levels=5), trace=True)
+    x = onet.bf16(onet.net_input(tr[4]["pyr_l"], tr[4]["pyr_r"]))[None]
+    out, _ = onet.Net([(onet.bf16(w), b) for w, b in layers]).forward(x)
+    return out[0]
+
+
+def _gate_ambiguous(ref, net_out, wi, hi, thr=0.5, band=1e-6):
+    """Pixels whose oracle confidence lies within `band` of the threshold:
+    the FP32 network output may decide them either way."""
+    _, lo = ref.gate(net_out, wi, hi, 4, thr - band)
+    _, hi_ = ref.gate(net_out, wi, hi, 4, thr + band)
+    return lo != hi_
 
 
 def _gpu(torch, pair):
@@ -84,43 +110,62 @@ def test_all_fallback_equals_plain(torch_cuda):
 
 @pytest.mark.parametrize("iters", [12, 4])
 def test_confident_proposal_matches_oracle(torch_cuda, ref, iters):
+    """A confident constant proposal: the gate keeps every pixel and the
+    fine levels run from -4 * 1.5 (the bias is exact in bfloat16 and FP32)."""
     from paper_2106_07136_amd import bdis
     pair = synth.make_pair(640, 480, 64.0, 32)
     L, R = _gpu(torch_cuda, pair)
-    net = _const_net(32, 1.5, 10.0)
+    layers = _const_layers(32, 1.5, 10.0)
     gp = bdis.Params(levels=5, init=1, learned_iters=iters)
     h = bdis.Bdis(gp)
-    h.set_net(net)
+    h.set_net(_net(layers))
     got = h.compute(L, R).cpu().numpy()
     U2 = h.debug_stage(bdis.STAGE_FIELD, 2)
-    # gate: u = -4 * 1.5 everywhere (the bias is exact in bfloat16 and FP32)
+    keep = h.debug_stage(bdis.STAGE_KEEP, 2)
+    exp, field, kref = ref.compute_learned(pair.left, pair.right, oracle_params(ref, gp),
+                                           _oracle_net_out(ref, pair, layers), 4, 2, 0.5, iters)
+    assert kref.all() and keep.all()
+    np.testing.assert_array_equal(U2, field)
     np.testing.assert_array_equal(U2, np.full_like(U2, -6.0))
-    exp = ref.compute_init(pair.left, pair.right, oracle_params(ref, gp), 2, U2, iters)
     assert_parity(got, exp, f"learned confident iters={iters}")
 
 
-def test_partial_fallback_matches_oracle(torch_cuda, ref):
-    """Confidence follows the left image: where it is low the plain coarse
-    levels' field is used, elsewhere the learned one."""
+@pytest.mark.parametrize("seed", [33, 37])
+def test_gate_and_merge_match_oracle(torch_cuda, ref, seed):
+    """A network whose disparity and confidence both vary in space (each
+    follows one image): k_gate's keep mask and the merged injection-level
+    field against the oracle's gate and merge, element by element, then the
+    output at the parity tolerance.  The oracle runs its own pyramid, network
+    input and FP64 network; only pixels whose confidence is within 1e-6 of
+    the threshold may be decided either way (FP32 network output)."""
     from paper_2106_07136_amd import bdis
-    torch = torch_cuda
-    pair = synth.make_pair(640, 480, 64.0, 33)
-    L, R = _gpu(torch, pair)
-    net = _varying_net(32, 2.0, 2000.0, -3.0)
-    gp = bdis.Params(levels=5, init=1, learned_iters=12)
+    pair = synth.make_pair(640, 480, 64.0, seed)
+    L, R = _gpu(torch_cuda, pair)
+    layers = _varying_layers(32, 2.0, 16.0, 100.0, -4.0)
+    gp = bdis.Params(levels=5, init=1, learned_iters=8)
     h = bdis.Bdis(gp)
-    h.set_net(net)
+    h.set_net(_net(layers))
     got = h.compute(L, R).cpu().numpy()
     U2 = h.debug_stage(bdis.STAGE_FIELD, 2)
-    _, tr = ref.compute(pair.left, pair.right, oracle_params(ref, bdis.Params(levels=5)), trace=True)
-    plain2 = tr[2]["field"]
-    learned = np.abs(U2 - (-8.0)) == 0
-    from_plain = np.abs(U2 - plain2) <= 1e-6
-    assert np.all(learned | from_plain)
-    frac = learned.mean()
-    assert 0.05 < frac < 0.95, frac
-    exp = ref.compute_init(pair.left, pair.right, oracle_params(ref, gp), 2, U2, 12)
-    assert_parity(got, exp, "learned partial fallback")
+    keep = h.debug_stage(bdis.STAGE_KEEP, 2)
+    net_out = _oracle_net_out(ref, pair, layers)
+    assert np.ptp(net_out[..., 0]) > 0.5 and np.ptp(net_out[..., 1]) > 5.0
+    exp, field, kref = ref.compute_learned(pair.left, pair.right, oracle_params(ref, gp), net_out,
+                                           4, 2, 0.5, 8)
+    amb = _gate_ambiguous(ref, net_out, U2.shape[1], U2.shape[0])
+    sure = ~amb
+    print(f"seed {seed}: kept {kref.mean():.3f}, ambiguous {amb.mean():.2e}", flush=True)
+    assert 0.05 < kref.mean() < 0.95
+    assert amb.mean() < 1e-3
+    np.testing.assert_array_equal(keep[sure], kref[sure])
+    both_kept = sure & (kref == 1)
+    both_plain = sure & (kref == 0)
+    # the proposal: FP32 network output against FP64, times 4
+    np.testing.assert_allclose(U2[both_kept], field[both_kept], rtol=1e-6, atol=1e-5)
+    # the plain field: the FP64 coarse levels against the oracle's
+    err = np.abs(U2[both_plain] - field[both_plain])
+    assert np.sqrt(np.mean(err ** 2)) <= 1e-3 and (err <= 1e-2).mean() >= 0.999
+    assert_parity(got, exp, f"learned gate + merge seed {seed}")
 
 
 @pytest.mark.parametrize("mode", [0, 1])
@@ -129,7 +174,7 @@ def test_learned_batch_equals_single(torch_cuda, mode):
     torch = torch_cuda
     spec = [(640, 480, 64.0, 41), (320, 240, 32.0, 42), (640, 480, 64.0, 43)]
     pairs = [synth.make_pair(*s) for s in spec]
-    net = _varying_net(32, 1.0, 2000.0, -3.0)
+    net = _net(_varying_layers(32, 1.0, 0.5, 100.0, -4.0))
     gp = bdis.Params(levels=0, init=1, learned_iters=8)
     singles = []
     import dataclasses

@@ -40,6 +40,16 @@ MUTATIONS = {
     "uncovered_zero": ("v = NAN; /* Sec. 3.2", "v = 0.0; /* Sec. 3.2"),
     "convergence_test_off": ("(P->conv_tol > 0 && P->iters > 0 &&", "(0 && P->iters > 0 &&"),
     "divergence_bound_off": ("fabs(o->u - u0) > (double)p ||", "0 ||"),
+    # learned initial field (gate and merge)
+    "gate_disparity_sign": ("U[i] = -(double)scale * ref_bilinear(", "U[i] = (double)scale * ref_bilinear("),
+    "gate_no_logistic": ("c[i] = 1.0 / (1.0 + exp(-net[2 * i + 1]));", "c[i] = net[2 * i + 1];"),
+    "gate_transposed": ("ref_bilinear(d, W4, H4, X, Y)", "ref_bilinear(d, W4, H4, Y, X)"),
+    "gate_strict_threshold": ("ref_bilinear(c, W4, H4, X, Y) >= thr", "ref_bilinear(c, W4, H4, X, Y) > thr"),
+    "gate_coordinate_scale": ("double X = (double)x / scale, Y = (double)y / scale;",
+                              "double X = (double)x / (2 * scale), Y = (double)y / (2 * scale);"),
+    "merge_inverted": ("if (keep[i])\n                    U[l][i] = Ug[i];",
+                       "if (!keep[i])\n                    U[l][i] = Ug[i];"),
+    "fine_iters_ignored": ("Pl.iters = lrn->fine_iters;", "Pl.iters = P->iters;"),
 }
 
 

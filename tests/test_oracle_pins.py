@@ -508,3 +508,130 @@ def test_compute_init_with_own_field_is_compute(ref):
     w2, h2 = ref.level_dims(160, 120, 2)
     d3 = ref.compute_init(S.left, S.right, prm, 2, np.full((h2, w2), -6 / 4.0), 8)
     assert np.nanmax(np.abs(d3[8:-8, 14:-8] - 6)) < 1e-3
+
+
+# ---------------------------------------------------------------- learned gate
+
+def _logistic(z):
+    return 1.0 / (1.0 + math.exp(-z))
+
+
+def test_gate_constant_proposal(ref):
+    """A constant network output: the proposal is the disparity scaled to the
+    injection level with eq. (1)'s sign (u = -scale d), and the gate keeps
+    every pixel or none, by the logistic confidence against the threshold
+    (a confidence equal to the threshold is kept)."""
+    net = np.zeros((6, 9, 2))
+    net[..., 0], net[..., 1] = 1.25, 0.7
+    for scale in (2, 4):
+        U, keep = ref.gate(net, 9 * scale - 2, 6 * scale - 1, scale, thr=0.5)
+        assert U.shape == (6 * scale - 1, 9 * scale - 2)
+        assert np.all(U == -scale * 1.25) and np.all(keep == 1)
+    assert _logistic(0.7) < 0.7
+    _, keep = ref.gate(net, 18, 12, 2, thr=0.7)
+    assert np.all(keep == 0)
+    net[..., 1] = 0.0  # logistic(0) = 0.5 exactly
+    _, keep = ref.gate(net, 18, 12, 2, thr=0.5)
+    assert np.all(keep == 1)
+
+
+@pytest.mark.parametrize("scale", [2, 4])
+def test_gate_reproduces_affine_disparity(ref, scale):
+    """Bilinear reading is exact on an affine field: pixel (x, y) of the
+    injection level sees the network's d at (x / scale, y / scale), clamped to
+    the network level (different x and y slopes catch a transposition)."""
+    H4, W4 = 7, 10
+    Y4, X4 = np.mgrid[0:H4, 0:W4].astype(float)
+    net = np.zeros((H4, W4, 2))
+    net[..., 0] = 0.5 + 0.25 * X4 - 0.125 * Y4
+    net[..., 1] = 5.0
+    Wi, Hi = W4 * scale, H4 * scale
+    U, keep = ref.gate(net, Wi, Hi, scale)
+    y, x = np.mgrid[0:Hi, 0:Wi].astype(float)
+    X, Y = np.minimum(x / scale, W4 - 1), np.minimum(y / scale, H4 - 1)
+    np.testing.assert_allclose(U, -scale * (0.5 + 0.25 * X - 0.125 * Y), rtol=0, atol=1e-12)
+    assert np.all(keep == 1)
+
+
+def test_gate_interpolates_confidence_not_logit(ref):
+    """Confidence +2 / -20 logits on two sides of a column step (scale 4):
+    the logistic is taken at the taps and then interpolated, so the pixel a
+    quarter of the way across is kept (0.75 * 0.88 = 0.66) and the one half
+    way is not (0.44); interpolating the logit would drop both.  Hand count:
+    kept iff x / 4 <= 2.25, i.e. x <= 9, in every row."""
+    net = np.zeros((5, 8, 2))
+    net[:, :3, 1] = 2.0
+    net[:, 3:, 1] = -20.0
+    assert 0.75 * _logistic(2.0) + 0.25 * _logistic(-20.0) >= 0.5
+    assert 0.5 * _logistic(2.0) + 0.5 * _logistic(-20.0) < 0.5
+    _, keep = ref.gate(net, 32, 20, 4)
+    exp = np.zeros((20, 32), np.uint8)
+    exp[:, :10] = 1
+    np.testing.assert_array_equal(keep, exp)
+    # the same step along y keeps rows y <= 9 only
+    net_t = np.zeros((8, 5, 2))
+    net_t[:3, :, 1], net_t[3:, :, 1] = 2.0, -20.0
+    _, keep_t = ref.gate(net_t, 20, 32, 4)
+    np.testing.assert_array_equal(keep_t, exp.T)
+
+
+def _learned_case(ref):
+    P = synth.make_pair(160, 120, 16, seed=6)
+    prm = ref.Params(levels=5, iters=8)
+    w4, h4 = ref.level_dims(160, 120, 4)
+    return P, prm, w4, h4
+
+
+def test_learned_all_fallback_is_plain(ref):
+    """Nothing kept: the injection level holds the plain field, so with the
+    plain iteration count the result is the plain method's exactly, and with
+    fewer fine iterations it is the plain field continued with them."""
+    P, prm, w4, h4 = _learned_case(ref)
+    net = np.zeros((h4, w4, 2))
+    net[..., 0], net[..., 1] = 3.0, -30.0
+    d, tr = ref.compute(P.left, P.right, prm, trace=True)
+    dl, field, keep = ref.compute_learned(P.left, P.right, prm, net, 4, 2, 0.5, fine_iters=8)
+    assert not keep.any()
+    np.testing.assert_array_equal(field, tr[2]["field"])
+    np.testing.assert_array_equal(np.isnan(dl), np.isnan(d))
+    np.testing.assert_array_equal(dl[np.isfinite(dl)], d[np.isfinite(d)])
+    d4, _, _ = ref.compute_learned(P.left, P.right, prm, net, 4, 2, 0.5, fine_iters=4)
+    e4 = ref.compute_init(P.left, P.right, prm, 2, tr[2]["field"], 4)
+    np.testing.assert_array_equal(np.isnan(d4), np.isnan(e4))
+    np.testing.assert_array_equal(d4[np.isfinite(d4)], e4[np.isfinite(e4)])
+    assert not np.array_equal(np.nan_to_num(d4), np.nan_to_num(d))
+
+
+def test_learned_merge_takes_proposal_where_kept(ref):
+    """A proposal kept on the left half of the network level only: the merged
+    injection-level field is the gate's value where kept and the plain field
+    elsewhere, and the finer levels run from that merged field."""
+    P, prm, w4, h4 = _learned_case(ref)
+    net = np.zeros((h4, w4, 2))
+    net[..., 0] = 2.0 + 0.1 * np.arange(w4)[None, :]
+    net[:, : w4 // 2, 1] = 8.0
+    net[:, w4 // 2:, 1] = -8.0
+    _, tr = ref.compute(P.left, P.right, prm, trace=True)
+    dl, field, keep = ref.compute_learned(P.left, P.right, prm, net, 4, 2, 0.5, fine_iters=6)
+    w2, h2 = ref.level_dims(160, 120, 2)
+    Ug, kg = ref.gate(net, w2, h2, 4)
+    np.testing.assert_array_equal(keep, kg)
+    assert 0.2 < keep.mean() < 0.8
+    np.testing.assert_array_equal(field, np.where(kg == 1, Ug, tr[2]["field"]))
+    e = ref.compute_init(P.left, P.right, prm, 2, field, 6)
+    np.testing.assert_array_equal(np.isnan(dl), np.isnan(e))
+    np.testing.assert_array_equal(dl[np.isfinite(dl)], e[np.isfinite(e)])
+
+
+def test_learned_confident_shift_needs_no_coarse_levels(ref):
+    """An integer shift of 6 px and a confident constant proposal of 6/16 px
+    at the 1/16 level: every pixel keeps the proposal, and the two fine
+    levels recover the shift."""
+    S = synth.integer_shift_pair(160, 120, 6, seed=3)
+    prm = ref.Params(levels=5, iters=8)
+    w4, h4 = ref.level_dims(160, 120, 4)
+    net = np.zeros((h4, w4, 2))
+    net[..., 0], net[..., 1] = 6.0 / 16, 10.0
+    d, field, keep = ref.compute_learned(S.left, S.right, prm, net, 4, 2, 0.5, fine_iters=8)
+    assert keep.all() and np.all(field == -6.0 / 4)
+    assert np.nanmax(np.abs(d[8:-8, 14:-8] - 6)) < 1e-3
