@@ -146,6 +146,30 @@ BDIS_API bdis_status bdis_compute(bdis_t *h, const uint8_t *left, const uint8_t 
                          int32_t height, int32_t pitch_bytes, float *disp,
                          int32_t disp_pitch_elems, void *stream);
 
+/* bdis_compute for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same kernels and results (bit for bit), but the workspace is a
+ * library-owned array of BDIS_NOALLOC_SCRATCH_BYTES per device, created when
+ * the library is loaded on that device and kept until the process ends.
+ * The call allocates nothing (no hipMalloc, hipFree or allocating library
+ * routine) and does not use or grow the handle's workspace.
+ *   - A request whose workspace exceeds the scratch (bdis_plan's
+ *     workspace_bytes, e.g. 19.9 MiB for 1920x1080 at the defaults) fails
+ *     with BDIS_E_INVALID_ARG before anything is enqueued.
+ *   - Plain path only: params.init = BDIS_INIT_LEARNED gives
+ *     BDIS_E_UNSUPPORTED.
+ *   - Every call on a device, from any handle, shares that device's array:
+ *     calls that overlap in time on one device (different streams, threads
+ *     or handles) race and corrupt each other's results.  Serialise them
+ *     (one stream, or events).  Nothing in the array needs to start at zero.
+ *   - bdis_debug_stage is not available after this call (BDIS_E_STATE).
+ *   - Per-launch profiling records nothing for this call.
+ * Arguments, ownership and the other errors are those of bdis_compute. */
+#define BDIS_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+BDIS_API bdis_status bdis_compute_noalloc(bdis_t *h, const uint8_t *left, const uint8_t *right, int32_t width,
+                                          int32_t height, int32_t pitch_bytes, float *disp,
+                                          int32_t disp_pitch_elems, void *stream);
+
 /* The same for n independent pairs of mixed sizes in one pass: each kernel of
  * the path is launched once for all pairs (level by level, coarsest first).
  * `pairs` is a HOST array of n entries, read during the call only.  Each

@@ -103,6 +103,7 @@ def lib():
         L.bdis_set_params.argtypes = [vp, C.POINTER(CParams)]
         L.bdis_reserve.argtypes = [vp, i32, i32, i32]
         L.bdis_compute.argtypes = [vp, vp, vp, i32, i32, i32, vp, i32, vp]
+        L.bdis_compute_noalloc.argtypes = [vp, vp, vp, i32, i32, i32, vp, i32, vp]
         L.bdis_compute_batch.argtypes = [vp, C.POINTER(CPair), i32, vp]
         L.bdis_set_tuning.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
         L.bdis_debug_stage.argtypes = [vp, i32, i32, vp, C.c_size_t]
@@ -120,6 +121,7 @@ def lib():
         L.bdis_last_error.argtypes = [vp]
         L.bdis_last_error.restype = C.c_char_p
         for name in ("bdis_plan", "bdis_create", "bdis_set_params", "bdis_reserve", "bdis_compute",
+                     "bdis_compute_noalloc",
                      "bdis_compute_batch", "bdis_set_tuning", "bdis_debug_stage",
                      "bdis_set_profiling", "bdis_get_profile", "bdis_set_batch_mode",
                      "bdis_batch_error", "bdis_set_net", "bdis_net_input", "bdis_set_fold_densify"):

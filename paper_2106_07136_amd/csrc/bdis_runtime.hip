@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -19,7 +20,32 @@
 
 using namespace bdis;
 
+// Workspace of bdis_compute_noalloc: one array per device, created when the
+// library's code object is loaded on that device and kept until the process
+// ends.  In host code `scratch` names a host-side stand-in, not device
+// memory: the device address is looked up once per device with
+// hipGetSymbolAddress (resolve_scratch) and only that address is used.
+static __device__ __align__(256) char scratch[BDIS_NOALLOC_SCRATCH_BYTES];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch[kMaxDevices] = {};
+
+// Device address of this device's scratch array; `device` must be current.
+hipError_t resolve_scratch(int device, char **out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    if (!g_scratch[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch[device] = static_cast<char *>(p);
+    }
+    *out = g_scratch[device];
+    return hipSuccess;
+}
 
 constexpr int kMaxLevels = 12;
 constexpr int kSupportedPatch[] = {4, 6, 8, 10, 12, 16};
@@ -266,6 +292,8 @@ struct bdis_ctx {
     int *p_err = nullptr;         // device error flag of the last persistent run
     hipStream_t last_batch_stream = nullptr;
     int n_cu = 0;
+    // this device's copy of the no-allocation scratch array (see below)
+    char *scratch = nullptr;
     // autotuner table
     int ntune = 0;
     int tune_w[kMaxTuning], tune_p[kMaxTuning], tune_s[kMaxTuning];
@@ -1027,7 +1055,10 @@ bdis_status run_level_graph(bdis_t *h, const std::vector<Launch> &ls, hipStream_
 }
 
 // Shared body of bdis_compute and bdis_compute_batch.
-bdis_status run(bdis_t *h, std::vector<PairIn> &pairs, hipStream_t s, int mode = 1) {
+// fixed_ws: a caller-chosen workspace of fixed_bytes (the no-allocation
+// entry point); nullptr = the handle's own, grown on demand.
+bdis_status run(bdis_t *h, std::vector<PairIn> &pairs, hipStream_t s, int mode = 1, char *fixed_ws = nullptr,
+                size_t fixed_bytes = 0) {
     DeviceGuard dg(h->device);
     const size_t esz = esize(h->prm);
     const bool lrn = learned(h);
@@ -1073,9 +1104,18 @@ bdis_status run(bdis_t *h, std::vector<PairIn> &pairs, hipStream_t s, int mode =
             net_bytes += align_up(px * kNetIn * 2) + 3 * align_up(px * C * 2) + align_up(px * 2 * 4);
         }
     }
-    bdis_status st = ensure_ws(h, total + net_bytes);
-    if (st != BDIS_OK) return st;
-    char *base = h->ws;
+    char *base = fixed_ws;
+    if (fixed_ws) {
+        if (total + net_bytes > fixed_bytes) {
+            set_err(h->err, "this request needs %zu bytes of workspace; the no-allocation scratch holds %zu",
+                    total + net_bytes, fixed_bytes);
+            return BDIS_E_INVALID_ARG;
+        }
+    } else {
+        bdis_status st = ensure_ws(h, total + net_bytes);
+        if (st != BDIS_OK) return st;
+        base = h->ws;
+    }
     size_t off = 0;
     for (auto &p : pairs) {
         carve(base + off, p.g, esz, p.ws, inj);
@@ -1200,6 +1240,13 @@ bdis_status bdis_create(const bdis_params *p, int device, bdis_t **out) {
         bdis_destroy(h);
         return st;
     }
+    const hipError_t se = resolve_scratch(device, &h->scratch);
+    if (se != hipSuccess) {
+        (void)hipGetLastError();
+        set_err(g_thread_err, "hipGetSymbolAddress of the no-allocation scratch failed: %s", hipGetErrorString(se));
+        bdis_destroy(h);
+        return BDIS_E_HIP;
+    }
     *out = h;
     return BDIS_OK;
 }
@@ -1248,6 +1295,33 @@ bdis_status bdis_compute(bdis_t *h, const uint8_t *left, const uint8_t *right, i
     h->last = pairs[0];
     h->last_stream = s;
     return BDIS_OK;
+}
+
+bdis_status bdis_compute_noalloc(bdis_t *h, const uint8_t *left, const uint8_t *right, int32_t width,
+                                 int32_t height, int32_t pitch_bytes, float *disp, int32_t disp_pitch_elems,
+                                 void *stream) {
+    if (!h) { set_err(g_thread_err, "handle is NULL"); return BDIS_E_INVALID_ARG; }
+    bdis_status st = check_pair(h, left, right, width, height, pitch_bytes, disp, disp_pitch_elems, h->prm.patch);
+    if (st != BDIS_OK) return st;
+    if (learned(h)) {
+        set_err(h->err, "bdis_compute_noalloc runs the plain path only (init = zero)");
+        return BDIS_E_UNSUPPORTED;
+    }
+    if (!h->scratch) { set_err(h->err, "no scratch address for device %d", h->device); return BDIS_E_STATE; }
+    std::vector<PairIn> pairs(1);
+    PairIn &p = pairs[0];
+    p.left = left; p.right = right; p.disp = disp;
+    p.W = width; p.H = height; p.pitch = pitch_bytes; p.dpitch = disp_pitch_elems;
+    p.patch = h->prm.patch; p.stride = h->prm.stride;
+    p.dmax = h->prm.max_disparity;
+    // direct launches without per-launch events (recording them would create events)
+    const bool prof = h->profiling;
+    h->profiling = false;
+    st = run(h, pairs, (hipStream_t)stream, 1, h->scratch, BDIS_NOALLOC_SCRATCH_BYTES);
+    h->profiling = prof;
+    // the stage taps of bdis_debug_stage would point into the shared scratch
+    h->have_last = false;
+    return st;
 }
 
 bdis_status bdis_compute_batch(bdis_t *h, const bdis_pair *pairs, int32_t n, void *stream) {
