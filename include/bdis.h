@@ -26,6 +26,10 @@
  *   - A handle is bound to one device and is not thread-safe: use one handle
  *     per host thread.  The handle owns its device workspace, grown on demand
  *     (bdis_reserve pre-sizes it) and freed by bdis_destroy.
+ *   - Every compute call on a handle uses the same workspace, so calls on one
+ *     handle must not overlap on the device: issue them on one stream, or
+ *     order them (events) when they are on different streams.  Growing the
+ *     workspace synchronises the device first.
  */
 #ifndef BDIS_H
 #define BDIS_H
@@ -135,7 +139,10 @@ BDIS_API bdis_status bdis_create(const bdis_params *p, int device, bdis_t **out)
 BDIS_API bdis_status bdis_set_params(bdis_t *h, const bdis_params *p);
 
 /* Grows the workspace so pairs up to width x height (and batches of up to
- * n_pairs such pairs) need no allocation inside bdis_compute*. */
+ * n_pairs such pairs) need no allocation inside bdis_compute*, for the
+ * handle's current parameters (with init = learned, the network's level,
+ * keep mask and activations included; reserve after bdis_set_net for the
+ * network's channel count, else 48 channels are assumed). */
 BDIS_API bdis_status bdis_reserve(bdis_t *h, int32_t width, int32_t height, int32_t n_pairs);
 
 /* Disparity of one rectified pair, coarse to fine over the whole pyramid
@@ -324,6 +331,62 @@ BDIS_API bdis_status bdis_set_net(bdis_t *h, bdisnet_t *net);
  * |L(x) - R(x - d)|/64 for d = 0..13, R's column clamped.  Used to build
  * training batches. */
 BDIS_API bdis_status bdis_net_input(bdis_t *h, const bdis_pair *pairs, int32_t n, uint16_t *x, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Before and after the matcher (Sec. 1: stereo under the pinhole camera
+ * model is rectified and undistorted before disparity estimation; Sec. 3:
+ * the data are rectified and undistorted with their calibration; Sec. 3.2:
+ * errors in mm, and undistortion leaves invalid pixels at the image edges).
+ * Handle-free calls on the current HIP device; errors as above, with the
+ * message in bdis_last_error(NULL).
+ * ------------------------------------------------------------------------ */
+
+/* Calibration of one camera of a stereo rig.  Lens model: radial-tangential
+ * (Brown-Conrady).  A rectified pixel (u, v) looks along the ray
+ * ((u - ncx) / nfx, (v - ncy) / nfy, 1) of the rectified frame; R maps a
+ * direction of the raw camera frame to the rectified frame (row-major), so
+ * the raw frame sees R^T of that ray, projected to (x, y); the lens moves it
+ * to x (1 + k1 r^2 + k2 r^4 + k3 r^6) + 2 p1 x y + p2 (r^2 + 2 x^2) and
+ * y (1 + k1 r^2 + k2 r^4 + k3 r^6) + p1 (r^2 + 2 y^2) + 2 p2 x y
+ * (r^2 = x^2 + y^2), and (fx, fy, cx, cy) maps that to raw pixels. */
+typedef struct {
+    double fx, fy, cx, cy;       /* raw camera matrix, pixels                 */
+    double k1, k2, p1, p2, k3;   /* distortion of the raw image               */
+    double R[9];                 /* rectifying rotation, row-major            */
+    double nfx, nfy, ncx, ncy;   /* camera matrix of the rectified image      */
+} bdis_camera;
+
+/* One image to rectify: raw src (device uint8, src_pitch bytes per row) into
+ * dst (device uint8, dst_pitch bytes per row), both caller-owned. */
+typedef struct {
+    const uint8_t *src;
+    uint8_t *dst;
+    int32_t src_width, src_height, src_pitch;
+    int32_t dst_width, dst_height, dst_pitch;
+    bdis_camera cam;
+} bdis_rectify_job;
+
+/* Rectified, undistorted images for the matcher, n = 1..8 jobs (a stereo
+ * pair is 2) in one launch.  Each output pixel takes its raw image
+ * bilinearly at its source position (computed in FP64 per pixel; no map is
+ * stored) and rounds to the nearest gray level, halves up.  A source
+ * position outside the raw image's pixel centres gives 0, below the default
+ * validity band, so the matcher leaves such edge pixels out (Sec. 3.2).
+ * `jobs` is a HOST array read during the call.  Errors: BDIS_E_INVALID_ARG
+ * (NULL pointer, size outside [1, 65536], pitch < width, non-finite
+ * calibration or a zero focal length), BDIS_E_HIP. */
+BDIS_API bdis_status bdis_rectify(const bdis_rectify_job *jobs, int32_t n, void *stream);
+
+/* Depth along the optical axis of a rectified pair: Z = focal_px *
+ * baseline / d, computed in FP64 and stored as float32, in the unit of
+ * `baseline` (mm for the paper's figures); NaN where d is NaN or
+ * d <= min_disparity.  disp and depth: device float32, pitches in elements.
+ * Errors: BDIS_E_INVALID_ARG (NULL pointer, bad size or pitch, focal_px or
+ * baseline not finite and positive, min_disparity negative), BDIS_E_HIP. */
+BDIS_API bdis_status bdis_depth_from_disparity(const float *disp, int32_t width, int32_t height,
+                                               int32_t disp_pitch_elems, double focal_px, double baseline,
+                                               float min_disparity, float *depth, int32_t depth_pitch_elems,
+                                               void *stream);
 
 /* Frees the handle and its workspace; NULL is allowed. */
 BDIS_API void bdis_destroy(bdis_t *h);

@@ -51,6 +51,43 @@ class _Trace(C.Structure):
                 ("field", _PD * MAX_LEVELS)]
 
 
+class _Camera(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("fx", "fy", "cx", "cy", "k1", "k2", "p1", "p2", "k3")] + \
+               [("R", C.c_double * 9)] + [(n, C.c_double) for n in ("nfx", "nfy", "ncx", "ncy")]
+
+
+@dataclass
+class Camera:
+    """Raw camera matrix and Brown-Conrady distortion, rectifying rotation
+    (row-major, rectified = R raw) and the rectified camera matrix."""
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+    k1: float = 0.0
+    k2: float = 0.0
+    p1: float = 0.0
+    p2: float = 0.0
+    k3: float = 0.0
+    R: tuple = (1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0)
+    nfx: float | None = None
+    nfy: float | None = None
+    ncx: float | None = None
+    ncy: float | None = None
+
+    def _c(self) -> _Camera:
+        c = _Camera()
+        for n in ("fx", "fy", "cx", "cy", "k1", "k2", "p1", "p2", "k3"):
+            setattr(c, n, float(getattr(self, n)))
+        for i, v in enumerate(self.R):
+            c.R[i] = float(v)
+        c.nfx = float(self.fx if self.nfx is None else self.nfx)
+        c.nfy = float(self.fy if self.nfy is None else self.nfy)
+        c.ncx = float(self.cx if self.ncx is None else self.ncx)
+        c.ncy = float(self.cy if self.ncy is None else self.ncy)
+        return c
+
+
 @dataclass
 class Params:
     """Method parameters; defaults follow Sec. 3 (sigma_r = sigma_s = 4,
@@ -121,6 +158,13 @@ def lib():
         L.ref_compute_learned.argtypes = [C.POINTER(_Params), _PU8, _PU8, C.c_int, C.c_int,
                                           C.c_int, _PD, C.c_int, C.c_int, C.c_double, C.c_int,
                                           _PD, _PD, _PU8]
+        L.ref_rectify_source.restype = None
+        L.ref_rectify_source.argtypes = [C.POINTER(_Camera), C.c_double, C.c_double, _PD, _PD]
+        L.ref_rectify.restype = None
+        L.ref_rectify.argtypes = [C.POINTER(_Camera), _PU8, C.c_int, C.c_int, C.c_int, _PU8, C.c_int,
+                                  C.c_int, C.c_int]
+        L.ref_depth.restype = None
+        L.ref_depth.argtypes = [_PD, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double, _PD]
         L.ref_num_levels.restype = C.c_int
         L.ref_grid_count.restype = C.c_int
         L.ref_grid_pos.restype = C.c_int
@@ -361,3 +405,33 @@ def compute_learned(left, right, params: Params, net_out, net_level=4, inj_level
     if rc != 0:
         raise ValueError(f"ref_compute_learned failed: {rc}")
     return disp, field, keep
+
+
+# ---- rectification and depth ------------------------------------------------
+
+def rectify_source(cam: Camera, u, v):
+    """Raw-image position (x, y) that rectified pixel (u, v) samples."""
+    x, y = C.c_double(), C.c_double()
+    c = cam._c()
+    lib().ref_rectify_source(C.byref(c), float(u), float(v), C.byref(x), C.byref(y))
+    return x.value, y.value
+
+
+def rectify(cam: Camera, src, out_shape=None):
+    """Rectified, undistorted uint8 image of out_shape (default: src's)."""
+    src = np.ascontiguousarray(src, np.uint8)
+    sh, sw = src.shape
+    dh, dw = out_shape or src.shape
+    dst = np.empty((dh, dw), np.uint8)
+    c = cam._c()
+    lib().ref_rectify(C.byref(c), _u8(src), sw, sh, sw, _u8(dst), dw, dh, dw)
+    return dst
+
+
+def depth(disp, f, B, d_min=0.0):
+    """Z = f B / d (NaN where d is NaN or <= d_min)."""
+    d = np.ascontiguousarray(disp, np.float64)
+    H, W = d.shape
+    out = np.empty((H, W))
+    lib().ref_depth(_d(d), W, H, float(f), float(B), float(d_min), _d(out))
+    return out

@@ -735,3 +735,84 @@ done:
     free(awu);
     return rc;
 }
+
+/* ------------------------------------------------------------------------ */
+/* The steps around the matcher (Sec. 1: stereo follows the pinhole camera  */
+/* model with rectification and undistortion before disparity estimation;  */
+/* Sec. 3: the data are rectified and undistorted from the calibration;    */
+/* Sec. 3.2: depth errors in mm, and the invalid pixels undistortion leaves */
+/* at the image edges).  Not part of the paper's algorithm: standard        */
+/* pinhole geometry with the radial-tangential (Brown-Conrady) lens model.  */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    double fx, fy, cx, cy;          /* raw camera matrix                                */
+    double k1, k2, p1, p2, k3;      /* radial (k) and tangential (p) distortion          */
+    double R[9];                    /* rectifying rotation, row-major: rectified = R raw */
+    double nfx, nfy, ncx, ncy;      /* camera matrix of the rectified image             */
+} ref_camera;
+
+/* Where rectified pixel (u, v) comes from in the raw image.  The rectified
+ * pixel's ray in the rectified frame is ((u - ncx) / nfx, (v - ncy) / nfy, 1);
+ * the raw frame sees it rotated back by R^T; projected to the raw normalised
+ * plane (x, y), the lens moves it to
+ *   x_d = x (1 + k1 r^2 + k2 r^4 + k3 r^6) + 2 p1 x y + p2 (r^2 + 2 x^2)
+ *   y_d = y (1 + k1 r^2 + k2 r^4 + k3 r^6) + p1 (r^2 + 2 y^2) + 2 p2 x y
+ * with r^2 = x^2 + y^2, and the raw camera matrix maps it to pixels. */
+void ref_rectify_source(const ref_camera *c, double u, double v, double *xs, double *ys)
+{
+    double a = (u - c->ncx) / c->nfx, b = (v - c->ncy) / c->nfy;
+    /* R^T (a, b, 1): column j of R dotted with (a, b, 1) */
+    double X = c->R[0] * a + c->R[3] * b + c->R[6];
+    double Y = c->R[1] * a + c->R[4] * b + c->R[7];
+    double Z = c->R[2] * a + c->R[5] * b + c->R[8];
+    double x = X / Z, y = Y / Z;
+    double r2 = x * x + y * y;
+    double radial = 1.0 + c->k1 * r2 + c->k2 * r2 * r2 + c->k3 * r2 * r2 * r2;
+    double xd = x * radial + 2.0 * c->p1 * x * y + c->p2 * (r2 + 2.0 * x * x);
+    double yd = y * radial + c->p1 * (r2 + 2.0 * y * y) + 2.0 * c->p2 * x * y;
+    *xs = c->fx * xd + c->cx;
+    *ys = c->fy * yd + c->cy;
+}
+
+/* Rectified, undistorted image: each output pixel takes the raw image
+ * bilinearly at its source position, rounded to the nearest gray level
+ * (halves up).  A source position outside the raw image (beyond its pixel
+ * centres) gives 0, below the validity band: the matcher treats those edge
+ * pixels as invalid (Sec. 3.2). */
+void ref_rectify(const ref_camera *c, const uint8_t *src, int sw, int sh, int spitch, uint8_t *dst,
+                 int dw, int dh, int dpitch)
+{
+    for (int v = 0; v < dh; v++)
+        for (int u = 0; u < dw; u++) {
+            double xs, ys;
+            ref_rectify_source(c, (double)u, (double)v, &xs, &ys);
+            uint8_t out = 0;
+            if (xs >= 0.0 && ys >= 0.0 && xs <= (double)(sw - 1) && ys <= (double)(sh - 1)) {
+                int mx = (int)floor(xs), my = (int)floor(ys);
+                if (mx > sw - 2) mx = sw - 2;
+                if (my > sh - 2) my = sh - 2;
+                if (mx < 0) mx = 0;
+                if (my < 0) my = 0;
+                double fx = sw > 1 ? xs - mx : 0.0, fy = sh > 1 ? ys - my : 0.0;
+                int mx1 = sw > 1 ? mx + 1 : mx, my1 = sh > 1 ? my + 1 : my;
+                double top = (1.0 - fx) * src[(size_t)my * spitch + mx] + fx * src[(size_t)my * spitch + mx1];
+                double bot = (1.0 - fx) * src[(size_t)my1 * spitch + mx] + fx * src[(size_t)my1 * spitch + mx1];
+                double val = (1.0 - fy) * top + fy * bot;
+                double q = floor(val + 0.5);
+                out = (uint8_t)(q < 0.0 ? 0.0 : (q > 255.0 ? 255.0 : q));
+            }
+            dst[(size_t)v * dpitch + u] = out;
+        }
+}
+
+/* Depth along the optical axis from disparity in a rectified pair with
+ * focal length f (pixels) and baseline B: Z = f B / d, in the unit of B.
+ * Unestimated (NaN) and disparities at or below d_min give NaN. */
+void ref_depth(const double *disp, int W, int H, double f, double B, double d_min, double *depth)
+{
+    for (size_t i = 0; i < (size_t)W * H; i++) {
+        double d = disp[i];
+        depth[i] = (isfinite(d) && d > d_min) ? f * B / d : NAN;
+    }
+}

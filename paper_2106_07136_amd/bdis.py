@@ -42,6 +42,17 @@ class CPair(C.Structure):
                 ("disp_pitch_elems", C.c_int32), ("max_disparity", C.c_float)]
 
 
+class CCamera(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("fx", "fy", "cx", "cy", "k1", "k2", "p1", "p2", "k3")] + \
+               [("R", C.c_double * 9)] + [(n, C.c_double) for n in ("nfx", "nfy", "ncx", "ncy")]
+
+
+class CRectifyJob(C.Structure):
+    _fields_ = [("src", C.c_void_p), ("dst", C.c_void_p), ("src_width", C.c_int32), ("src_height", C.c_int32),
+                ("src_pitch", C.c_int32), ("dst_width", C.c_int32), ("dst_height", C.c_int32),
+                ("dst_pitch", C.c_int32), ("cam", CCamera)]
+
+
 class CKernelTime(C.Structure):
     _fields_ = [("name", C.c_char * 48), ("launches", C.c_int32), ("total_ms", C.c_double)]
 
@@ -114,6 +125,8 @@ def lib():
         L.bdis_net_input.argtypes = [vp, C.POINTER(CPair), i32, vp, vp]
         L.bdis_set_profiling.argtypes = [vp, i32]
         L.bdis_get_profile.argtypes = [vp, C.POINTER(CKernelTime), i32, C.POINTER(i32)]
+        L.bdis_rectify.argtypes = [C.POINTER(CRectifyJob), i32, vp]
+        L.bdis_depth_from_disparity.argtypes = [vp, i32, i32, i32, C.c_double, C.c_double, C.c_float, vp, i32, vp]
         L.bdis_destroy.argtypes = [vp]
         L.bdis_destroy.restype = None
         L.bdis_status_string.argtypes = [C.c_int]
@@ -124,7 +137,8 @@ def lib():
                      "bdis_compute_noalloc",
                      "bdis_compute_batch", "bdis_set_tuning", "bdis_debug_stage",
                      "bdis_set_profiling", "bdis_get_profile", "bdis_set_batch_mode",
-                     "bdis_batch_error", "bdis_set_net", "bdis_net_input", "bdis_set_fold_densify"):
+                     "bdis_batch_error", "bdis_set_net", "bdis_net_input", "bdis_set_fold_densify",
+                     "bdis_rectify", "bdis_depth_from_disparity"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -296,3 +310,69 @@ class Bdis:
         arr = (CKernelTime * max(cnt.value, 1))()
         _check(lib().bdis_get_profile(self._h, arr, cnt.value, C.byref(cnt)), self._h)
         return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms) for i in range(cnt.value)}
+
+
+@dataclass
+class Camera:
+    """Mirror of bdis_camera: raw camera matrix, Brown-Conrady distortion,
+    rectifying rotation (row-major, rectified = R raw) and the rectified
+    camera matrix (None = the raw one)."""
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+    k1: float = 0.0
+    k2: float = 0.0
+    p1: float = 0.0
+    p2: float = 0.0
+    k3: float = 0.0
+    R: tuple = (1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0)
+    nfx: float | None = None
+    nfy: float | None = None
+    ncx: float | None = None
+    ncy: float | None = None
+
+    def to_c(self) -> CCamera:
+        c = CCamera()
+        for n in ("fx", "fy", "cx", "cy", "k1", "k2", "p1", "p2", "k3"):
+            setattr(c, n, float(getattr(self, n)))
+        for i, v in enumerate(self.R):
+            c.R[i] = float(v)
+        c.nfx = float(self.fx if self.nfx is None else self.nfx)
+        c.nfy = float(self.fy if self.nfy is None else self.nfy)
+        c.ncx = float(self.cx if self.ncx is None else self.ncx)
+        c.ncy = float(self.cy if self.ncy is None else self.ncy)
+        return c
+
+
+def rectify(srcs, cams, outs=None, out_shapes=None, stream=None):
+    """Rectified, undistorted uint8 device images, one per (src, camera), in
+    one launch (up to 8)."""
+    import torch
+    n = len(srcs)
+    if outs is None:
+        shapes = out_shapes or [s.shape for s in srcs]
+        outs = [torch.empty(sh, dtype=torch.uint8, device=s.device) for sh, s in zip(shapes, srcs)]
+    arr = (CRectifyJob * n)()
+    for i, (s, o, c) in enumerate(zip(srcs, outs, cams)):
+        if s.dtype != torch.uint8 or o.dtype != torch.uint8 or s.stride(1) != 1 or o.stride(1) != 1:
+            raise ValueError(f"job {i}: uint8 images with contiguous rows required")
+        arr[i] = CRectifyJob(s.data_ptr(), o.data_ptr(), s.shape[1], s.shape[0], s.stride(0), o.shape[1],
+                             o.shape[0], o.stride(0), c.to_c())
+    _check(lib().bdis_rectify(arr, n, _stream_ptr(stream)))
+    return outs
+
+
+def depth_from_disparity(disp, focal_px, baseline, min_disparity=0.0, out=None, stream=None):
+    """Z = focal_px * baseline / d (float32 device tensor, NaN where d is NaN
+    or <= min_disparity)."""
+    import torch
+    H, W = disp.shape
+    if out is None:
+        out = torch.empty((H, W), dtype=torch.float32, device=disp.device)
+    if disp.dtype != torch.float32 or out.dtype != torch.float32 or disp.stride(1) != 1 or out.stride(1) != 1:
+        raise ValueError("float32 tensors with contiguous rows required")
+    _check(lib().bdis_depth_from_disparity(disp.data_ptr(), W, H, disp.stride(0), float(focal_px), float(baseline),
+                                           float(min_disparity), out.data_ptr(), out.stride(0),
+                                           _stream_ptr(stream)))
+    return out

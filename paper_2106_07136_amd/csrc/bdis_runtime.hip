@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "bdis.h"
+#include "bdis_geometry.hpp"
 #include "bdis_kernels.hpp"
 #include "bdis_persist.hpp"
 #include "bdisnet_internal.hpp"
@@ -775,6 +776,15 @@ void pick_tuning(const bdis_t *h, int W, int &patch, int &stride) {
         if (W <= h->tune_w[i]) { patch = h->tune_p[i]; stride = h->tune_s[i]; return; }
 }
 
+// calibration of one rectify job: finite, non-zero focal lengths
+bool camera_ok(const bdis_camera &c) {
+    const double v[] = {c.fx, c.fy, c.cx, c.cy, c.k1, c.k2, c.p1, c.p2, c.k3, c.nfx, c.nfy, c.ncx, c.ncy,
+                        c.R[0], c.R[1], c.R[2], c.R[3], c.R[4], c.R[5], c.R[6], c.R[7], c.R[8]};
+    for (double x : v)
+        if (!std::isfinite(x)) return false;
+    return c.fx != 0.0 && c.fy != 0.0 && c.nfx != 0.0 && c.nfy != 0.0;
+}
+
 bdis_status check_pair(bdis_t *h, const uint8_t *L, const uint8_t *R, int W, int H, int pitch,
                        float *disp, int dpitch, int patch) {
     if (!L || !R || !disp) { set_err(h->err, "NULL image or output pointer"); return BDIS_E_INVALID_ARG; }
@@ -1269,11 +1279,25 @@ bdis_status bdis_reserve(bdis_t *h, int32_t width, int32_t height, int32_t n_pai
     Geo g;
     size_t worst = 0;
     int Lreq = requested_levels(h->prm, h->prm.max_disparity);
+    // the learned init also needs the pyramid down to the network's level,
+    // the keep mask at the injection level and the network's activations
+    // (input, three hidden layers, output) for every pair
+    const bool lrn = learned(h);
+    const int inj = lrn ? h->prm.learned_fine_levels : 0;
     for (int p : kSupportedPatch)
         for (int s = 1; s <= p; s++)
-            if (make_geo(width, height, p, s, Lreq, g)) worst = std::max(worst, align_up(pair_ws_bytes(g, sizeof(double))));
+            if (make_geo(width, height, p, s, Lreq, g, lrn ? kNetLevel + 1 : 0))
+                worst = std::max(worst, align_up(pair_ws_bytes(g, sizeof(double), g.L > inj ? inj : 0)));
+    size_t net = 0;
+    if (lrn) {
+        int w4 = width, h4 = height;
+        for (int l = 0; l < kNetLevel; l++) { w4 = (w4 + 1) / 2; h4 = (h4 + 1) / 2; }
+        const size_t C = h->net ? (size_t)bdisnet::channels(h->net) : 48;
+        const size_t px = (size_t)n_pairs * w4 * h4;
+        net = align_up(px * kNetIn * 2) + 3 * align_up(px * C * 2) + align_up(px * 2 * 4);
+    }
     DeviceGuard dg(h->device);
-    return ensure_ws(h, worst * (size_t)n_pairs);
+    return ensure_ws(h, worst * (size_t)n_pairs + net);
 }
 
 bdis_status bdis_compute(bdis_t *h, const uint8_t *left, const uint8_t *right, int32_t width,
@@ -1572,6 +1596,66 @@ void bdis_destroy(bdis_t *h) {
         for (auto e : h->spare) (void)hipEventDestroy(e);
     }
     delete h;
+}
+
+bdis_status bdis_rectify(const bdis_rectify_job *jobs, int32_t n, void *stream) {
+    if (!jobs || n < 1 || n > kMaxRectifyJobs) {
+        set_err(g_thread_err, "need 1 <= n <= %d rectify jobs", kMaxRectifyJobs);
+        return BDIS_E_INVALID_ARG;
+    }
+    RectifyPack pk;
+    memset(&pk, 0, sizeof pk);
+    pk.n = n;
+    long long blocks = 0;
+    for (int i = 0; i < n; i++) {
+        const bdis_rectify_job &J = jobs[i];
+        if (!J.src || !J.dst) { set_err(g_thread_err, "job %d: NULL image pointer", i); return BDIS_E_INVALID_ARG; }
+        if (J.src_width < 1 || J.src_height < 1 || J.dst_width < 1 || J.dst_height < 1 || J.src_width > 65536 ||
+            J.src_height > 65536 || J.dst_width > 65536 || J.dst_height > 65536) {
+            set_err(g_thread_err, "job %d: image sizes must be in [1, 65536]", i);
+            return BDIS_E_INVALID_ARG;
+        }
+        if (J.src_pitch < J.src_width || J.dst_pitch < J.dst_width) {
+            set_err(g_thread_err, "job %d: pitch smaller than width", i);
+            return BDIS_E_INVALID_ARG;
+        }
+        if (!camera_ok(J.cam)) {
+            set_err(g_thread_err, "job %d: calibration must be finite with non-zero focal lengths", i);
+            return BDIS_E_INVALID_ARG;
+        }
+        pk.j[i] = J;
+        pk.blocks[i] = (int)blocks;
+        const long long threads = (long long)((J.dst_width + kRectPx - 1) / kRectPx) * J.dst_height;
+        blocks += (threads + bdis::kBlock - 1) / bdis::kBlock;
+    }
+    pk.blocks[n] = (int)blocks;
+    hipLaunchKernelGGL(k_rectify, dim3((unsigned)blocks), dim3(bdis::kBlock), 0, (hipStream_t)stream, pk);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) { set_err(g_thread_err, "k_rectify launch failed: %s", hipGetErrorString(e)); return BDIS_E_HIP; }
+    return BDIS_OK;
+}
+
+bdis_status bdis_depth_from_disparity(const float *disp, int32_t width, int32_t height, int32_t disp_pitch_elems,
+                                      double focal_px, double baseline, float min_disparity, float *depth,
+                                      int32_t depth_pitch_elems, void *stream) {
+    if (!disp || !depth) { set_err(g_thread_err, "NULL disparity or depth pointer"); return BDIS_E_INVALID_ARG; }
+    if (width < 1 || height < 1 || width > 65536 || height > 65536 || (long long)width * height > (1ll << 31) - 1) {
+        set_err(g_thread_err, "sizes must be in [1, 65536] with fewer than 2^31 pixels");
+        return BDIS_E_INVALID_ARG;
+    }
+    if (disp_pitch_elems < width || depth_pitch_elems < width) { set_err(g_thread_err, "pitch smaller than width"); return BDIS_E_INVALID_ARG; }
+    if (!std::isfinite(focal_px) || !std::isfinite(baseline) || !std::isfinite(min_disparity) || focal_px <= 0.0 ||
+        baseline <= 0.0 || min_disparity < 0.f) {
+        set_err(g_thread_err, "focal length and baseline must be finite and positive, min_disparity finite and >= 0");
+        return BDIS_E_INVALID_ARG;
+    }
+    const long long n = (long long)width * height;
+    hipLaunchKernelGGL(k_depth, dim3((unsigned)((n + bdis::kBlock - 1) / bdis::kBlock)), dim3(bdis::kBlock), 0,
+                       (hipStream_t)stream, disp, width, height, disp_pitch_elems, focal_px * baseline,
+                       min_disparity, depth, depth_pitch_elems);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) { set_err(g_thread_err, "k_depth launch failed: %s", hipGetErrorString(e)); return BDIS_E_HIP; }
+    return BDIS_OK;
 }
 
 const char *bdis_status_string(bdis_status s) {

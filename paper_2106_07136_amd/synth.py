@@ -202,3 +202,83 @@ def mixed_batch_spec(seed0: int = 3000):
         for _ in range(n):
             spec.append((W, H, 0.1 * W, seed0 + len(spec)))
     return spec
+
+
+def stereo_rig(W: int, H: int, seed: int, baseline: float = 5.0) -> dict:
+    """Seeded synthetic calibration of a stereo endoscope of W x H images (the
+    calibration of the paper's rigs is not available): per camera a focal
+    length of 0.8-1.0 W px, a principal point within 2 % of the centre,
+    barrel distortion (k1 in [-0.25, -0.1], k2 in [0, 0.05]), tangential
+    terms below 1e-3, and a rectifying rotation of up to 1 degree about each
+    axis; both rectified cameras share a focal length and principal point.
+    Returns {"left": {...}, "right": {...}, "focal": f, "baseline": B} with
+    each camera's fields named as in bdis_camera.  Draw order fixed."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nf = float(rng.uniform(0.8, 1.0) * W)
+    ncx, ncy = (W - 1) / 2.0, (H - 1) / 2.0
+    cams = {}
+    for side in ("left", "right"):
+        f = float(rng.uniform(0.8, 1.0) * W)
+        cx = (W - 1) / 2.0 + float(rng.uniform(-0.02, 0.02) * W)
+        cy = (H - 1) / 2.0 + float(rng.uniform(-0.02, 0.02) * H)
+        k1, k2 = float(rng.uniform(-0.25, -0.1)), float(rng.uniform(0.0, 0.05))
+        p1, p2 = (float(v) for v in rng.uniform(-1e-3, 1e-3, 2))
+        a, b, c = (float(v) for v in np.deg2rad(rng.uniform(-1.0, 1.0, 3)))
+        rz = np.array([[np.cos(a), -np.sin(a), 0], [np.sin(a), np.cos(a), 0], [0, 0, 1]])
+        ry = np.array([[np.cos(b), 0, np.sin(b)], [0, 1, 0], [-np.sin(b), 0, np.cos(b)]])
+        rx = np.array([[1, 0, 0], [0, np.cos(c), -np.sin(c)], [0, np.sin(c), np.cos(c)]])
+        R = rz @ ry @ rx
+        cams[side] = dict(fx=f, fy=f, cx=cx, cy=cy, k1=k1, k2=k2, p1=p1, p2=p2, k3=0.0,
+                          R=tuple(float(v) for v in R.ravel()), nfx=nf, nfy=nf, ncx=ncx, ncy=ncy)
+    return {"left": cams["left"], "right": cams["right"], "focal": nf, "baseline": float(baseline)}
+
+
+def _keys_cubic_2d(img: np.ndarray, xs: np.ndarray, ys: np.ndarray) -> np.ndarray:
+    """Keys (a = -0.5) bicubic reading of img at (xs, ys), border replicated."""
+    H, W = img.shape
+
+    def k(s):
+        s = np.abs(s)
+        return np.where(s <= 1, (1.5 * s - 2.5) * s * s + 1,
+                        np.where(s < 2, ((-0.5 * s + 2.5) * s - 4) * s + 2, 0.0))
+
+    x0, y0 = np.floor(xs).astype(np.int64), np.floor(ys).astype(np.int64)
+    out = np.zeros(xs.shape)
+    for j in range(-1, 3):
+        wy = k(ys - (y0 + j))
+        yy = np.clip(y0 + j, 0, H - 1)
+        for i in range(-1, 3):
+            xx = np.clip(x0 + i, 0, W - 1)
+            out += wy * k(xs - (x0 + i)) * img[yy, xx]
+    return out
+
+
+def raw_capture(rect: np.ndarray, cam: dict, iters: int = 20) -> np.ndarray:
+    """The raw (distorted, unrectified) uint8 image a camera with calibration
+    `cam` (fields as in bdis_camera) would record of the rectified image
+    `rect`: for each raw pixel, its undistorted ray (fixed-point inversion of
+    the lens model, `iters` steps), rotated into the rectified frame and read
+    from `rect` with Keys bicubic interpolation (not the bilinear reading of
+    the rectification itself).  Rays that leave `rect` give 0.  Input
+    generation only: it lets a rectification be checked against the image it
+    should recover."""
+    H, W = rect.shape
+    y, x = np.mgrid[0:H, 0:W].astype(np.float64)
+    xd = (x - cam["cx"]) / cam["fx"]
+    yd = (y - cam["cy"]) / cam["fy"]
+    xu, yu = xd.copy(), yd.copy()
+    for _ in range(iters):
+        r2 = xu * xu + yu * yu
+        radial = 1 + cam["k1"] * r2 + cam["k2"] * r2 * r2 + cam["k3"] * r2 ** 3
+        dx = 2 * cam["p1"] * xu * yu + cam["p2"] * (r2 + 2 * xu * xu)
+        dy = cam["p1"] * (r2 + 2 * yu * yu) + 2 * cam["p2"] * xu * yu
+        xu, yu = (xd - dx) / radial, (yd - dy) / radial
+    R = np.asarray(cam["R"], np.float64).reshape(3, 3)
+    X = R[0, 0] * xu + R[0, 1] * yu + R[0, 2]
+    Y = R[1, 0] * xu + R[1, 1] * yu + R[1, 2]
+    Z = R[2, 0] * xu + R[2, 1] * yu + R[2, 2]
+    u = cam["nfx"] * X / Z + cam["ncx"]
+    v = cam["nfy"] * Y / Z + cam["ncy"]
+    val = _keys_cubic_2d(rect.astype(np.float64), u, v)
+    inside = (u >= 0) & (v >= 0) & (u <= W - 1) & (v <= H - 1)
+    return np.where(inside, np.clip(np.rint(val), 0, 255), 0).astype(np.uint8)

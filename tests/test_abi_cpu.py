@@ -109,3 +109,14 @@ def test_create_without_gpu_reports_no_device():
     with pytest.raises(bdis.BdisError) as e:
         bdis.Bdis(bdis.Params(window=2))
     assert e.value.status == bdis.E_INVALID_ARG
+
+
+def test_geometry_structs_match_the_header():
+    """bdis_camera is 22 doubles and bdis_rectify_job two pointers, six
+    int32 and a camera, with no padding (the kernels take them by value)."""
+    import ctypes as C
+    assert C.sizeof(bdis.CCamera) == 22 * 8
+    assert C.sizeof(bdis.CRectifyJob) == 2 * 8 + 6 * 4 + 22 * 8
+    txt = open(os.path.join(ROOT, "include", "bdis.h")).read()
+    for name in ("bdis_rectify", "bdis_depth_from_disparity", "bdis_camera", "bdis_rectify_job"):
+        assert name in txt

@@ -50,6 +50,17 @@ MUTATIONS = {
     "merge_inverted": ("if (keep[i])\n                    U[l][i] = Ug[i];",
                        "if (!keep[i])\n                    U[l][i] = Ug[i];"),
     "fine_iters_ignored": ("Pl.iters = lrn->fine_iters;", "Pl.iters = P->iters;"),
+    # rectification and depth
+    "rotation_not_transposed": ("double X = c->R[0] * a + c->R[3] * b + c->R[6];",
+                                "double X = c->R[0] * a + c->R[1] * b + c->R[2];"),
+    "tangential_swapped": ("double xd = x * radial + 2.0 * c->p1 * x * y + c->p2 * (r2 + 2.0 * x * x);",
+                           "double xd = x * radial + 2.0 * c->p2 * x * y + c->p1 * (r2 + 2.0 * x * x);"),
+    "radial_k2_power": ("c->k2 * r2 * r2 +", "c->k2 * r2 +"),
+    "tangential_no_2x2": ("c->p2 * (r2 + 2.0 * x * x)", "c->p2 * (r2 + x * x)"),
+    "rectify_truncates": ("double q = floor(val + 0.5);", "double q = floor(val);"),
+    "rectify_outside_kept": ("if (xs >= 0.0 && ys >= 0.0 && xs <= (double)(sw - 1) && ys <= (double)(sh - 1)) {",
+                             "if (1) {"),
+    "depth_inverted": ("f * B / d : NAN;", "d / (f * B) : NAN;"),
 }
 
 

@@ -635,3 +635,91 @@ def test_learned_confident_shift_needs_no_coarse_levels(ref):
     d, field, keep = ref.compute_learned(S.left, S.right, prm, net, 4, 2, 0.5, fine_iters=8)
     assert keep.all() and np.all(field == -6.0 / 4)
     assert np.nanmax(np.abs(d[8:-8, 14:-8] - 6)) < 1e-3
+
+
+# ---------------------------------------------------------------- rectification and depth
+
+def _img(h, w, seed=0):
+    return np.random.default_rng(seed).integers(0, 256, (h, w)).astype(np.uint8)
+
+
+def test_rectify_identity_is_exact(ref):
+    src = _img(37, 53)
+    cam = ref.Camera(400.0, 410.0, 26.0, 18.0)
+    np.testing.assert_array_equal(ref.rectify(cam, src), src)
+
+
+def test_rectify_principal_point_shift(ref):
+    """Moving the rectified principal point by 3 px shifts the image by 3 px;
+    the 3 columns whose source lies left of the raw image are 0 (invalid).
+    Half a pixel gives the mean of two neighbours, rounded half up (a focal
+    length of 256 px keeps the coordinates exact)."""
+    src = _img(20, 30, 1)
+    cam = ref.Camera(300.0, 300.0, 15.0, 10.0, ncx=18.0)
+    out = ref.rectify(cam, src)
+    np.testing.assert_array_equal(out[:, 3:], src[:, :-3])
+    assert np.all(out[:, :3] == 0)
+    half = ref.rectify(ref.Camera(256.0, 256.0, 15.0, 10.0, ncx=15.5), src)
+    s = src.astype(np.int64)
+    np.testing.assert_array_equal(half[:, 1:], (s[:, :-1] + s[:, 1:] + 1) // 2)
+    assert np.all(half[:, 0] == 0)
+
+
+def test_rectify_rotation_about_the_axis(ref):
+    """A rectifying rotation of 90 degrees about the optical axis (rectified
+    = R raw, R = [[0, -1, 0], [1, 0, 0], [0, 0, 1]]) on a square image with a
+    centred principal point: rectified pixel (u, v) shows raw pixel
+    (v, N - 1 - u) (R used in the wrong direction would show (N - 1 - v, u))."""
+    N = 24
+    src = _img(N, N, 2)
+    c = (N - 1) / 2
+    cam = ref.Camera(200.0, 200.0, c, c, R=(0, -1, 0, 1, 0, 0, 0, 0, 1))
+    out = ref.rectify(cam, src)
+    v, u = np.mgrid[0:N, 0:N]
+    np.testing.assert_array_equal(out, src[N - 1 - u, v])
+
+
+def test_rectify_source_lens_model_special_cases(ref):
+    """The lens model on the x axis (y = 0, fx = fy = 100, centre 50, 40),
+    point at normalised x = 0.5: radial terms scale it by 1 + k1 x^2 + k2 x^4
+    + k3 x^6; p1 moves it along y by p1 x^2; p2 along x by 3 p2 x^2.  On the
+    y axis p1 and p2 swap roles."""
+    base = dict(fx=100.0, fy=100.0, cx=50.0, cy=40.0)
+    u, v = 100.0, 40.0  # x = 0.5, y = 0
+    for kw, (ex, ey) in [(dict(k1=0.2), (50 + 50 * 1.05, 40)),
+                         (dict(k2=0.16), (50 + 50 * 1.01, 40)),
+                         (dict(k3=0.64), (50 + 50 * 1.01, 40)),
+                         (dict(p1=0.1), (100, 40 + 100 * 0.025)),
+                         (dict(p2=0.1), (100 + 100 * 0.075, 40))]:
+        xs, ys = ref.rectify_source(ref.Camera(**base, **kw), u, v)
+        assert abs(xs - ex) < 1e-12 and abs(ys - ey) < 1e-12, (kw, xs, ys)
+    # y axis, normalised y = 0.5
+    xs, ys = ref.rectify_source(ref.Camera(**base, p1=0.1), 50.0, 90.0)
+    assert abs(xs - 50) < 1e-12 and abs(ys - (90 + 100 * 0.075)) < 1e-12
+    xs, ys = ref.rectify_source(ref.Camera(**base, p2=0.1), 50.0, 90.0)
+    assert abs(xs - (50 + 100 * 0.025)) < 1e-12 and abs(ys - 90) < 1e-12
+
+
+def test_rectify_radial_lens_keeps_radial_symmetry(ref):
+    """Radial distortion around a centred principal point maps a radially
+    symmetric raw image to a radially symmetric rectified one (pixels mirrored
+    through the centre take equal values)."""
+    N = 41
+    c = (N - 1) / 2
+    y, x = np.mgrid[0:N, 0:N]
+    r = np.hypot(x - c, y - c)
+    src = np.clip(np.rint(128 + 100 * np.cos(r / 3.0)), 0, 255).astype(np.uint8)
+    out = ref.rectify(ref.Camera(60.0, 60.0, c, c, k1=-0.15, k2=0.02), src)
+    np.testing.assert_array_equal(out, out[::-1, ::-1])
+    np.testing.assert_array_equal(out, out.T)
+    assert not np.array_equal(out, src)
+
+
+def test_depth_closed_form(ref):
+    d = np.array([[1.0, 2.5, np.nan], [0.0, -1.0, 40.0]])
+    z = ref.depth(d, 700.0, 5.5, d_min=0.0)
+    fin = np.isfinite(z)
+    np.testing.assert_array_equal(fin, [[True, True, False], [False, False, True]])
+    np.testing.assert_allclose(z[fin] * d[fin], 700.0 * 5.5, rtol=1e-15)
+    z2 = ref.depth(d, 700.0, 5.5, d_min=2.0)
+    assert np.isnan(z2[0, 0]) and np.isfinite(z2[0, 1])
