@@ -304,6 +304,22 @@ BDIS_API bdis_status bdisnet_get_grads(bdisnet_t *h, float *host, int64_t n);
  * BF16 copies used by the kernels are refreshed. */
 BDIS_API bdis_status bdisnet_adam_step(bdisnet_t *h, float lr, float beta1, float beta2, float eps,
                                        int32_t step, void *stream);
+/* Checkpoints for resuming training bit for bit.  Layout (little-endian):
+ * 8 bytes "BDISNET\0", uint32 version (1), int32 channels, int64 parameter
+ * count n, int64 last Adam step, then n FP32 master weights (the layout of
+ * bdisnet_set_params), n FP32 first and n FP32 second Adam moments:
+ * bdisnet_checkpoint_bytes(h) = 32 + 12 n bytes.  Save writes to HOST memory
+ * `blob` of capacity `bytes`; load restores weights, moments and step into a
+ * network of the same channel count and refreshes the BF16 copies.  Both
+ * synchronise the device.  Errors: BDIS_E_INVALID_ARG (capacity too small;
+ * on load: wrong magic or version, another channel count, a truncated blob,
+ * a non-finite value or a negative second moment). */
+BDIS_API int64_t bdisnet_checkpoint_bytes(const bdisnet_t *h);
+BDIS_API bdis_status bdisnet_save(bdisnet_t *h, void *blob, int64_t bytes);
+BDIS_API bdis_status bdisnet_load(bdisnet_t *h, const void *blob, int64_t bytes);
+/* The last step passed to bdisnet_adam_step (0 after create or
+ * set_params; restored by load). */
+BDIS_API int32_t bdisnet_step(const bdisnet_t *h);
 /* Input of layer `layer` (0 = the network input) from the last forward, as
  * bfloat16 bits in HOST memory.  Synchronous. */
 BDIS_API bdis_status bdisnet_debug_activation(bdisnet_t *h, int32_t layer, uint16_t *host, size_t elems);
@@ -321,9 +337,17 @@ BDIS_API const char *bdisnet_last_error(const bdisnet_t *h);
  * of the handle (forked from and joined back into the caller's stream, also
  * inside a captured graph), so the network costs no time on the path.  The
  * finer levels run with learned_iters LK iterations.  The handle does not own
- * the network; keep it alive while it is attached.
+ * a network attached here; keep it alive while it is attached (a network the
+ * handle owns, from bdis_set_net_weights, is freed first).
  * Errors: BDIS_E_INVALID_ARG (network on another device). */
 BDIS_API bdis_status bdis_set_net(bdis_t *h, bdisnet_t *net);
+
+/* Loads a network for the learned init from a bdisnet_save checkpoint (HOST
+ * memory, read during the call; only its weights are used) into a network
+ * the handle creates and owns, and attaches it in place of any other.  The
+ * owned network is freed by bdis_destroy, by the next bdis_set_net_weights
+ * and by bdis_set_net.  Errors: as bdisnet_load, BDIS_E_OOM, BDIS_E_HIP. */
+BDIS_API bdis_status bdis_set_net_weights(bdis_t *h, const void *blob, int64_t bytes);
 
 /* Network input of n pairs whose 1/16 levels have the same size: builds
  * their pyramids down to the 1/16 level and writes x (device, NHWC

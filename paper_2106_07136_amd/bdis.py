@@ -233,6 +233,16 @@ class Bdis:
         _check(lib().bdis_set_net(self._h, net.handle if net is not None else None), self._h)
         self._net = net
 
+    def set_net_weights(self, blob: bytes):
+        """Load a network checkpoint (ProposalNet.save_checkpoint) into a
+        network this handle owns and attach it for params.init == 1."""
+        import numpy as np
+        from . import net as _net
+        L = _net._lib()
+        a = np.frombuffer(blob, np.uint8)
+        _check(L.bdis_set_net_weights(self._h, a.ctypes.data, a.size), self._h)
+        self._net = None
+
     def net_input(self, lefts, rights, out=None, stream=None):
         """Network input (N, H/16, W/16, 16) bfloat16 for same-size pairs."""
         import torch

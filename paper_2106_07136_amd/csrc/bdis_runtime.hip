@@ -250,6 +250,7 @@ struct bdis_ctx {
     double *gtab_d = nullptr;  // spatial Gaussian tables, one per precision
     float *gtab_f = nullptr;
     bdisnet_t *net = nullptr;  // proposal network for init = BDIS_INIT_LEARNED
+    bdisnet_t *owned_net = nullptr;  // created by bdis_set_net_weights (== net while attached)
     std::vector<NetGroup> groups;
     // last single-pair run, for bdis_debug_stage
     bool have_last = false;
@@ -1401,8 +1402,33 @@ bdis_status bdis_batch_error(bdis_t *h, int32_t *flag) {
 bdis_status bdis_set_net(bdis_t *h, bdisnet_t *net) {
     if (!h) { set_err(g_thread_err, "handle is NULL"); return BDIS_E_INVALID_ARG; }
     if (net && bdisnet::device_of(net) != h->device) { set_err(h->err, "network is on another device"); return BDIS_E_INVALID_ARG; }
+    if (h->owned_net && h->owned_net != net) {
+        bdisnet_destroy(h->owned_net);  // synchronises the device first
+        h->owned_net = nullptr;
+    }
     h->net = net;
     h->lv_key.clear();
+    return BDIS_OK;
+}
+
+bdis_status bdis_set_net_weights(bdis_t *h, const void *blob, int64_t bytes) {
+    if (!h) { set_err(g_thread_err, "handle is NULL"); return BDIS_E_INVALID_ARG; }
+    if (!blob || bytes < 32) { set_err(h->err, "checkpoint too short"); return BDIS_E_INVALID_ARG; }
+    int32_t C = 0;
+    memcpy(&C, static_cast<const char *>(blob) + 12, 4);
+    if (C != 32 && C != 48) { set_err(h->err, "checkpoint of an unsupported network (%d channels)", C); return BDIS_E_INVALID_ARG; }
+    bdisnet_t *net = nullptr;
+    bdis_status st = bdisnet_create(C, h->device, &net);
+    if (st != BDIS_OK) { set_err(h->err, "%s", bdisnet_last_error(nullptr)); return st; }
+    st = bdisnet_load(net, blob, bytes);
+    if (st != BDIS_OK) {
+        set_err(h->err, "%s", bdisnet_last_error(net));
+        bdisnet_destroy(net);
+        return st;
+    }
+    st = bdis_set_net(h, net);
+    if (st != BDIS_OK) { bdisnet_destroy(net); return st; }
+    h->owned_net = net;
     return BDIS_OK;
 }
 
@@ -1595,6 +1621,7 @@ void bdis_destroy(bdis_t *h) {
         for (auto &r : h->pending) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
         for (auto e : h->spare) (void)hipEventDestroy(e);
     }
+    if (h->owned_net) bdisnet_destroy(h->owned_net);
     delete h;
 }
 

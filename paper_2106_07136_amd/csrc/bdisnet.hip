@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -53,6 +54,7 @@ struct bdisnet_ctx {
     size_t red_cap = 0;
     Geo last{0, 0, 0, 0};
     bool have_fwd = false, have_gout = false;
+    int step = 0;  // last Adam step taken (0: none since the weights were set)
     char err[512] = "";
 };
 
@@ -435,6 +437,75 @@ bdis_status bdisnet_set_params(bdisnet_t *h, const float *host, int64_t n) {
     NCHK(h, hipMemcpy(h->w, host, n * 4, hipMemcpyHostToDevice));
     NCHK(h, hipMemset(h->m, 0, n * 4));
     NCHK(h, hipMemset(h->v, 0, n * 4));
+    h->step = 0;
+    bdis_status st = pack_all(h, nullptr);
+    if (st != BDIS_OK) return st;
+    NCHK(h, hipDeviceSynchronize());
+    return BDIS_OK;
+}
+
+// Checkpoint layout (little-endian): 8 magic bytes "BDISNET\0", uint32
+// version 1, int32 channels, int64 parameter count n, int64 last Adam step,
+// then the FP32 master weights, the first and the second Adam moments (n
+// values each).
+namespace {
+constexpr char kMagic[8] = {'B', 'D', 'I', 'S', 'N', 'E', 'T', 0};
+constexpr uint32_t kVersion = 1;
+constexpr int64_t kHeader = 32;
+}  // namespace
+
+int64_t bdisnet_checkpoint_bytes(const bdisnet_t *h) { return h ? kHeader + 12 * (int64_t)h->nparam : 0; }
+
+int32_t bdisnet_step(const bdisnet_t *h) { return h ? h->step : 0; }
+
+bdis_status bdisnet_save(bdisnet_t *h, void *blob, int64_t bytes) {
+    if (!h) { seterr(g_net_err, "handle is NULL"); return BDIS_E_INVALID_ARG; }
+    const int64_t need = bdisnet_checkpoint_bytes(h);
+    if (!blob || bytes < need) { seterr(h->err, "checkpoint needs %lld bytes", (long long)need); return BDIS_E_INVALID_ARG; }
+    char *b = static_cast<char *>(blob);
+    const int32_t C = h->C;
+    const int64_t n = h->nparam, step = h->step;
+    memcpy(b, kMagic, 8);
+    memcpy(b + 8, &kVersion, 4);
+    memcpy(b + 12, &C, 4);
+    memcpy(b + 16, &n, 8);
+    memcpy(b + 24, &step, 8);
+    DevGuard dg(h->device);
+    NCHK(h, hipDeviceSynchronize());
+    NCHK(h, hipMemcpy(b + kHeader, h->w, n * 4, hipMemcpyDeviceToHost));
+    NCHK(h, hipMemcpy(b + kHeader + 4 * n, h->m, n * 4, hipMemcpyDeviceToHost));
+    NCHK(h, hipMemcpy(b + kHeader + 8 * n, h->v, n * 4, hipMemcpyDeviceToHost));
+    return BDIS_OK;
+}
+
+bdis_status bdisnet_load(bdisnet_t *h, const void *blob, int64_t bytes) {
+    if (!h) { seterr(g_net_err, "handle is NULL"); return BDIS_E_INVALID_ARG; }
+    const char *b = static_cast<const char *>(blob);
+    if (!b || bytes < kHeader) { seterr(h->err, "checkpoint too short"); return BDIS_E_INVALID_ARG; }
+    uint32_t ver;
+    int32_t C;
+    int64_t n, step;
+    memcpy(&ver, b + 8, 4);
+    memcpy(&C, b + 12, 4);
+    memcpy(&n, b + 16, 8);
+    memcpy(&step, b + 24, 8);
+    if (memcmp(b, kMagic, 8) != 0 || ver != kVersion) { seterr(h->err, "not a version-1 network checkpoint"); return BDIS_E_INVALID_ARG; }
+    if (C != h->C || n != h->nparam) {
+        seterr(h->err, "checkpoint of a %d-channel network (%lld parameters); this one has %d", C, (long long)n, h->C);
+        return BDIS_E_INVALID_ARG;
+    }
+    if (bytes < kHeader + 12 * n || step < 0 || step > INT32_MAX) { seterr(h->err, "checkpoint truncated or corrupt"); return BDIS_E_INVALID_ARG; }
+    for (int64_t i = 0; i < 3 * n; i++) {
+        float x;
+        memcpy(&x, b + kHeader + 4 * i, 4);
+        if (!std::isfinite(x) || (i >= 2 * n && x < 0.f)) { seterr(h->err, "checkpoint value %lld is invalid", (long long)i); return BDIS_E_INVALID_ARG; }
+    }
+    DevGuard dg(h->device);
+    NCHK(h, hipDeviceSynchronize());
+    NCHK(h, hipMemcpy(h->w, b + kHeader, n * 4, hipMemcpyHostToDevice));
+    NCHK(h, hipMemcpy(h->m, b + kHeader + 4 * n, n * 4, hipMemcpyHostToDevice));
+    NCHK(h, hipMemcpy(h->v, b + kHeader + 8 * n, n * 4, hipMemcpyHostToDevice));
+    h->step = (int)step;
     bdis_status st = pack_all(h, nullptr);
     if (st != BDIS_OK) return st;
     NCHK(h, hipDeviceSynchronize());
@@ -541,6 +612,7 @@ bdis_status bdisnet_adam_step(bdisnet_t *h, float lr, float beta1, float beta2, 
     hipLaunchKernelGGL(k_adam, dim3((unsigned)((h->nparam + 255) / 256)), dim3(256), 0, s, h->w, h->m, h->v, h->g,
                        h->nparam, lr, beta1, beta2, eps, c1, c2);
     NCHK(h, hipGetLastError());
+    h->step = step;
     return pack_all(h, s);
 }
 

@@ -34,11 +34,19 @@ def _lib():
         L.bdisnet_backward.argtypes = [vp, vp]
         L.bdisnet_adam_step.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float, i32, vp]
         L.bdisnet_debug_activation.argtypes = [vp, i32, vp, C.c_size_t]
+        L.bdisnet_checkpoint_bytes.argtypes = [vp]
+        L.bdisnet_checkpoint_bytes.restype = i64
+        L.bdisnet_save.argtypes = [vp, vp, i64]
+        L.bdisnet_load.argtypes = [vp, vp, i64]
+        L.bdisnet_step.argtypes = [vp]
+        L.bdisnet_step.restype = i32
+        L.bdis_set_net_weights.argtypes = [vp, vp, i64]
         L.bdisnet_last_error.argtypes = [vp]
         L.bdisnet_last_error.restype = C.c_char_p
         for n in ("bdisnet_create", "bdisnet_set_params", "bdisnet_get_params", "bdisnet_get_grads",
                   "bdisnet_forward", "bdisnet_loss", "bdisnet_set_output_grad", "bdisnet_backward",
-                  "bdisnet_adam_step", "bdisnet_debug_activation"):
+                  "bdisnet_adam_step", "bdisnet_debug_activation", "bdisnet_save", "bdisnet_load",
+                  "bdis_set_net_weights"):
             getattr(L, n).restype = C.c_int
         L._net_bound = True
     return L
@@ -145,6 +153,22 @@ class ProposalNet:
 
     def adam_step(self, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
         _check(_lib().bdisnet_adam_step(self._h, lr, beta1, beta2, eps, step, bdis._stream_ptr(stream)), self._h)
+
+    @property
+    def step(self) -> int:
+        """The last Adam step taken (0 after set_params)."""
+        return int(_lib().bdisnet_step(self._h))
+
+    def save_checkpoint(self) -> bytes:
+        """Weights, Adam moments and step as one blob (see bdisnet_save)."""
+        n = int(_lib().bdisnet_checkpoint_bytes(self._h))
+        buf = np.empty(n, np.uint8)
+        _check(_lib().bdisnet_save(self._h, buf.ctypes.data, n), self._h)
+        return buf.tobytes()
+
+    def load_checkpoint(self, blob: bytes):
+        a = np.frombuffer(blob, np.uint8)
+        _check(_lib().bdisnet_load(self._h, a.ctypes.data, a.size), self._h)
 
     def activation(self, layer, shape_nhw):
         """Input of `layer` from the last forward as float64 (bf16 values)."""

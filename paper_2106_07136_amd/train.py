@@ -102,9 +102,17 @@ def build_dataset(sizes, workers, chunk):
     return data
 
 
-def train(data, channels=32, epochs=6, batch=64, lr=2e-3, seed=0, conf_tol=1.0, log_every=500):
+def train(data, channels=32, epochs=6, batch=64, lr=2e-3, seed=0, conf_tol=1.0, log_every=500,
+          resume=None, stop_after=None, state_out=None):
     """data: list of (X, T, V) per image size; every step takes one batch of
-    one size, the sizes interleaved in proportion to their counts."""
+    one size, the sizes interleaved in proportion to their counts.
+
+    Resumable: `stop_after` ends the run after that many steps (counted from
+    the start); `state_out`, a dict, receives the state to resume from (the
+    network checkpoint with its Adam moments and step, the epoch, the
+    position in the epoch and the data-order generator's state at the start
+    of that epoch); `resume` takes such a state and continues the run as if
+    it had not stopped, bit for bit."""
     import torch
 
     from . import net
@@ -114,14 +122,28 @@ def train(data, channels=32, epochs=6, batch=64, lr=2e-3, seed=0, conf_tol=1.0, 
     per_epoch = [(k, j) for k, (X, _, _) in enumerate(data) for j in range(X.shape[0] // batch)]
     total = epochs * len(per_epoch)
     loss_buf = torch.empty((), dtype=torch.float32, device=data[0][0].device)
-    step = 0
-    hist = []
+    step, ep0, pos0, hist = 0, 0, 0, []
+    if resume is not None:
+        pn.load_checkpoint(resume["net"])
+        step, ep0, pos0 = int(resume["step"]), int(resume["epoch"]), int(resume["pos"])
+        hist = [tuple(h) for h in resume["hist"]]
+        g.set_state(torch.from_numpy(np.asarray(resume["rng"], np.uint8).copy()))
+        assert pn.step == step, "checkpoint step does not match the network's"
     t0 = time.time()
-    for ep in range(epochs):
+
+    def snapshot(ep, pos, rng):
+        if state_out is not None:
+            state_out.update(net=pn.save_checkpoint(), step=step, epoch=ep, pos=pos, rng=rng, hist=list(hist))
+
+    for ep in range(ep0, epochs):
+        rng_start = g.get_state().numpy().copy()
         perms = [torch.randperm(X.shape[0], generator=g).to(X.device) for (X, _, _) in data]
         order = torch.randperm(len(per_epoch), generator=g).tolist()
-        for o in order:
-            k, j = per_epoch[o]
+        for pos in range(pos0 if ep == ep0 else 0, len(order)):
+            if stop_after is not None and step >= stop_after:
+                snapshot(ep, pos, rng_start)
+                return pn, hist
+            k, j = per_epoch[order[pos]]
             X, T, V = data[k]
             idx = perms[k][j * batch:(j + 1) * batch]
             step += 1
@@ -135,7 +157,22 @@ def train(data, channels=32, epochs=6, batch=64, lr=2e-3, seed=0, conf_tol=1.0, 
                 lv = float(loss_buf.item())
                 hist.append((step, lv))
                 log(f"train: epoch {ep} step {step}/{total} loss {lv:.4f} lr {lr_t:.2e} ({time.time() - t0:.1f} s)")
+    snapshot(epochs, 0, g.get_state().numpy().copy())
     return pn, hist
+
+
+def save_state(path, state):
+    """A resumable training state (train's state_out) as an .npz of plain
+    arrays (no pickled objects)."""
+    np.savez(path, net=np.frombuffer(state["net"], np.uint8), step=np.int64(state["step"]),
+             epoch=np.int64(state["epoch"]), pos=np.int64(state["pos"]), rng=np.asarray(state["rng"], np.uint8),
+             hist=np.array(json.dumps(state["hist"])))
+
+
+def load_state(path):
+    z = np.load(path, allow_pickle=False)
+    return {"net": z["net"].tobytes(), "step": int(z["step"]), "epoch": int(z["epoch"]), "pos": int(z["pos"]),
+            "rng": z["rng"], "hist": json.loads(str(z["hist"]))}
 
 
 def save(path, pn, meta):
@@ -172,11 +209,24 @@ def main():
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--chunk", type=int, default=256)
     ap.add_argument("--out", required=True, help="output path; {C} is replaced by the width")
+    ap.add_argument("--state", default=None,
+                    help="resumable training state path ({C} replaced); resumed from when it exists, "
+                         "written when the run stops")
+    ap.add_argument("--stop-after", type=int, default=None, help="stop after this many steps (then resume)")
     a = ap.parse_args()
     sizes = parse_sizes(a.sizes)
     data = build_dataset(sizes, a.workers, a.chunk)
     for C in [int(c) for c in a.channels.split(",")]:
-        pn, hist = train(data, C, a.epochs, a.batch, a.lr, conf_tol=a.conf_tol)
+        spath = a.state.replace("{C}", str(C)) if a.state else None
+        resume = load_state(spath) if spath and os.path.exists(spath) else None
+        st = {}
+        pn, hist = train(data, C, a.epochs, a.batch, a.lr, conf_tol=a.conf_tol, resume=resume,
+                         stop_after=a.stop_after, state_out=st)
+        if spath:
+            save_state(spath, st)
+            log(f"train: state saved to {spath} at step {st['step']}")
+        if a.stop_after is not None and st["epoch"] < a.epochs:
+            continue
         meta = {"sizes": sizes, "epochs": a.epochs, "batch": a.batch, "lr": a.lr, "conf_tol": a.conf_tol,
                 "loss_history": hist}
         path = a.out.replace("{C}", str(C))

@@ -109,3 +109,116 @@ def test_loss_and_adam_match_oracle(torch_cuda):
     w1 = pn.get_params().astype(np.float64)
     exp, _, _ = onet.adam(flat.astype(np.float64), g.astype(np.float64), 0.0, 0.0, 1, lr=1e-2)
     assert np.max(np.abs(w1 - exp)) <= 1e-6
+
+
+def _train_steps(torch, pn, X, T, V, steps, first=1):
+    for s in range(first, first + steps):
+        pn.forward(X)
+        pn.loss(T, V, delta=1.0, conf_tol=1.0, conf_weight=0.1)
+        pn.backward()
+        pn.adam_step(1e-3 * (1.0 + 0.1 * s), s)
+    torch.cuda.synchronize()
+
+
+def _rand_batch(torch, N=4, H=12, W=16, seed=3):
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    X = (torch.rand((N, H, W, 16), generator=g) * 2 - 1).to(torch.bfloat16).cuda().contiguous()
+    T = (torch.rand((N, H, W), generator=g) * 4).cuda().contiguous()
+    V = (torch.rand((N, H, W), generator=g) > 0.2).to(torch.uint8).cuda().contiguous()
+    return X, T, V
+
+
+def _parse_checkpoint(blob):
+    """The checkpoint layout include/bdis.h documents."""
+    assert blob[:8] == b"BDISNET\0"
+    ver, C = np.frombuffer(blob[8:16], np.int32)
+    n, step = np.frombuffer(blob[16:32], np.int64)
+    arr = np.frombuffer(blob[32:], np.float32)
+    assert arr.size == 3 * n
+    return dict(version=int(ver), channels=int(C), n=int(n), step=int(step), w=arr[:n], m=arr[n:2 * n],
+                v=arr[2 * n:])
+
+
+def test_checkpoint_resume_is_bitwise(torch_cuda):
+    """Six Adam steps in one go against three, a checkpoint, a new network
+    loaded from it and three more: weights, both moments and the step count
+    equal bit for bit (forward, backward and Adam are deterministic)."""
+    from paper_2106_07136_amd import net
+    torch = torch_cuda
+    X, T, V = _rand_batch(torch)
+    flat = net.init_params(32, 1)
+    a = net.ProposalNet(32)
+    a.set_params(flat)
+    _train_steps(torch, a, X, T, V, 6)
+    b = net.ProposalNet(32)
+    b.set_params(flat)
+    _train_steps(torch, b, X, T, V, 3)
+    blob = b.save_checkpoint()
+    ck = _parse_checkpoint(blob)
+    assert (ck["version"], ck["channels"], ck["n"], ck["step"]) == (1, 32, b.nparam, 3)
+    np.testing.assert_array_equal(ck["w"], b.get_params())
+    assert np.all(ck["v"] >= 0) and np.any(ck["m"] != 0)
+    b.close()
+    c = net.ProposalNet(32)
+    c.load_checkpoint(blob)
+    assert c.step == 3
+    _train_steps(torch, c, X, T, V, 3, first=4)
+    assert a.save_checkpoint() == c.save_checkpoint()
+
+
+def test_training_run_resumes_bitwise(torch_cuda):
+    """train.train stopped after 5 of 9 steps (mid-epoch) and resumed from
+    its state ends where the uninterrupted run ends, bit for bit; the state
+    survives a round trip through its .npz file."""
+    import os
+    import tempfile
+
+    from paper_2106_07136_amd import train
+    torch = torch_cuda
+    X, T, V = _rand_batch(torch, N=24, seed=4)
+    data = [(X, T, V)]
+    full = {}
+    train.train(data, channels=32, epochs=3, batch=8, lr=2e-3, log_every=100, state_out=full)
+    part = {}
+    train.train(data, channels=32, epochs=3, batch=8, lr=2e-3, log_every=100, stop_after=5, state_out=part)
+    assert part["step"] == 5 and part["epoch"] == 1 and part["pos"] == 2
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "state.npz")
+        train.save_state(path, part)
+        resumed_from = train.load_state(path)
+    rest = {}
+    train.train(data, channels=32, epochs=3, batch=8, lr=2e-3, log_every=100, resume=resumed_from, state_out=rest)
+    assert rest["step"] == full["step"] == 9
+    assert rest["net"] == full["net"]
+
+
+def test_set_net_weights_equals_attached_network(torch_cuda):
+    """A handle that loads a checkpoint into a network of its own computes
+    the same learned-init disparity, bit for bit, as one given the network
+    object; wrong checkpoints are refused."""
+    from paper_2106_07136_amd import bdis, net, synth
+    torch = torch_cuda
+    pair = synth.make_pair(640, 480, 64.0, 52)
+    L, R = torch.from_numpy(pair.left).cuda(), torch.from_numpy(pair.right).cuda()
+    pn = net.ProposalNet(32)
+    pn.set_params(net.init_params(32, 7))
+    gp = bdis.Params(levels=5, init=1, learned_iters=8)
+    h1 = bdis.Bdis(gp)
+    h1.set_net(pn)
+    d1 = h1.compute(L, R).cpu().numpy()
+    h2 = bdis.Bdis(gp)
+    h2.set_net_weights(pn.save_checkpoint())
+    d2 = h2.compute(L, R).cpu().numpy()
+    np.testing.assert_array_equal(d1.view(np.uint32), d2.view(np.uint32))
+    bad = bytearray(pn.save_checkpoint())
+    bad[0:1] = b"X"
+    with pytest.raises(bdis.BdisError) as e:
+        h2.set_net_weights(bytes(bad))
+    assert e.value.status == bdis.E_INVALID_ARG
+    p48 = net.ProposalNet(48)
+    with pytest.raises(bdis.BdisError) as e:
+        p48.load_checkpoint(pn.save_checkpoint())
+    assert e.value.status == bdis.E_INVALID_ARG
+    # the owned network stays usable after the refusals
+    d3 = h2.compute(L, R).cpu().numpy()
+    np.testing.assert_array_equal(d1.view(np.uint32), d3.view(np.uint32))

@@ -138,3 +138,58 @@ def test_net_input_channels():
     # R(x - d) = L(x) - 3 d + 6: |L - R(x - d)| = |3 d - 6| away from the left border
     for d in range(4):
         np.testing.assert_allclose(x[:, d:, 2 + d], abs(3 * d - 6) / 64)
+
+
+def test_oracle_training_resumes_bitwise():
+    """The oracle's training step (forward, loss, backward, Adam) run for
+    3 + 3 steps with the state written to the checkpoint layout that
+    include/bdis.h documents after step 3 and read back from it (FP32, as the
+    GPU keeps it) ends where 6 uninterrupted steps end when the run keeps
+    FP32 state too: resuming loses nothing."""
+    import struct
+
+    rng = np.random.default_rng(9)
+    C = 16
+    dims = [(16, C), (C, C), (C, C), (C, 2)]
+    layers = [(rng.normal(0, np.sqrt(2 / (9 * ci)), (3, 3, ci, co)).astype(np.float32).astype(np.float64),
+               np.zeros(co)) for ci, co in dims]
+    x = onet.bf16(rng.normal(0, 1, (2, 6, 7, 16)))
+    t = rng.uniform(0, 4, (2, 6, 7))
+    valid = rng.uniform(size=(2, 6, 7)) > 0.2
+    flat = lambda ls: np.concatenate([np.concatenate([w.ravel(), b.ravel()]) for w, b in ls])
+
+    def unflat(v):
+        out, o = [], 0
+        for ci, co in dims:
+            w = v[o:o + 9 * ci * co].reshape(3, 3, ci, co)
+            o += 9 * ci * co
+            out.append((w, v[o:o + co]))
+            o += co
+        return out
+
+    def steps(w, m, v, first, count):
+        for s in range(first, first + count):
+            ls = [(onet.bf16(a), b) for a, b in unflat(w)]
+            out, acts = onet.Net(ls).forward(x)
+            _, g = onet.loss_and_grad(out, t, valid)
+            grads = onet.Net(ls).backward(acts, g)
+            gv = flat(grads)
+            w, m, v = onet.adam(w, gv, m, v, s, 1e-3)
+            w, m, v = (a.astype(np.float32).astype(np.float64) for a in (w, m, v))
+        return w, m, v
+
+    w0 = flat(layers)
+    z = np.zeros_like(w0)
+    wa, ma, va = steps(w0, z, z, 1, 6)
+    wb, mb, vb = steps(w0, z, z, 1, 3)
+    n = w0.size
+    blob = b"BDISNET\0" + struct.pack("<IiqQ", 1, C, n, 3) + \
+        np.concatenate([wb, mb, vb]).astype("<f4").tobytes()
+    assert len(blob) == 32 + 12 * n
+    ver, ch, nn, step = struct.unpack("<IiqQ", blob[8:32])
+    arr = np.frombuffer(blob[32:], "<f4").astype(np.float64)
+    assert (ver, ch, nn, step) == (1, C, n, 3)
+    wc, mc, vc = steps(arr[:n], arr[n:2 * n], arr[2 * n:], step + 1, 3)
+    np.testing.assert_array_equal(wc, wa)
+    np.testing.assert_array_equal(mc, ma)
+    np.testing.assert_array_equal(vc, va)
