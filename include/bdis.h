@@ -141,8 +141,7 @@ BDIS_API bdis_status bdis_set_params(bdis_t *h, const bdis_params *p);
 /* Grows the workspace so pairs up to width x height (and batches of up to
  * n_pairs such pairs) need no allocation inside bdis_compute*, for the
  * handle's current parameters (with init = learned, the network's level,
- * keep mask and activations included; reserve after bdis_set_net for the
- * network's channel count, else 48 channels are assumed). */
+ * keep mask and output included). */
 BDIS_API bdis_status bdis_reserve(bdis_t *h, int32_t width, int32_t height, int32_t n_pairs);
 
 /* Disparity of one rectified pair, coarse to fine over the whole pyramid
@@ -239,6 +238,8 @@ BDIS_API bdis_status bdis_set_tuning(bdis_t *h, int32_t n, const int32_t *max_wi
  *   stage 7: learned init only: the gate's keep mask at the injection level
  *            (uint8, W_l x H_l, level = learned_fine_levels; 1 = the
  *            network's proposal was kept, 0 = the plain field was used)
+ *   stage 8: learned init only: the network's output at the 1/16 level
+ *            (FP32, H_4 x W_4 x 2: disparity, confidence logit; level = 4)
  * Stages 0-3, 5 and 6 are in the handle's arithmetic type (double with
  * precision 0, float with precision 1).  Pyramid values hold validity in the
  * sign bit (negative or -0 = invalid).

@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbdis.so")
 
 OK, E_INVALID_ARG, E_NO_DEVICE, E_OOM, E_HIP, E_UNSUPPORTED, E_STATE = 0, -1, -2, -3, -4, -5, -6
-STAGE_PYR_L, STAGE_PYR_R, STAGE_U, STAGE_W, STAGE_STATUS, STAGE_FIELD, STAGE_U0, STAGE_KEEP = range(8)
+STAGE_PYR_L, STAGE_PYR_R, STAGE_U, STAGE_W, STAGE_STATUS, STAGE_FIELD, STAGE_U0, STAGE_KEEP, STAGE_NET = range(9)
 
 
 class BdisError(RuntimeError):
@@ -296,6 +296,13 @@ class Bdis:
         """Host numpy copy of one stage tap of the last single-pair compute."""
         import numpy as np
         info = plan(self.params, *self._last_shape)
+        if stage == STAGE_NET:
+            w, h = self._last_shape
+            for _ in range(level):
+                w, h = (w + 1) // 2, (h + 1) // 2
+            a = np.empty((h, w, 2), np.float32)
+            _check(lib().bdis_debug_stage(self._h, stage, level, a.ctypes.data, a.nbytes), self._h)
+            return a
         if stage in (STAGE_PYR_L, STAGE_PYR_R, STAGE_FIELD, STAGE_KEEP):
             shape = (info["height"][level], info["width"][level])
         else:

@@ -150,8 +150,8 @@ static_assert(sizeof(GateJob) == 3 * 8 + 8 * 4, "GateJob must have no padding");
 // within the same kernel-argument size); larger sets are split.
 constexpr int kMaxJobs = 24;
 template <typename Job> struct PackCap { static constexpr int value = kMaxJobs; };
-template <> struct PackCap<NetInJob> { static constexpr int value = 62; };
-template <> struct PackCap<GateJob> { static constexpr int value = 62; };
+template <> struct PackCap<NetInJob> { static constexpr int value = 96; };
+template <> struct PackCap<GateJob> { static constexpr int value = 70; };
 template <typename Job>
 struct JobPack {
     int n;

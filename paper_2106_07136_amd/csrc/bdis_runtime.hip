@@ -211,20 +211,11 @@ void carve(char *base, const Geo &g, size_t esz, PairWs &w, int inj = 0) {
     if (inj > 0) w.keep = (uint8_t *)take((size_t)g.W[inj] * g.H[inj]);
 }
 
-// Same-size pairs whose network input, hidden activations and output share
-// one contiguous batch.
+// Same-size pairs whose network outputs share one contiguous batch.
 struct NetGroup {
     int W4, H4;
     std::vector<int> pairs;  // indices into the call's pair list
-    uint16_t *x = nullptr, *a[3] = {};
     float *out = nullptr;
-};
-
-// Kernel-argument payload of a network forward launch.
-struct NetLaunch {
-    uint16_t *x, *a1, *a2, *a3;
-    float *out;
-    int n, H, W, pad_;
 };
 
 struct PairIn {
@@ -384,7 +375,7 @@ bdis_status ensure_ws(bdis_t *h, size_t bytes) {
 // A launch: kernel kind, template selectors and its jobs (passed by value).
 // K_FORK / K_JOIN launch nothing: work after a fork runs on the side stream
 // (lane 1) until the join makes the main stream wait for it.
-enum Kind { K_PYR2, K_LK, K_DENSE, K_NETIN, K_NET, K_GATE, K_FORK, K_JOIN };
+enum Kind { K_PYR2, K_LK, K_DENSE, K_NETIN, K_NETF, K_GATE, K_FORK, K_JOIN };
 struct Launch {
     Kind kind;
     int level;
@@ -512,16 +503,17 @@ void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<Launch> &l
     KParams kp0 = make_kparams(h->prm, h->prm.patch);
     plan_pyramid(ls, pairs, Lpmax, f64, kp0);
     if (lrn) {
-        std::vector<NetInJob> in;
+        std::vector<bdisnet::FusedJob> fused;
         std::vector<GateJob> gate;
         for (auto &p : pairs) {
             const NetGroup &G = h->groups[p.group];
-            NetInJob j{};
+            bdisnet::FusedJob j{};
             j.L = p.ws.pyr_l[kNetLevel];
             j.R = p.ws.pyr_r[kNetLevel];
-            j.x = G.x + (size_t)p.gindex * G.W4 * G.H4 * kNetIn;
+            j.out = G.out + (size_t)p.gindex * G.W4 * G.H4 * 2;
             j.W = G.W4; j.H = G.H4;
-            in.push_back(j);
+            j.tiles_x = bdisnet::fused_tiles_x(G.W4);
+            fused.push_back(j);
             GateJob q{};
             q.net = G.out + (size_t)p.gindex * G.W4 * G.H4 * 2;
             q.U = p.ws.U[inj];
@@ -539,13 +531,21 @@ void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<Launch> &l
         // level's densification, the first launch that reads the gate
         ls.push_back(Launch{K_FORK, 0, 0, false, f64, 0, kp0, {}});
         const size_t first_side = ls.size();
-        append(ls, K_NETIN, kNetLevel, 0, false, f64, in, kp0,
-               [](const NetInJob &j) { return (j.W * j.H + kBlock - 1) / kBlock; });
-        for (const NetGroup &G : h->groups) {
-            Launch L{K_NET, kNetLevel, 0, false, f64, 0, kp0, {}};
-            NetLaunch nl{G.x, G.a[0], G.a[1], G.a[2], G.out, (int)G.pairs.size(), G.H4, G.W4, 0};
-            L.pack.resize(sizeof nl);
-            memcpy(L.pack.data(), &nl, sizeof nl);
+        // the network: input channels and the four layers in one launch per
+        // pack of up to kFusedCap pairs
+        for (size_t s0 = 0; s0 < fused.size(); s0 += bdisnet::kFusedCap) {
+            bdisnet::FusedPack pk;
+            memset(&pk, 0, sizeof pk);
+            int blocks = 0;
+            for (size_t i = s0; i < fused.size() && i < s0 + bdisnet::kFusedCap; i++) {
+                pk.j[pk.n] = fused[i];
+                pk.j[pk.n].block0 = blocks;
+                blocks += bdisnet::fused_blocks(fused[i].W, fused[i].H);
+                pk.n++;
+            }
+            Launch L{K_NETF, kNetLevel, 0, false, f64, blocks, kp0, {}};
+            L.pack.resize(sizeof pk);
+            memcpy(L.pack.data(), &pk, sizeof pk);
             ls.push_back(std::move(L));
         }
         append(ls, K_GATE, inj, 0, false, f64, gate, kp0,
@@ -633,6 +633,7 @@ static_assert(sizeof(JobPack<PyrJob>) + sizeof(KParams) <= 4000, "pyramid job pa
 static_assert(sizeof(JobPack<LkJob>) + sizeof(KParams) <= 4000, "LK job pack too large");
 static_assert(sizeof(JobPack<DenseJob>) + sizeof(KParams) <= 4000, "densify job pack too large");
 static_assert(sizeof(JobPack<NetInJob>) <= 4000 && sizeof(JobPack<GateJob>) <= 4000, "job pack too large");
+static_assert(sizeof(bdisnet::FusedPack) <= 4000, "fused network job pack too large");
 
 template <typename Job>
 const JobPack<Job> &pack_of(const Launch &L) {
@@ -672,11 +673,10 @@ void launch_one(bdis_t *h, const Launch &L, hipStream_t s) {
     case K_NETIN:
         hipLaunchKernelGGL(k_net_input<T>, dim3(L.blocks), dim3(kBlock), 0, s, pack_of<NetInJob>(L));
         break;
-    case K_NET: {
-        NetLaunch nl;
-        memcpy(&nl, L.pack.data(), sizeof nl);
-        uint16_t *acts[4] = {nl.x, nl.a1, nl.a2, nl.a3};
-        (void)bdisnet::forward_internal(h->net, nl.x, nl.n, nl.H, nl.W, nl.out, acts, s);
+    case K_NETF: {
+        bdisnet::FusedPack pk;
+        memcpy(&pk, L.pack.data(), sizeof pk);
+        (void)bdisnet::forward_fused(h->net, pk, L.blocks, L.f64, s);
         break;
     }
     case K_GATE:
@@ -718,7 +718,7 @@ std::string launch_name(const Launch &L) {
     case K_LK: snprintf(buf, sizeof buf, "lk_%s_p%d_l%d", t, L.patch, L.level); break;
     case K_DENSE: snprintf(buf, sizeof buf, "dense_%s_l%d", t, L.level); break;
     case K_NETIN: snprintf(buf, sizeof buf, "netin_%s", t); break;
-    case K_NET: snprintf(buf, sizeof buf, "net_forward"); break;
+    case K_NETF: snprintf(buf, sizeof buf, "net_forward"); break;
     default: snprintf(buf, sizeof buf, "gate_%s", t); break;
     }
     return buf;
@@ -1093,7 +1093,6 @@ bdis_status run(bdis_t *h, std::vector<PairIn> &pairs, hipStream_t s, int mode =
     h->groups.clear();
     size_t net_bytes = 0;
     if (lrn) {
-        const int C = bdisnet::channels(h->net);
         for (size_t i = 0; i < pairs.size(); i++) {
             PairIn &p = pairs[i];
             int gi = -1;
@@ -1112,7 +1111,7 @@ bdis_status run(bdis_t *h, std::vector<PairIn> &pairs, hipStream_t s, int mode =
         }
         for (const NetGroup &G : h->groups) {
             size_t px = (size_t)G.pairs.size() * G.W4 * G.H4;
-            net_bytes += align_up(px * kNetIn * 2) + 3 * align_up(px * C * 2) + align_up(px * 2 * 4);
+            net_bytes += align_up(px * 2 * 4);
         }
     }
     char *base = fixed_ws;
@@ -1133,15 +1132,8 @@ bdis_status run(bdis_t *h, std::vector<PairIn> &pairs, hipStream_t s, int mode =
         off += align_up(pair_ws_bytes(p.g, esz, inj));
     }
     if (lrn) {
-        const int C = bdisnet::channels(h->net);
         for (NetGroup &G : h->groups) {
             size_t px = (size_t)G.pairs.size() * G.W4 * G.H4;
-            G.x = (uint16_t *)(base + off);
-            off += align_up(px * kNetIn * 2);
-            for (int a = 0; a < 3; a++) {
-                G.a[a] = (uint16_t *)(base + off);
-                off += align_up(px * C * 2);
-            }
             G.out = (float *)(base + off);
             off += align_up(px * 2 * 4);
         }
@@ -1293,9 +1285,7 @@ bdis_status bdis_reserve(bdis_t *h, int32_t width, int32_t height, int32_t n_pai
     if (lrn) {
         int w4 = width, h4 = height;
         for (int l = 0; l < kNetLevel; l++) { w4 = (w4 + 1) / 2; h4 = (h4 + 1) / 2; }
-        const size_t C = h->net ? (size_t)bdisnet::channels(h->net) : 48;
-        const size_t px = (size_t)n_pairs * w4 * h4;
-        net = align_up(px * kNetIn * 2) + 3 * align_up(px * C * 2) + align_up(px * 2 * 4);
+        net = align_up((size_t)n_pairs * w4 * h4 * 2 * 4);
     }
     DeviceGuard dg(h->device);
     return ensure_ws(h, worst * (size_t)n_pairs + net);
@@ -1512,7 +1502,10 @@ bdis_status bdis_debug_stage(bdis_t *h, int32_t stage, int32_t level, void *dst,
     if (!h) { set_err(g_thread_err, "handle is NULL"); return BDIS_E_INVALID_ARG; }
     if (!h->have_last) { set_err(h->err, "no single-pair compute to inspect"); return BDIS_E_STATE; }
     const PairIn &p = h->last;
-    if (!dst || level < 0 || level >= p.g.L) { set_err(h->err, "bad level or dst"); return BDIS_E_INVALID_ARG; }
+    if (!dst || level < 0 || level >= (stage == 8 ? p.g.Lp : p.g.L)) {
+        set_err(h->err, "bad level or dst");
+        return BDIS_E_INVALID_ARG;
+    }
     const size_t esz = esize(h->prm);
     size_t px = (size_t)p.g.W[level] * p.g.H[level] * esz, np = (size_t)p.g.nx[level] * p.g.ny[level];
     const void *src = nullptr;
@@ -1528,6 +1521,11 @@ bdis_status bdis_debug_stage(bdis_t *h, int32_t stage, int32_t level, void *dst,
     case 7:
         if (level == h->prm.learned_fine_levels) src = p.ws.keep;
         need = (size_t)p.g.W[level] * p.g.H[level];
+        break;
+    case 8:
+        if (learned(h) && level == kNetLevel && p.group >= 0 && p.group < (int)h->groups.size())
+            src = h->groups[p.group].out + (size_t)p.gindex * p.g.W[kNetLevel] * p.g.H[kNetLevel] * 2;
+        need = (size_t)p.g.W[kNetLevel] * p.g.H[kNetLevel] * 2 * sizeof(float);
         break;
     default: set_err(h->err, "unknown stage %d", stage); return BDIS_E_INVALID_ARG;
     }

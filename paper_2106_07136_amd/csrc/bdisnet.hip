@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "bdis.h"
+#include "bdisnet_fused.hpp"
 #include "bdisnet_internal.hpp"
 #include "bdisnet_kernels.hpp"
 
@@ -42,6 +43,7 @@ struct bdisnet_ctx {
     long long nparam = 0;
     float *w = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;  // device, nparam each
     uint16_t *ffrag[kLayers] = {}, *dfrag[kLayers] = {};
+    uint16_t *f32frag[kLayers] = {};  // B fragments of the fused forward (16x16x32 MFMA)
     // training buffers for the last forward
     size_t cap_m = 0;
     uint16_t *act[kLayers] = {};  // act[0] = copy of the input, act[l] = input of layer l
@@ -216,11 +218,16 @@ __global__ void k_adam(float *__restrict__ w, float *__restrict__ m, float *__re
 
 // ---------------------------------------------------------------- helpers
 
+size_t frag32_elems(int CI, int CO) { return (size_t)((9 * CI + 31) / 32) * ((CO + 15) / 16) * 64 * 8; }
+
 bdis_status pack_all(bdisnet_t *h, hipStream_t s) {
     for (int l = 0; l < kLayers; l++) {
         const int nf = 9 * h->CI[l] * cop(h->CO[l]);
         hipLaunchKernelGGL(k_pack, dim3((nf + 255) / 256), dim3(256), 0, s, h->w + h->w_off[l], h->CI[l], h->CO[l],
                            h->ffrag[l], h->dfrag[l]);
+        const int n32 = (int)frag32_elems(h->CI[l], h->CO[l]);
+        hipLaunchKernelGGL(k_pack32, dim3((n32 + 255) / 256), dim3(256), 0, s, h->w + h->w_off[l], h->CI[l],
+                           h->CO[l], h->f32frag[l]);
     }
     NCHK(h, hipGetLastError());
     return BDIS_OK;
@@ -338,6 +345,26 @@ size_t act_bytes(const bdisnet_t *h, size_t M) {  // bytes of hidden activations
     return M * (size_t)h->C * 2;
 }
 
+template <typename T, int C>
+void launch_fused(bdisnet_t *h, const FusedPack &pk, int blocks, hipStream_t s) {
+    const size_t lds = (size_t)(fused_x_elems<C>() + fused_y_elems<C>()) * sizeof(uint16_t);
+    hipLaunchKernelGGL((k_net_fused<T, C>), dim3(blocks), dim3(kBlock), lds, s, pk, h->f32frag[0], h->f32frag[1],
+                       h->f32frag[2], h->f32frag[3], h->w + h->b_off[0], h->w + h->b_off[1], h->w + h->b_off[2],
+                       h->w + h->b_off[3]);
+}
+
+bdis_status forward_fused(bdisnet_t *h, const FusedPack &pk, int blocks, bool f64, hipStream_t s) {
+    if (blocks <= 0) return BDIS_OK;
+    if (h->C == 32) {
+        if (f64) launch_fused<double, 32>(h, pk, blocks, s);
+        else launch_fused<float, 32>(h, pk, blocks, s);
+    } else {
+        if (f64) launch_fused<double, 48>(h, pk, blocks, s);
+        else launch_fused<float, 48>(h, pk, blocks, s);
+    }
+    return hipGetLastError() == hipSuccess ? BDIS_OK : BDIS_E_HIP;
+}
+
 int channels(const bdisnet_t *h) { return h->C; }
 int device_of(const bdisnet_t *h) { return h->device; }
 
@@ -383,7 +410,8 @@ bdis_status bdisnet_create(int32_t channels, int device, bdisnet_t **out) {
               hipMalloc(&h->v, off * 4) == hipSuccess && hipMalloc(&h->g, off * 4) == hipSuccess;
     for (int l = 0; ok && l < kLayers; l++) {
         size_t nf = 9ull * ci[l] * cop(co[l]);
-        ok = hipMalloc(&h->ffrag[l], nf * 2) == hipSuccess && hipMalloc(&h->dfrag[l], nf * 2) == hipSuccess;
+        ok = hipMalloc(&h->ffrag[l], nf * 2) == hipSuccess && hipMalloc(&h->dfrag[l], nf * 2) == hipSuccess &&
+             hipMalloc(&h->f32frag[l], frag32_elems(ci[l], co[l]) * 2) == hipSuccess;
     }
     if (ok) {
         // partials of the widest weight gradient for up to 4096 chunks
@@ -416,7 +444,7 @@ void bdisnet_destroy(bdisnet_t *h) {
             if (p) (void)hipFree(p);
         if (h->cnt) (void)hipFree(h->cnt);
         for (int l = 0; l < kLayers; l++) {
-            for (uint16_t *p : {h->ffrag[l], h->dfrag[l], h->act[l], h->gz[l]})
+            for (uint16_t *p : {h->ffrag[l], h->dfrag[l], h->f32frag[l], h->act[l], h->gz[l]})
                 if (p) (void)hipFree(p);
         }
     }

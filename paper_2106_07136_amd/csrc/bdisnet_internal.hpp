@@ -18,3 +18,31 @@ int channels(const bdisnet_t *h);
 int device_of(const bdisnet_t *h);
 
 }  // namespace bdisnet
+
+namespace bdisnet {
+
+// The network's inference for the stereo path in one launch (input channels
+// and the four layers, per spatial tile): one job per pair.
+struct FusedJob {
+    const void *L, *R;  // the pair's 1/16 pyramid level (arithmetic type, sign bit = invalid)
+    float *out;         // network output, H x W x 2 FP32 (disparity, confidence logit)
+    int W, H;           // size of the 1/16 level
+    int tiles_x;        // output tiles per row
+    int block0;         // first block of this job in its launch
+};
+static_assert(sizeof(FusedJob) == 3 * 8 + 4 * 4, "FusedJob must have no padding");
+constexpr int kFusedCap = 96;
+struct FusedPack {
+    int n;
+    int pad_;
+    FusedJob j[kFusedCap];
+};
+// Output tile of the fused forward, and its blocks for one W x H image.
+constexpr int kFTX = 16, kFTY = 8;
+inline int fused_tiles_x(int W) { return (W + kFTX - 1) / kFTX; }
+inline int fused_blocks(int W, int H) { return fused_tiles_x(W) * ((H + kFTY - 1) / kFTY); }
+// Enqueues the fused forward of the jobs of pk (`blocks` in all) on s;
+// f64: the pyramid holds doubles (else floats).
+bdis_status forward_fused(bdisnet_t *h, const FusedPack &pk, int blocks, bool f64, hipStream_t s);
+
+}  // namespace bdisnet

@@ -261,3 +261,39 @@ def test_training_reduces_loss(torch_cuda):
     assert len(losses) == 40 and all(np.isfinite(losses))
     print(f"loss {losses[0]:.4f} -> {np.mean(losses[-5:]):.4f}", flush=True)
     assert np.mean(losses[-5:]) < 0.8 * losses[0]
+
+
+@pytest.mark.parametrize("C,W,H,dmax,seed", [(32, 640, 480, 64.0, 38), (48, 1920, 1080, 192.0, 39)])
+def test_fused_forward_matches_oracle(torch_cuda, ref, C, W, H, dmax, seed):
+    """The stereo path's network launch (input channels and the four layers
+    in one kernel, 16x16x32 matrix-core products, tiles with a 4-pixel halo)
+    against the oracle's chain: its pyramid, input channels and FP64 network
+    with bfloat16 weights and activations.  A 120x68 level (1920x1080) has
+    partial tiles on both axes.  Differences: FP32 summation order, and a
+    bfloat16 activation now and then rounded the other way, carried forward."""
+    from paper_2106_07136_amd import bdis, net
+    rng = np.random.default_rng(seed)
+    layers = net.unflatten(net.init_params(C, seed).astype(np.float64), C)
+    layers = [(w * (10.0 if i == 3 else 1.0), rng.normal(0, 0.1, b.shape)) for i, (w, b) in enumerate(layers)]
+    flat = net.flatten(layers)
+    pn = net.ProposalNet(C)
+    pn.set_params(flat)
+    pair = synth.make_pair(W, H, dmax, seed)
+    L, R = _gpu(torch_cuda, pair)
+    gp = bdis.Params(levels=0, max_disparity=dmax, init=1, learned_iters=8)
+    h = bdis.Bdis(gp)
+    h.set_net(pn)
+    h.compute(L, R)
+    got = h.debug_stage(bdis.STAGE_NET, 4).astype(np.float64)
+    ol = [(onet.bf16(w), np.float32(b).astype(np.float64)) for w, b in net.unflatten(flat.astype(np.float64), C)]
+    levels = ref.num_levels(W, H, 8, 1 + int(np.ceil(np.log2(dmax / 4))))
+    _, tr = ref.compute(pair.left, pair.right, ref.Params(levels=max(levels, 5)), trace=True)
+    x = onet.bf16(onet.net_input(tr[4]["pyr_l"], tr[4]["pyr_r"]))[None]
+    exp, _ = onet.Net(ol).forward(x)
+    exp = exp[0]
+    assert got.shape == exp.shape
+    rel = np.linalg.norm(got - exp) / np.linalg.norm(exp)
+    close = (np.abs(got - exp) <= 1e-2 * (np.abs(exp) + 1.0)).mean()
+    print(f"fused forward C={C} {W}x{H}: relative L2 {rel:.2e}, within 1e-2 {close:.5f}", flush=True)
+    assert np.isfinite(got).all()
+    assert rel <= 5e-3 and close >= 0.999
