@@ -34,7 +34,7 @@ struct KParams {
     int iters;           // LK iterations, no early exit
     int window;          // posterior window samples (odd)
     double window_step;  // spacing of the samples, level px
-    double tau;          // 2 sigma_r^2 s^2, eq. (4)
+    double inv_tau;      // 1 / (2 sigma_r^2 s^2), eq. (4)
     int min_valid;       // gamma gate: kept iff valid count >= min_valid
     int fusion;          // 0 Bayesian, 1 DIS eq. (2)
     int vlo, vhi;        // level-0 validity band
@@ -1160,6 +1160,12 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
             constexpr bool WBATCH = MERGE && P <= 12;
             // WN: compile-time bound on the window count (kp.window <= WN),
             // so that only the sums of samples that exist are reduced
+            // waves whose patch rows are all left-valid (the common case)
+            // skip the mask in the window sums; others apply it as a factor
+            const bool allv = __all((int)(vmask == (1u << P) - 1u)) != 0;
+            T mv[P];
+#pragma unroll
+            for (int c = 0; c < P; c++) mv[c] = ((vmask >> c) & 1u) ? T(1) : T(0);
             auto window_post = [&]() -> T {
                 // With WBATCH the runs R[clamp(xi0 + c, 0, W-1)], c = 0..P,
                 // of every sample are read before any is used: one LDS round
@@ -1216,14 +1222,26 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
                         }
                         const T omf = T(1) - uf;
                         // two interleaved chains per sum: half the dependent
-                        // adds (one wave per SIMD at the small levels)
+                        // adds (one wave per SIMD at the small levels).  The
+                        // left-valid mask enters as a 0/1 factor of the
+                        // residual (the same bits as selecting it), and not
+                        // at all in waves whose rows are all valid.
                         T s0 = 0, s1 = 0, e0 = 0, e1 = 0;
+                        if (allv) {
 #pragma unroll
-                        for (int c = 0; c < P; c++) {
-                            const T d = omf * v[c] + uf * v[c + 1];
-                            const T q = ((vmask >> c) & 1u) ? d - Tv[c] : T(0);
-                            if (c & 1) { s1 += q; e1 += q * q; }
-                            else { s0 += q; e0 += q * q; }
+                            for (int c = 0; c < P; c++) {
+                                const T q = (omf * v[c] + uf * v[c + 1]) - Tv[c];
+                                if (c & 1) { s1 += q; e1 = fma(q, q, e1); }
+                                else { s0 += q; e0 = fma(q, q, e0); }
+                            }
+                        } else {
+#pragma unroll
+                            for (int c = 0; c < P; c++) {
+                                const T q = (omf * v[c] + uf * v[c + 1]) - Tv[c];
+                                const T mq = mv[c] * q;
+                                if (c & 1) { s1 = fma(mv[c], q, s1); e1 = fma(mq, q, e1); }
+                                else { s0 = fma(mv[c], q, s0); e0 = fma(mq, q, e0); }
+                            }
                         }
                         acc[2 * i] = s0 + s1;
                         acc[2 * i + 1] = e0 + e1;
@@ -1246,7 +1264,7 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
 #pragma unroll
                 for (int q = 0; q < (WN + SEG - 1) / SEG; q++) {
                     int i = r + q * SEG;
-                    if (i < kp.window) term += i == cw ? T(1) : exp(-(energy(i) - Ec) / (T)kp.tau);
+                    if (i < kp.window) term += i == cw ? T(1) : exp(-(energy(i) - Ec) * (T)kp.inv_tau);
                 }
                 return T(1) / seg_sum<SEG>(term);
             };
@@ -1270,15 +1288,20 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
                 else vj = !signbit(v[j]);
                 rmask |= (uint32_t)vj << j;
             }
-            int cnt = 0;
-#pragma unroll
-            for (int c = 0; c < P; c++) {
-                int xi = xi0 + c;
-                bool inb = xi >= 0 && (xi < W - 1 || (xi == W - 1 && uf == T(0)));
-                int m = min(max(xi, 0), W - 2) - m0;  // 0 <= m <= P
-                bool vab = ((rmask >> m) & 3u) == 3u;  // taps m and m + 1
-                cnt += (((vmask >> c) & 1u) && inb && vab) ? 1 : 0;
-            }
+            // Column c samples x = xi0 + c + uf: inside the row iff
+            // 0 <= xi0 + c <= W - 2, or xi0 + c == W - 1 with uf == 0.  Its
+            // taps are m0 + m and m0 + m + 1 with m = c + (xi0 - m0) inside,
+            // and W - 2 - m0 at the last column.  As bit masks:
+            // pairs (bit j: taps j, j + 1 valid) shifted to the columns,
+            // cut to the in-row columns, plus the last-column case.
+            const uint32_t pairs = rmask & (rmask >> 1);
+            const int off = xi0 - m0;
+            const uint32_t colpairs = off >= 0 ? (off < 32 ? pairs >> off : 0u) : (-off < 32 ? pairs << -off : 0u);
+            const int clo = max(0, -xi0), chi = min(P, W - 1 - xi0);  // columns with 0 <= xi <= W - 2
+            uint32_t good = chi > clo ? colpairs & (((1u << (chi - clo)) - 1u) << clo) : 0u;
+            const int ce = W - 1 - xi0;  // the column at the last pixel
+            if (uf == T(0) && ce >= 0 && ce < P && ((pairs >> ((W - 2 - m0) & 31)) & 1u)) good |= 1u << ce;
+            int cnt = __builtin_popcount(vmask & good);
             cnt = seg_sum_i<SEG>(cnt);
             if (cnt < kp.min_valid) {
                 status = ST_GATED;

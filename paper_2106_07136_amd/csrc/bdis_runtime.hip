@@ -340,7 +340,7 @@ KParams make_kparams(const bdis_params &p, int patch) {
     k.window = p.window;
     k.window_step = p.window_step;
     double s = p.s_mode == 0 ? (double)p.window : (double)patch;
-    k.tau = 2.0 * (double)p.sigma_r * (double)p.sigma_r * s * s;
+    k.inv_tau = 1.0 / (2.0 * (double)p.sigma_r * (double)p.sigma_r * s * s);
     // kept iff count / p^2 >= gamma, decided on integers
     int need = 0;
     while (need <= patch * patch && (double)need / ((double)patch * patch) < (double)p.gamma) need++;
