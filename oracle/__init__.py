@@ -165,6 +165,17 @@ def lib():
                                   C.c_int, C.c_int]
         L.ref_depth.restype = None
         L.ref_depth.argtypes = [_PD, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double, _PD]
+        L.ref_patch_energy2d.restype = C.c_double
+        L.ref_patch_energy2d.argtypes = [_PD, _PD, _PU8, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                         C.c_double, C.c_double]
+        L.ref_patch_lk2d.restype = C.c_int
+        L.ref_patch_lk2d.argtypes = [_PD, _PD, _PD, _PD, _PU8, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                     C.c_int, C.c_double, C.c_double, C.c_double, _PD, _PD, _PD]
+        L.ref_valid_ratio2d.restype = C.c_double
+        L.ref_valid_ratio2d.argtypes = [_PU8, _PU8, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double,
+                                        C.c_double]
+        L.ref_compute_2d.restype = C.c_int
+        L.ref_compute_2d.argtypes = [C.POINTER(_Params), _PU8, _PU8, C.c_int, C.c_int, C.c_int, _PD, _PD]
         L.ref_num_levels.restype = C.c_int
         L.ref_grid_count.restype = C.c_int
         L.ref_grid_pos.restype = C.c_int
@@ -435,3 +446,58 @@ def depth(disp, f, B, d_min=0.0):
     out = np.empty((H, W))
     lib().ref_depth(_d(d), W, H, float(f), float(B), float(d_min), _d(out))
     return out
+
+
+# ---- 2-D search ---------------------------------------------------------------
+
+def grad_y(img):
+    img = np.ascontiguousarray(img, np.float64)
+    H, W = img.shape
+    out = np.empty_like(img)
+    lib().ref_grad_y(_d(img), W, H, _d(out))
+    return out
+
+
+def patch_energy2d(L, R, ML, x0, y0, p, u, v):
+    L = np.ascontiguousarray(L, np.float64)
+    R = np.ascontiguousarray(R, np.float64)
+    ML = np.ascontiguousarray(ML, np.uint8)
+    H, W = L.shape
+    return lib().ref_patch_energy2d(_d(L), _d(R), _u8(ML), W, H, x0, y0, p, float(u), float(v))
+
+
+def patch_lk2d(L, R, ML, x0, y0, p, iters, u0, v0, eps_h=1e-6):
+    """Returns (status, u, v, steps) for one patch with the 2-D search."""
+    L = np.ascontiguousarray(L, np.float64)
+    R = np.ascontiguousarray(R, np.float64)
+    ML = np.ascontiguousarray(ML, np.uint8)
+    GX, GY = grad_x(L), grad_y(L)
+    H_, W = L.shape
+    u, v = C.c_double(), C.c_double()
+    steps = np.zeros(max(iters, 1))
+    st = lib().ref_patch_lk2d(_d(L), _d(R), _d(GX), _d(GY), _u8(ML), W, H_, x0, y0, p, iters, float(u0),
+                              float(v0), float(eps_h), C.byref(u), C.byref(v), _d(steps))
+    return st, u.value, v.value, steps[:iters]
+
+
+def valid_ratio2d(ML, MR, x0, y0, p, u, v):
+    ML = np.ascontiguousarray(ML, np.uint8)
+    MR = np.ascontiguousarray(MR, np.uint8)
+    H, W = ML.shape
+    return lib().ref_valid_ratio2d(_u8(ML), _u8(MR), W, H, x0, y0, p, float(u), float(v))
+
+
+def compute_2d(left, right, params: Params | None = None):
+    """2-D search: returns (d, v) with d = -U_0 and v = V_0 (NaN where
+    unestimated); the right image's match of left (x, y) is (x - d, y + v)."""
+    params = params or Params()
+    left = np.ascontiguousarray(left, np.uint8)
+    right = np.ascontiguousarray(right, np.uint8)
+    H, W = left.shape
+    d = np.empty((H, W))
+    v = np.empty((H, W))
+    p = params._c()
+    rc = lib().ref_compute_2d(C.byref(p), _u8(left), _u8(right), W, H, W, _d(d), _d(v))
+    if rc != 0:
+        raise ValueError(f"ref_compute_2d failed: {rc}")
+    return d, v

@@ -816,3 +816,296 @@ void ref_depth(const double *disp, int W, int H, double f, double B, double d_mi
         depth[i] = (isfinite(d) && d > d_min) ? f * B / d : NAN;
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* 2-D search: the DIS patch search the method builds on (Sec. 2.1: the     */
+/* inverse-compositional LK of DIS, restricted by the paper to the epipolar */
+/* direction; Fig. 1) estimates a full translation (u, v) per patch, which  */
+/* tolerates imperfect rectification.  Everything else is the 1-D method:   */
+/* mean-normalised residuals, the window posterior along the disparity      */
+/* direction at the converged v (eqs. (3)-(4)), the gates, and the spatial  */
+/* Gaussian fusion (eq. (5)) applied to u and to v with the same weights.   */
+/* Sign convention: I_r(x + u, y + v) ~ I_l(x, y); outputs d = -u and v.    */
+/* ------------------------------------------------------------------------ */
+
+/* Template-side gradient along y: central difference, replicate border. */
+void ref_grad_y(const double *img, int W, int H, double *g)
+{
+    for (int y = 0; y < H; y++)
+        for (int x = 0; x < W; x++) {
+            int yp = y + 1 < H ? y + 1 : H - 1;
+            int ym = y - 1 > 0 ? y - 1 : 0;
+            g[(size_t)y * W + x] = 0.5 * (img[(size_t)yp * W + x] - img[(size_t)ym * W + x]);
+        }
+}
+
+/* Mean-normalised energy at (u, v): sum over left-valid pixels of
+ * (d_j - mean d)^2, d_j = I_r(x_j + u, y_j + v) - I_l(x_j, y_j), I_r read
+ * bilinearly with clamped coordinates. */
+double ref_patch_energy2d(const double *L, const double *R, const uint8_t *ML, int W, int H, int x0, int y0, int p,
+                          double u, double v)
+{
+    double sum = 0.0;
+    int n = 0;
+    for (int r = 0; r < p; r++)
+        for (int c = 0; c < p; c++) {
+            size_t i = (size_t)(y0 + r) * W + (x0 + c);
+            if (!ML[i])
+                continue;
+            sum += ref_bilinear(R, W, H, x0 + c + u, y0 + r + v) - L[i];
+            n++;
+        }
+    if (n == 0)
+        return 0.0;
+    double mean = sum / n, E = 0.0;
+    for (int r = 0; r < p; r++)
+        for (int c = 0; c < p; c++) {
+            size_t i = (size_t)(y0 + r) * W + (x0 + c);
+            if (!ML[i])
+                continue;
+            double d = ref_bilinear(R, W, H, x0 + c + u, y0 + r + v) - L[i] - mean;
+            E += d * d;
+        }
+    return E;
+}
+
+/* Inverse-compositional LK on one patch in 2-D.  J_j = (gx_j, gy_j) - mean,
+ * H = sum J J^T (2 x 2); each step solves H (du, dv) = sum J_j e_j and moves
+ * (u, v) <- (u, v) - (du, dv).  Degenerate if n = 0 or the smaller
+ * eigenvalue of H is at most eps_h n (no 2-D texture: the aperture problem).
+ * step_hist receives max(|du|, |dv|) per iteration. */
+int ref_patch_lk2d(const double *L, const double *R, const double *GX, const double *GY, const uint8_t *ML,
+                   int W, int H, int x0, int y0, int p, int iters, double u0, double v0, double eps_h,
+                   double *u_out, double *v_out, double *step_hist)
+{
+    int n = 0;
+    double sx = 0.0, sy = 0.0;
+    for (int r = 0; r < p; r++)
+        for (int c = 0; c < p; c++) {
+            size_t i = (size_t)(y0 + r) * W + (x0 + c);
+            if (ML[i]) {
+                sx += GX[i];
+                sy += GY[i];
+                n++;
+            }
+        }
+    *u_out = u0;
+    *v_out = v0;
+    if (n == 0)
+        return REF_DEGENERATE;
+    double mx = sx / n, my = sy / n, hxx = 0.0, hxy = 0.0, hyy = 0.0;
+    for (int r = 0; r < p; r++)
+        for (int c = 0; c < p; c++) {
+            size_t i = (size_t)(y0 + r) * W + (x0 + c);
+            if (!ML[i])
+                continue;
+            double jx = GX[i] - mx, jy = GY[i] - my;
+            hxx += jx * jx;
+            hxy += jx * jy;
+            hyy += jy * jy;
+        }
+    double tr = hxx + hyy, det = hxx * hyy - hxy * hxy;
+    double disc = 0.25 * (hxx - hyy) * (hxx - hyy) + hxy * hxy;
+    double lmin = 0.5 * tr - sqrt(disc);
+    if (!(lmin > eps_h * n))
+        return REF_DEGENERATE;
+    double u = u0, v = v0;
+    for (int t = 0; t < iters; t++) {
+        double dsum = 0.0;
+        for (int r = 0; r < p; r++)
+            for (int c = 0; c < p; c++) {
+                size_t i = (size_t)(y0 + r) * W + (x0 + c);
+                if (ML[i])
+                    dsum += ref_bilinear(R, W, H, x0 + c + u, y0 + r + v) - L[i];
+            }
+        double dmean = dsum / n, bx = 0.0, by = 0.0;
+        for (int r = 0; r < p; r++)
+            for (int c = 0; c < p; c++) {
+                size_t i = (size_t)(y0 + r) * W + (x0 + c);
+                if (!ML[i])
+                    continue;
+                double e = ref_bilinear(R, W, H, x0 + c + u, y0 + r + v) - L[i] - dmean;
+                bx += (GX[i] - mx) * e;
+                by += (GY[i] - my) * e;
+            }
+        /* (du, dv) = H^-1 (bx, by) */
+        double du = (hyy * bx - hxy * by) / det, dv = (hxx * by - hxy * bx) / det;
+        if (step_hist)
+            step_hist[t] = fabs(du) > fabs(dv) ? fabs(du) : fabs(dv);
+        u -= du;
+        v -= dv;
+    }
+    *u_out = u;
+    *v_out = v;
+    return REF_KEPT;
+}
+
+/* Valid fraction at (u, v): left pixel valid, its sample inside the image,
+ * and all four bilinear taps valid in the right mask. */
+double ref_valid_ratio2d(const uint8_t *ML, const uint8_t *MR, int W, int H, int x0, int y0, int p, double u,
+                         double v)
+{
+    int cnt = 0;
+    for (int r = 0; r < p; r++)
+        for (int c = 0; c < p; c++) {
+            size_t i = (size_t)(y0 + r) * W + (x0 + c);
+            double X = x0 + c + u, Y = y0 + r + v;
+            if (!ML[i] || X < 0.0 || X > (double)(W - 1) || Y < 0.0 || Y > (double)(H - 1))
+                continue;
+            int mx = (int)floor(X), my = (int)floor(Y);
+            if (W > 1 && mx > W - 2) mx = W - 2;
+            if (H > 1 && my > H - 2) my = H - 2;
+            int mx1 = W > 1 ? mx + 1 : mx, my1 = H > 1 ? my + 1 : my;
+            if (MR[(size_t)my * W + mx] && MR[(size_t)my * W + mx1] && MR[(size_t)my1 * W + mx] &&
+                MR[(size_t)my1 * W + mx1])
+                cnt++;
+        }
+    return (double)cnt / ((double)p * p);
+}
+
+/* Whole pair with the 2-D search, coarse to fine.  disp = -U_0 and vout = V_0
+ * (W*H doubles each, NaN where no kept patch covers the pixel).  The
+ * posterior window is along x at the converged v.  Returns 0, -1 (bad
+ * arguments) or -2 (allocation). */
+int ref_compute_2d(const ref_params *P, const uint8_t *Limg, const uint8_t *Rimg, int W, int H, int pitch,
+                   double *disp, double *vout)
+{
+    if (!P || !Limg || !Rimg || !disp || !vout || W < 1 || H < 1 || pitch < W || P->patch < 1 ||
+        P->stride < 1 || P->iters < 0 || P->iters > 1000 || P->window < 1 || (P->window % 2) == 0 ||
+        P->window > 63 || W < P->patch || H < P->patch || P->fusion != 0)
+        return -1;
+    int NL = ref_num_levels(W, H, P->patch, P->levels);
+    if (NL < 1)
+        return -1;
+    double *pl[REF_MAX_LEVELS], *pr[REF_MAX_LEVELS], *gx[REF_MAX_LEVELS], *gy[REF_MAX_LEVELS];
+    double *U[REF_MAX_LEVELS], *V[REF_MAX_LEVELS];
+    uint8_t *ml[REF_MAX_LEVELS], *mr[REF_MAX_LEVELS];
+    int Ws[REF_MAX_LEVELS], Hs[REF_MAX_LEVELS];
+    memset(pl, 0, sizeof pl); memset(pr, 0, sizeof pr); memset(gx, 0, sizeof gx); memset(gy, 0, sizeof gy);
+    memset(U, 0, sizeof U); memset(V, 0, sizeof V); memset(ml, 0, sizeof ml); memset(mr, 0, sizeof mr);
+    int rc = 0;
+    double *aw = NULL, *awu = NULL, *awv = NULL;
+    for (int l = 0; l < NL; l++) {
+        ref_level_dims(W, H, l, &Ws[l], &Hs[l]);
+        size_t n = (size_t)Ws[l] * Hs[l];
+        pl[l] = (double *)malloc(n * sizeof(double));
+        pr[l] = (double *)malloc(n * sizeof(double));
+        gx[l] = (double *)malloc(n * sizeof(double));
+        gy[l] = (double *)malloc(n * sizeof(double));
+        U[l] = (double *)malloc(n * sizeof(double));
+        V[l] = (double *)malloc(n * sizeof(double));
+        ml[l] = (uint8_t *)malloc(n);
+        mr[l] = (uint8_t *)malloc(n);
+        if (!pl[l] || !pr[l] || !gx[l] || !gy[l] || !U[l] || !V[l] || !ml[l] || !mr[l]) {
+            rc = -2;
+            goto done2;
+        }
+    }
+    aw = (double *)malloc((size_t)W * H * sizeof(double));
+    awu = (double *)malloc((size_t)W * H * sizeof(double));
+    awv = (double *)malloc((size_t)W * H * sizeof(double));
+    if (!aw || !awu || !awv) {
+        rc = -2;
+        goto done2;
+    }
+    for (int y = 0; y < H; y++)
+        for (int x = 0; x < W; x++) {
+            pl[0][(size_t)y * W + x] = Limg[(size_t)y * pitch + x];
+            pr[0][(size_t)y * W + x] = Rimg[(size_t)y * pitch + x];
+        }
+    ref_mask_base(Limg, W, H, pitch, P->valid_lo, P->valid_hi, ml[0]);
+    ref_mask_base(Rimg, W, H, pitch, P->valid_lo, P->valid_hi, mr[0]);
+    for (int l = 1; l < NL; l++) {
+        ref_blur_decimate(pl[l - 1], Ws[l - 1], Hs[l - 1], pl[l]);
+        ref_blur_decimate(pr[l - 1], Ws[l - 1], Hs[l - 1], pr[l]);
+        ref_mask_down(ml[l - 1], Ws[l - 1], Hs[l - 1], ml[l]);
+        ref_mask_down(mr[l - 1], Ws[l - 1], Hs[l - 1], mr[l]);
+    }
+    for (int l = 0; l < NL; l++) {
+        ref_grad_x(pl[l], Ws[l], Hs[l], gx[l]);
+        ref_grad_y(pl[l], Ws[l], Hs[l], gy[l]);
+    }
+    for (int l = NL - 1; l >= 0; l--) {
+        int w = Ws[l], h = Hs[l], p = P->patch;
+        int nx = ref_grid_count(w, p, P->stride), ny = ref_grid_count(h, p, P->stride);
+        size_t np = (size_t)nx * ny;
+        double *pu = (double *)malloc(np * sizeof(double));
+        double *pv = (double *)malloc(np * sizeof(double));
+        double *pp = (double *)malloc(np * sizeof(double));
+        int8_t *ps = (int8_t *)malloc(np);
+        double steps[1024];
+        if (!pu || !pv || !pp || !ps) {
+            free(pu); free(pv); free(pp); free(ps);
+            rc = -2;
+            goto done2;
+        }
+        for (int jy = 0; jy < ny; jy++)
+            for (int jx = 0; jx < nx; jx++) {
+                int k = jy * nx + jx;
+                int x0 = ref_grid_pos(jx, w, p, P->stride), y0 = ref_grid_pos(jy, h, p, P->stride);
+                double u0 = 0.0, v0 = 0.0;
+                if (l < NL - 1) {
+                    double cx = x0 + 0.5 * (p - 1), cy = y0 + 0.5 * (p - 1);
+                    u0 = 2.0 * ref_bilinear(U[l + 1], Ws[l + 1], Hs[l + 1], 0.5 * cx, 0.5 * cy);
+                    v0 = 2.0 * ref_bilinear(V[l + 1], Ws[l + 1], Hs[l + 1], 0.5 * cx, 0.5 * cy);
+                }
+                double u, v, post = 0.0;
+                int st = ref_patch_lk2d(pl[l], pr[l], gx[l], gy[l], ml[l], w, h, x0, y0, p, P->iters, u0, v0,
+                                        P->eps_h, &u, &v, steps);
+                if (st == REF_KEPT) {
+                    if (!isfinite(u) || !isfinite(v) || fabs(u - u0) > (double)p || fabs(v - v0) > (double)p ||
+                        (P->conv_tol > 0 && P->iters > 0 && !(steps[P->iters - 1] <= P->conv_tol))) {
+                        st = REF_DIVERGED;
+                    } else {
+                        double E[64];
+                        int nw = P->window, cw = (P->window - 1) / 2;
+                        for (int i = 0; i < nw; i++)
+                            E[i] = ref_patch_energy2d(pl[l], pr[l], ml[l], w, h, x0, y0, p,
+                                                      u + (i - cw) * P->window_step, v);
+                        double s = P->s_mode == 0 ? (double)P->window : (double)p;
+                        post = ref_posterior(E, nw, cw, 2.0 * P->sigma_r * P->sigma_r * s * s);
+                        if (ref_valid_ratio2d(ml[l], mr[l], w, h, x0, y0, p, u, v) < P->gamma) {
+                            st = REF_GATED;
+                            post = 0.0;
+                        }
+                    }
+                }
+                pu[k] = u;
+                pv[k] = v;
+                pp[k] = st == REF_KEPT ? post : 0.0;
+                ps[k] = (int8_t)st;
+            }
+        /* eq. (5) fusion of u, then of v, with the same weights */
+        ref_densify(P, w, h, nx, ny, pu, pp, ps, pl[l], pr[l], aw, awu);
+        ref_densify(P, w, h, nx, ny, pv, pp, ps, pl[l], pr[l], aw, awv);
+        for (int y = 0; y < h; y++)
+            for (int x = 0; x < w; x++) {
+                size_t i = (size_t)y * w + x;
+                double a, b;
+                if (aw[i] > 0.0) {
+                    a = awu[i] / aw[i];
+                    b = awv[i] / aw[i];
+                } else if (l == 0) {
+                    a = b = NAN;
+                } else if (l == NL - 1) {
+                    a = b = 0.0;
+                } else {
+                    a = 2.0 * ref_bilinear(U[l + 1], Ws[l + 1], Hs[l + 1], 0.5 * x, 0.5 * y);
+                    b = 2.0 * ref_bilinear(V[l + 1], Ws[l + 1], Hs[l + 1], 0.5 * x, 0.5 * y);
+                }
+                U[l][i] = a;
+                V[l][i] = b;
+            }
+        free(pu); free(pv); free(pp); free(ps);
+    }
+    for (size_t i = 0; i < (size_t)W * H; i++) {
+        disp[i] = -U[0][i];
+        vout[i] = V[0][i];
+    }
+done2:
+    for (int l = 0; l < NL; l++) {
+        free(pl[l]); free(pr[l]); free(gx[l]); free(gy[l]); free(U[l]); free(V[l]); free(ml[l]); free(mr[l]);
+    }
+    free(aw); free(awu); free(awv);
+    return rc;
+}

@@ -61,6 +61,17 @@ MUTATIONS = {
     "rectify_outside_kept": ("if (xs >= 0.0 && ys >= 0.0 && xs <= (double)(sw - 1) && ys <= (double)(sh - 1)) {",
                              "if (1) {"),
     "depth_inverted": ("f * B / d : NAN;", "d / (f * B) : NAN;"),
+    # 2-D search
+    "grad_y_sign": ("0.5 * (img[(size_t)yp * W + x] - img[(size_t)ym * W + x])",
+                    "0.5 * (img[(size_t)ym * W + x] - img[(size_t)yp * W + x])"),
+    "lk2d_cross_term_sign": ("double du = (hyy * bx - hxy * by) / det, dv = (hxx * by - hxy * bx) / det;",
+                             "double du = (hyy * bx + hxy * by) / det, dv = (hxx * by + hxy * bx) / det;"),
+    "lk2d_solve_swapped": ("double du = (hyy * bx - hxy * by) / det, dv = (hxx * by - hxy * bx) / det;",
+                           "double du = (hxx * bx - hxy * by) / det, dv = (hyy * by - hxy * bx) / det;"),
+    "energy2d_transposed": ("sum += ref_bilinear(R, W, H, x0 + c + u, y0 + r + v) - L[i];",
+                            "sum += ref_bilinear(R, W, H, x0 + c + v, y0 + r + u) - L[i];"),
+    "ratio2d_bottom_taps_ignored": ("MR[(size_t)my1 * W + mx] &&\n                MR[(size_t)my1 * W + mx1])",
+                                    "1 &&\n                1)"),
 }
 
 

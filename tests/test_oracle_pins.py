@@ -723,3 +723,92 @@ def test_depth_closed_form(ref):
     np.testing.assert_allclose(z[fin] * d[fin], 700.0 * 5.5, rtol=1e-15)
     z2 = ref.depth(d, 700.0, 5.5, d_min=2.0)
     assert np.isnan(z2[0, 0]) and np.isfinite(z2[0, 1])
+
+
+# ---------------------------------------------------------------- 2-D search
+
+def _shift2d(img, sx, sy):
+    """R(x, y) = L(x + sx, y + sy), border replicated."""
+    H, W = img.shape
+    ys = np.clip(np.arange(H) + sy, 0, H - 1)
+    xs = np.clip(np.arange(W) + sx, 0, W - 1)
+    return img[ys][:, xs].copy()
+
+
+def test_grad_y_exact_on_quadratic(ref):
+    y, x = np.mgrid[0:9, 0:7].astype(float)
+    img = 0.5 * y * y - 3 * y + 2 * x
+    g = ref.grad_y(img)
+    np.testing.assert_allclose(g[1:-1], (y - 3)[1:-1], atol=1e-12)
+    # replicate border: one-sided halves at the first and last rows
+    np.testing.assert_allclose(g[0], 0.5 * (img[1] - img[0]), atol=1e-12)
+    np.testing.assert_allclose(g[-1], 0.5 * (img[-1] - img[-2]), atol=1e-12)
+
+
+@pytest.mark.parametrize("sx,sy", [(0, 2), (3, -2), (5, 1)])
+def test_2d_integer_shift_recovered(ref, sx, sy):
+    """R(x, y) = L(x + sx, y + sy): left (x, y) matches right (x - sx, y - sy),
+    so d = sx and v = -sy away from the borders."""
+    L = synth.integer_shift_pair(128, 96, 0, seed=21).left
+    R = _shift2d(L, sx, sy)
+    d, v = ref.compute_2d(L, R, ref.Params(levels=3, iters=12))
+    m = 12
+    di, vi = d[m:-m, m + abs(sx):-m - abs(sx)], v[m:-m, m + abs(sx):-m - abs(sx)]
+    assert np.isfinite(di).mean() > 0.99
+    assert np.nanmax(np.abs(di - sx)) <= 1e-3 and np.nanmax(np.abs(vi + sy)) <= 1e-3
+
+
+def test_2d_lk_fixed_point_matches_brute_force(ref):
+    """Noise-free integer shift (2, -1): the LK iteration from (0.6, -0.4) off
+    the answer reaches it, and a brute-force search of the mean-normalised
+    SSD over a 1/16-px grid has its minimum there too."""
+    L = synth.integer_shift_pair(48, 40, 0, seed=22).left.astype(float)
+    R = _shift2d(L, 2, -1).astype(float)
+    ML = np.ones_like(L, np.uint8)
+    st, u, v, steps = ref.patch_lk2d(L, R, ML, 16, 16, 8, 30, -2 + 0.6, 1 - 0.4)
+    assert st == 0 and abs(u + 2) < 1e-9 and abs(v - 1) < 1e-9
+    grid = np.arange(-3.0, -1.0 + 1e-9, 1 / 16)
+    gridv = np.arange(0.0, 2.0 + 1e-9, 1 / 16)
+    E = np.array([[ref.patch_energy2d(L, R, ML, 16, 16, 8, a, b) for a in grid] for b in gridv])
+    j, i = np.unravel_index(np.argmin(E), E.shape)
+    assert abs(grid[i] + 2) < 1e-12 and abs(gridv[j] - 1) < 1e-12 and E[j, i] < 1e-18
+
+
+def test_2d_energy_reduces_to_1d_on_whole_rows(ref):
+    L = synth.integer_shift_pair(40, 24, 0, seed=23).left.astype(float)
+    R = _shift2d(L, 3, 0).astype(float) + np.random.default_rng(1).normal(0, 2, L.shape)
+    ML = np.ones_like(L, np.uint8)
+    for u in (-3.25, -2.5, 0.75):
+        assert ref.patch_energy2d(L, R, ML, 12, 8, 8, u, 0.0) == ref.patch_energy(L, R, ML, 12, 8, 8, u)
+
+
+def test_2d_vertical_stripes_are_degenerate(ref):
+    """An image constant along y has no y-gradient: the 2x2 Hessian is
+    singular (the aperture problem), so every patch is discarded."""
+    row = np.clip(np.rint(128 + 80 * np.sin(np.arange(64) / 3.0)), 0, 255).astype(np.uint8)
+    L = np.tile(row, (32, 1))
+    st, *_ = ref.patch_lk2d(L.astype(float), L.astype(float), np.ones_like(L), 8, 8, 8, 5, 0.0, 0.0)
+    assert st == 1
+    d, v = ref.compute_2d(L, L, ref.Params(levels=1))
+    assert np.isnan(d).all() and np.isnan(v).all()
+
+
+def test_2d_additive_offset_invariance(ref):
+    L = synth.integer_shift_pair(48, 40, 0, seed=24).left.astype(float)
+    R = _shift2d(L, 1, 1).astype(float) + np.random.default_rng(2).normal(0, 3, L.shape)
+    ML = np.ones_like(L, np.uint8)
+    a = ref.patch_lk2d(L, R, ML, 16, 16, 8, 10, -0.5, -0.5)
+    b = ref.patch_lk2d(L, R + 17.0, ML, 16, 16, 8, 10, -0.5, -0.5)
+    assert a[0] == b[0] == 0
+    assert abs(a[1] - b[1]) < 1e-9 and abs(a[2] - b[2]) < 1e-9
+
+
+def test_2d_valid_ratio_hand_counted(ref):
+    ML = np.ones((10, 10), np.uint8)
+    MR = np.ones((10, 10), np.uint8)
+    MR[5, :] = 0
+    # 4x4 patch at (2, 2), v = 0.5: rows 2..5 sample between rows y and y + 1;
+    # the row pairs touching row 5 are (4, 5) and (5, 6): patch rows 4 and 5
+    assert ref.valid_ratio2d(ML, MR, 2, 2, 4, 0.0, 0.5) == 8 / 16
+    # u = 6.5 pushes columns 2..5 to 8.5..11.5: only the first stays inside
+    assert ref.valid_ratio2d(ML, np.ones_like(MR), 2, 2, 4, 6.5, 0.0) == 4 / 16
