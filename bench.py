@@ -438,6 +438,54 @@ def rectified_leg(pair, steps, warmup, precision):
     return res
 
 
+def search2d_leg(steps, warmup, precision):
+    """The 2-D (x, y) patch search against the 1-D search on the headline
+    pair taken with an imperfect rectification (synth.misaligned_pair, seed
+    2, up to 6 px of roll: a vertical offset of 1.1-3.4 px across the
+    image): time per pair, per-kernel times, and the accuracy of d (and of
+    v for the 2-D search) against the generator's ground truth; both on the
+    aligned headline pair too."""
+    import numpy as np
+    import torch
+
+    from paper_2106_07136_amd import bdis, synth
+    mis, vg = synth.misaligned_pair(640, 480, 64.0, 2, v_max=6.0)
+    aligned = synth.make_pair(640, 480, 64.0, 2)
+    prm = bdis.Params(levels=5, iters=12, precision=precision)
+    h = bdis.Bdis(prm)
+    res = {"workload": "640x480, disparity 0-64 px, 5 levels, patch 8, stride 4, 12 iterations; misaligned: "
+                       "the same scene with the right image rolled (vertical offset 1.1-3.4 px)"}
+    for name, pair in (("misaligned", mis), ("aligned", aligned)):
+        L = torch.from_numpy(pair.left).cuda()
+        R = torch.from_numpy(pair.right).cuda()
+        d2 = torch.empty(L.shape, dtype=torch.float32, device=L.device)
+        v2 = torch.empty_like(d2)
+        d1 = torch.empty_like(d2)
+        ms2 = timed(lambda: h.compute_2d(L, R, d2, v2), steps, warmup)
+        ms1 = timed(lambda: h.compute(L, R, d1), steps, warmup)
+        a2, a1 = accuracy([d2], [pair]), accuracy([d1], [pair])
+        d2n, v2n = d2.cpu().numpy(), v2.cpu().numpy()
+        m = np.isfinite(d2n) & pair.valid
+        vt = vg if name == "misaligned" else np.zeros_like(d2n)
+        a2["v_epe_px"] = float(np.abs(v2n[m] - vt[m]).mean())
+        a2["median_d_err_px"] = float(np.median(np.abs(d2n[m] - pair.disp[m])))
+        m1 = np.isfinite(d1.cpu().numpy()) & pair.valid
+        a1["median_d_err_px"] = float(np.median(np.abs(d1.cpu().numpy()[m1] - pair.disp[m1])))
+        res[name] = {"search_2d": {"us_per_pair": ms2 * 1e3, "accuracy": a2},
+                     "search_1d": {"us_per_pair": ms1 * 1e3, "accuracy": a1}}
+        log(f"bench: 2-D search {name}: {ms2 * 1e3:.1f} us/pair {a2}; 1-D {ms1 * 1e3:.1f} us/pair {a1}")
+    h.set_profiling(True)
+    L = torch.from_numpy(mis.left).cuda()
+    R = torch.from_numpy(mis.right).cuda()
+    for _ in range(steps):
+        h.compute_2d(L, R)
+    prof = h.profile()
+    h.set_profiling(False)
+    res["kernels"] = {k: {"launches": n, "avg_us": t / n * 1e3} for k, (n, t) in prof.items()}
+    h.close()
+    return res
+
+
 def ablation_leg(variants, steps, warmup, precision):
     """BDIS against DIS's fusion (eq. (2)) on the same pairs, per generator
     variant, with the error statistics of the paper's Table 1 (median and
@@ -619,6 +667,7 @@ def main():
             "per call, plain vs learned init (48-channel proposal net)")
         res["convergence_test"] = conv_tol_leg(pair, held, args.precision)
         res["rectified_pipeline"] = rectified_leg(pair, 50, 5, args.precision)
+        res["search_2d"] = search2d_leg(50, 5, args.precision)
         res["ablation_dis_vs_bdis"] = {
             "workload": "16 640x480 pairs per variant (diffuse: no gain field, no specular blobs, seeds "
                         "95000-95015; non-Lambertian: the full generator, seeds 95100-95115), BDIS against "

@@ -176,6 +176,23 @@ BDIS_API bdis_status bdis_compute_noalloc(bdis_t *h, const uint8_t *left, const 
                                           int32_t height, int32_t pitch_bytes, float *disp,
                                           int32_t disp_pitch_elems, void *stream);
 
+/* Disparity with the 2-D (x, y) patch search of DIS, the method the paper
+ * builds on (Sec. 2.1, Fig. 1), which tolerates imperfectly rectified pairs:
+ * each patch estimates a translation (u, v) by inverse-compositional LK with
+ * a 2 x 2 Hessian of the mean-normalised template gradients (degenerate when
+ * its smaller eigenvalue is at most eps_h times the valid count: no 2-D
+ * texture), the right image read bilinearly.  The window posterior (eqs.
+ * (3)-(4)) samples along x at the converged v, the gamma gate needs all four
+ * bilinear taps valid, and both components are fused with the same weights
+ * (Sec. 2.3).  disp as in bdis_compute (d = -u: left (x, y) matches right
+ * (x - d, y + v)); vdisp (optional, device float32, vdisp_pitch_elems >=
+ * width) receives v, NaN where unestimated.  The handle's parameters apply;
+ * patch sides up to 8.  Errors: as bdis_compute, and BDIS_E_UNSUPPORTED for
+ * a patch above 8, eq. (2)'s fusion or the learned init. */
+BDIS_API bdis_status bdis_compute_2d(bdis_t *h, const uint8_t *left, const uint8_t *right, int32_t width,
+                                     int32_t height, int32_t pitch_bytes, float *disp, int32_t disp_pitch_elems,
+                                     float *vdisp, int32_t vdisp_pitch_elems, void *stream);
+
 /* The same for n independent pairs of mixed sizes in one pass: each kernel of
  * the path is launched once for all pairs (level by level, coarsest first).
  * `pairs` is a HOST array of n entries, read during the call only.  Each

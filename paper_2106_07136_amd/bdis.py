@@ -115,6 +115,7 @@ def lib():
         L.bdis_reserve.argtypes = [vp, i32, i32, i32]
         L.bdis_compute.argtypes = [vp, vp, vp, i32, i32, i32, vp, i32, vp]
         L.bdis_compute_noalloc.argtypes = [vp, vp, vp, i32, i32, i32, vp, i32, vp]
+        L.bdis_compute_2d.argtypes = [vp, vp, vp, i32, i32, i32, vp, i32, vp, i32, vp]
         L.bdis_compute_batch.argtypes = [vp, C.POINTER(CPair), i32, vp]
         L.bdis_set_tuning.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
         L.bdis_debug_stage.argtypes = [vp, i32, i32, vp, C.c_size_t]
@@ -134,7 +135,7 @@ def lib():
         L.bdis_last_error.argtypes = [vp]
         L.bdis_last_error.restype = C.c_char_p
         for name in ("bdis_plan", "bdis_create", "bdis_set_params", "bdis_reserve", "bdis_compute",
-                     "bdis_compute_noalloc",
+                     "bdis_compute_noalloc", "bdis_compute_2d",
                      "bdis_compute_batch", "bdis_set_tuning", "bdis_debug_stage",
                      "bdis_set_profiling", "bdis_get_profile", "bdis_set_batch_mode",
                      "bdis_batch_error", "bdis_set_net", "bdis_net_input", "bdis_set_fold_densify",
@@ -226,6 +227,28 @@ class Bdis:
                                   out.data_ptr(), out.stride(0), _stream_ptr(stream)), self._h)
         self._last_shape = (W, H)
         return out
+
+    def compute_2d(self, left, right, out=None, vout=None, stream=None, with_v=True):
+        """2-D patch search: returns (disparity, vertical offset) float32
+        device tensors; the right-image match of left (x, y) is (x - d, y + v).
+        with_v=False skips the vertical output (returned as None)."""
+        import torch
+        if left.dtype != torch.uint8 or right.dtype != torch.uint8 or left.shape != right.shape:
+            raise ValueError("left/right must be uint8 device tensors of equal shape")
+        if left.stride(1) != 1 or right.stride(1) != 1 or left.stride(0) != right.stride(0):
+            raise ValueError("rows must be contiguous with equal pitch")
+        H, W = left.shape
+        if out is None:
+            out = torch.empty((H, W), dtype=torch.float32, device=left.device)
+        if vout is None and with_v:
+            vout = torch.empty((H, W), dtype=torch.float32, device=left.device)
+        for t in (out, vout):
+            if t is not None and (t.dtype != torch.float32 or t.shape != (H, W) or t.stride(1) != 1):
+                raise ValueError("outputs must be float32 (H, W) with contiguous rows")
+        _check(lib().bdis_compute_2d(self._h, left.data_ptr(), right.data_ptr(), W, H, left.stride(0),
+                                     out.data_ptr(), out.stride(0), vout.data_ptr() if vout is not None else None,
+                                     vout.stride(0) if vout is not None else 0, _stream_ptr(stream)), self._h)
+        return out, vout
 
     def set_net(self, net):
         """Attach a paper_2106_07136_amd.net.ProposalNet (None detaches); it is

@@ -17,6 +17,7 @@
 #include "bdis_geometry.hpp"
 #include "bdis_kernels.hpp"
 #include "bdis_persist.hpp"
+#include "bdis_search2d.hpp"
 #include "bdisnet_internal.hpp"
 
 using namespace bdis;
@@ -375,7 +376,7 @@ bdis_status ensure_ws(bdis_t *h, size_t bytes) {
 // A launch: kernel kind, template selectors and its jobs (passed by value).
 // K_FORK / K_JOIN launch nothing: work after a fork runs on the side stream
 // (lane 1) until the join makes the main stream wait for it.
-enum Kind { K_PYR2, K_LK, K_DENSE, K_NETIN, K_NETF, K_GATE, K_FORK, K_JOIN };
+enum Kind { K_PYR2, K_LK, K_DENSE, K_NETIN, K_NETF, K_GATE, K_FORK, K_JOIN, K_LK2, K_DENSE2 };
 struct Launch {
     Kind kind;
     int level;
@@ -701,6 +702,31 @@ void launch_one(bdis_t *h, const Launch &L, hipStream_t s) {
         case 16: launch_lk<T, 16>(h, L, s); break;
         }
         break;
+    case K_LK2: {
+        const JobPack<Lk2Job> &pk = pack_of<Lk2Job>(L);
+        const dim3 g(L.blocks), b(kBlock);
+        switch (L.patch) {
+        case 4:
+            if (L.u8) hipLaunchKernelGGL((k_lk2d<T, 4, true>), g, b, 0, s, pk, L.kp);
+            else hipLaunchKernelGGL((k_lk2d<T, 4, false>), g, b, 0, s, pk, L.kp);
+            break;
+        case 6:
+            if (L.u8) hipLaunchKernelGGL((k_lk2d<T, 6, true>), g, b, 0, s, pk, L.kp);
+            else hipLaunchKernelGGL((k_lk2d<T, 6, false>), g, b, 0, s, pk, L.kp);
+            break;
+        default:
+            if (L.u8) hipLaunchKernelGGL((k_lk2d<T, 8, true>), g, b, 0, s, pk, L.kp);
+            else hipLaunchKernelGGL((k_lk2d<T, 8, false>), g, b, 0, s, pk, L.kp);
+            break;
+        }
+        break;
+    }
+    case K_DENSE2: {
+        const JobPack<Dense2Job> &pk = pack_of<Dense2Job>(L);
+        if (L.u8) hipLaunchKernelGGL((k_dense2d<T, true>), dim3(L.blocks), dim3(kBlock), 0, s, pk, L.kp);
+        else hipLaunchKernelGGL((k_dense2d<T, false>), dim3(L.blocks), dim3(kBlock), 0, s, pk, L.kp);
+        break;
+    }
     case K_DENSE: {
         const JobPack<DenseJob> &pk = pack_of<DenseJob>(L);
         if (L.u8) hipLaunchKernelGGL((k_dense<T, true>), dim3(L.blocks), dim3(kBlock), 0, s, pk, L.kp);
@@ -719,6 +745,8 @@ std::string launch_name(const Launch &L) {
     case K_DENSE: snprintf(buf, sizeof buf, "dense_%s_l%d", t, L.level); break;
     case K_NETIN: snprintf(buf, sizeof buf, "netin_%s", t); break;
     case K_NETF: snprintf(buf, sizeof buf, "net_forward"); break;
+    case K_LK2: snprintf(buf, sizeof buf, "lk2d_%s_p%d_l%d", t, L.patch, L.level); break;
+    case K_DENSE2: snprintf(buf, sizeof buf, "dense2d_%s_l%d", t, L.level); break;
     default: snprintf(buf, sizeof buf, "gate_%s", t); break;
     }
     return buf;
@@ -1148,6 +1176,106 @@ bdis_status run(bdis_t *h, std::vector<PairIn> &pairs, hipStream_t s, int mode =
     return BDIS_OK;
 }
 
+// Workspace of one pair for the 2-D search: pyramid levels >= 1, the fields
+// U_l and V_l of levels 1 .. L-1, and per level the records u, v, w and the
+// outcome byte.
+struct PairWs2 {
+    void *pyr_l[kMaxLevels], *pyr_r[kMaxLevels], *U[kMaxLevels], *V[kMaxLevels];
+    void *rec_u[kMaxLevels], *rec_v[kMaxLevels], *rec_w[kMaxLevels];
+    int8_t *rec_st[kMaxLevels];
+};
+
+size_t pair_ws2_bytes(const Geo &g, size_t esz, PairWs2 *w, char *base) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        void *p = base ? base + off : nullptr;
+        off += align_up(bytes);
+        return p;
+    };
+    if (w) memset(w, 0, sizeof *w);
+    for (int l = 0; l < g.L; l++) {
+        const size_t px = (size_t)g.W[l] * g.H[l], np = (size_t)g.nx[l] * g.ny[l];
+        void *a = nullptr, *b = nullptr, *c = nullptr, *d = nullptr;
+        if (l >= 1) { a = take(px * esz); b = take(px * esz); c = take(px * esz); d = take(px * esz); }
+        void *ru = take(np * esz), *rv = take(np * esz), *rw = take(np * esz), *rs = take(np);
+        if (w) {
+            w->pyr_l[l] = a; w->pyr_r[l] = b; w->U[l] = c; w->V[l] = d;
+            w->rec_u[l] = ru; w->rec_v[l] = rv; w->rec_w[l] = rw; w->rec_st[l] = (int8_t *)rs;
+        }
+    }
+    return off;
+}
+
+// The 2-D search on one pair: pyramid, then per level (coarsest first) the
+// 2-D LK launch and the two-field densification.
+bdis_status run_2d(bdis_t *h, const uint8_t *left, const uint8_t *right, int W, int H, int pitch, float *disp,
+                   int dpitch, float *vdisp, int vpitch, hipStream_t s) {
+    DeviceGuard dg(h->device);
+    const bdis_params &prm = h->prm;
+    const bool f64 = prm.precision == 0;
+    const size_t esz = esize(prm);
+    PairIn p;
+    p.left = left; p.right = right; p.disp = disp;
+    p.W = W; p.H = H; p.pitch = pitch; p.dpitch = dpitch;
+    p.patch = prm.patch; p.stride = prm.stride; p.dmax = prm.max_disparity;
+    if (!make_geo(W, H, p.patch, p.stride, requested_levels(prm, p.dmax), p.g)) {
+        set_err(h->err, "image %dx%d smaller than patch %d", W, H, p.patch);
+        return BDIS_E_INVALID_ARG;
+    }
+    const size_t need = align_up(pair_ws2_bytes(p.g, esz, nullptr, nullptr));
+    bdis_status st = ensure_ws(h, need);
+    if (st != BDIS_OK) return st;
+    PairWs2 w;
+    (void)pair_ws2_bytes(p.g, esz, &w, h->ws);
+    // the 1-D carve's pyramid pointers feed the shared pyramid planner
+    memset(&p.ws, 0, sizeof p.ws);
+    for (int l = 1; l < p.g.L; l++) { p.ws.pyr_l[l] = w.pyr_l[l]; p.ws.pyr_r[l] = w.pyr_r[l]; }
+    std::vector<PairIn> one{p};
+    std::vector<Launch> ls;
+    const KParams kp = make_kparams(prm, p.patch);
+    plan_pyramid(ls, one, p.g.Lp, f64, kp);
+    const void *gt = f64 ? (const void *)(h->gtab_d + gtab_offset(p.patch)) : (const void *)(h->gtab_f + gtab_offset(p.patch));
+    for (int l = p.g.L - 1; l >= 0; l--) {
+        const bool coarsest = l == p.g.L - 1;
+        Lk2Job j{};
+        j.L = l == 0 ? (const void *)left : w.pyr_l[l];
+        j.R = l == 0 ? (const void *)right : w.pyr_r[l];
+        j.Uc = coarsest ? nullptr : w.U[l + 1];
+        j.Vc = coarsest ? nullptr : w.V[l + 1];
+        j.rec_u = w.rec_u[l]; j.rec_v = w.rec_v[l]; j.rec_w = w.rec_w[l]; j.rec_st = w.rec_st[l];
+        j.pitch = l == 0 ? pitch : p.g.W[l];
+        j.W = p.g.W[l]; j.H = p.g.H[l];
+        j.Wc = coarsest ? 0 : p.g.W[l + 1]; j.Hc = coarsest ? 0 : p.g.H[l + 1];
+        j.nx = p.g.nx[l]; j.ny = p.g.ny[l]; j.stride = p.stride;
+        std::vector<Lk2Job> lj{j};
+        append(ls, K_LK2, l, p.patch, l == 0, f64, lj, kp, [](const Lk2Job &q) { return lk2_blocks(q.nx, q.ny); });
+        Dense2Job d{};
+        for (int f = 0; f < 2; f++) {
+            DenseView &D = f == 0 ? d.du : d.dv;
+            D.L = j.L; D.R = j.R;
+            D.rec_u = f == 0 ? w.rec_u[l] : w.rec_v[l];
+            D.rec_w = w.rec_w[l];
+            D.gtab = gt;
+            D.Uc = coarsest ? nullptr : (f == 0 ? w.U[l + 1] : w.V[l + 1]);
+            D.pitch = j.pitch; D.W = j.W; D.H = j.H; D.patch = p.patch; D.stride = p.stride;
+            D.nx = j.nx; D.ny = j.ny; D.Wc = j.Wc; D.Hc = j.Hc;
+            D.mode = l == 0 ? 2 : (coarsest ? 1 : 0);
+        }
+        d.Uo = l == 0 ? nullptr : w.U[l];
+        d.Vo = l == 0 ? nullptr : w.V[l];
+        d.out_d = l == 0 ? disp : nullptr;
+        d.out_v = l == 0 ? vdisp : nullptr;
+        d.out_pitch = dpitch; d.vout_pitch = vpitch;
+        std::vector<Dense2Job> dj{d};
+        append(ls, K_DENSE2, l, 0, l == 0, f64, dj, kp,
+               [](const Dense2Job &q) { return (q.du.W * q.du.H + kBlock - 1) / kBlock; });
+    }
+    st = launch_all(h, ls, s);
+    if (st != BDIS_OK) return st;
+    HIPCHK(h, hipGetLastError());
+    return BDIS_OK;
+}
+
 }  // namespace
 
 // ============================================================== C ABI
@@ -1335,6 +1463,24 @@ bdis_status bdis_compute_noalloc(bdis_t *h, const uint8_t *left, const uint8_t *
     st = run(h, pairs, (hipStream_t)stream, 1, h->scratch, BDIS_NOALLOC_SCRATCH_BYTES);
     h->profiling = prof;
     // the stage taps of bdis_debug_stage would point into the shared scratch
+    h->have_last = false;
+    return st;
+}
+
+bdis_status bdis_compute_2d(bdis_t *h, const uint8_t *left, const uint8_t *right, int32_t width, int32_t height,
+                            int32_t pitch_bytes, float *disp, int32_t disp_pitch_elems, float *vdisp,
+                            int32_t vdisp_pitch_elems, void *stream) {
+    if (!h) { set_err(g_thread_err, "handle is NULL"); return BDIS_E_INVALID_ARG; }
+    bdis_status st = check_pair(h, left, right, width, height, pitch_bytes, disp, disp_pitch_elems, h->prm.patch);
+    if (st != BDIS_OK) return st;
+    if (vdisp && vdisp_pitch_elems < width) { set_err(h->err, "vertical output pitch smaller than width"); return BDIS_E_INVALID_ARG; }
+    if (h->prm.patch > 8) { set_err(h->err, "the 2-D search takes patch sides up to 8 (got %d)", h->prm.patch); return BDIS_E_UNSUPPORTED; }
+    if (h->prm.fusion != BDIS_FUSION_BAYES || learned(h)) {
+        set_err(h->err, "the 2-D search runs the Bayesian fusion with the zero init");
+        return BDIS_E_UNSUPPORTED;
+    }
+    st = run_2d(h, left, right, width, height, pitch_bytes, disp, disp_pitch_elems, vdisp, vdisp_pitch_elems,
+                (hipStream_t)stream);
     h->have_last = false;
     return st;
 }

@@ -19,7 +19,7 @@ from dataclasses import dataclass
 import numpy as np
 from scipy.ndimage import gaussian_filter
 
-__all__ = ["StereoPair", "make_pair", "integer_shift_pair", "random_pair_tiny"]
+__all__ = ["StereoPair", "make_pair", "integer_shift_pair", "misaligned_pair", "random_pair_tiny"]
 
 
 @dataclass
@@ -164,6 +164,27 @@ def integer_shift_pair(W: int, H: int, s: int, seed: int) -> StereoPair:
     valid = (np.arange(W)[None, :] - s) >= 0
     valid = np.broadcast_to(valid, (H, W)).copy()
     return StereoPair(left, right, disp, valid, seed, float(s))
+
+
+def misaligned_pair(W: int, H: int, d_max: float, seed: int, v_max: float = 1.5):
+    """make_pair(W, H, d_max, seed) with an imperfect rectification: the
+    right image moved vertically by vf(x') = a + b (x' / (W - 1) - 1/2), a
+    small roll of the right camera, with a and b drawn uniformly from
+    [-v_max / 2, v_max / 2] (|vf| <= 3/4 v_max) from the stream PCG64([seed,
+    1]), and resampled with Keys bicubic interpolation.  Left (x, y) then
+    matches right (x - d, y + v) with v = vf(x - d).  Returns (pair, v) with
+    pair.right replaced and v the float32 vertical ground truth on the left
+    grid."""
+    pair = make_pair(W, H, d_max, seed)
+    rng = np.random.Generator(np.random.PCG64([seed, 1]))
+    a, b = (float(t) for t in rng.uniform(-0.5 * v_max, 0.5 * v_max, 2))
+    xs = np.arange(W, dtype=np.float64)
+    vf = a + b * (xs / max(W - 1, 1) - 0.5)
+    yy, xx = np.mgrid[0:H, 0:W].astype(np.float64)
+    right = _keys_cubic_2d(pair.right.astype(np.float64), xx, yy - vf[None, :])
+    pair.right = np.clip(np.rint(right), 0, 255).astype(np.uint8)
+    v = (a + b * ((xx - pair.disp) / max(W - 1, 1) - 0.5)).astype(np.float32)
+    return pair, v
 
 
 def random_pair_tiny(W: int, H: int, seed: int, lo=0, hi=256) -> tuple[np.ndarray, np.ndarray]:
