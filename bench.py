@@ -82,10 +82,10 @@ def dense_flops(pixels, taps):
 # WRITE_SIZE, scaled by a 256 MiB device copy (fetch x 1.9998, write x 1.0);
 # valid only for the kernel source they were taken on (sha256 prefix).
 KERNEL_SRC = os.path.join(ROOT, "paper_2106_07136_amd", "csrc", "bdis_kernels.hpp")
-MEASURED_TRAFFIC = {("lk_f64_p8_l0", "02f26ecdffb1884f"): 5579097}
+MEASURED_TRAFFIC = {("lk_f64_p8_l0", "dae8af00b954ca4c"): 5608790}
 # LDS bytes read + written per launch: rocprofv3 SQ_INSTS_LDS_LOAD_BANDWIDTH
 # + SQ_INSTS_LDS_STORE_BANDWIDTH (64-byte units), same validity rule.
-MEASURED_LDS = {("lk_f64_p8_l0", "02f26ecdffb1884f"): (1333382 + 228480) * 64}
+MEASURED_LDS = {("lk_f64_p8_l0", "dae8af00b954ca4c"): (1333382 + 228480) * 64}
 
 
 def _kernel_sha():
@@ -205,7 +205,9 @@ def profile_leg(name, calls, precision):
     mixed batch at patch 8 / stride 4 in the level graph; 'learned640' the 64
     held-out 640x480 pairs with the learned init (32 channels, 8 fine-level
     iterations), also in the level graph; 'plain640' the same pairs with the
-    plain init.  Prints one JSON line with the time per call.  The pairs are
+    plain init; 'search2d640' the 2-D search on the misaligned 640x480
+    headline pair, one pair per call.  Prints one JSON line with the time
+    per call.  The pairs are
     generated in this process, one after another: under a profiler the GPU
     is initialised before this function runs, and a forked worker pool would
     copy that state."""
@@ -223,8 +225,20 @@ def profile_leg(name, calls, precision):
         pn.set_params(flat)
         h = bdis.Bdis(bdis.Params(levels=0, iters=12, precision=precision, init=1, learned_iters=8))
         h.set_net(pn)
+    elif name == "search2d640":
+        import torch
+        mis, _ = synth.misaligned_pair(640, 480, 64.0, 2, v_max=6.0)
+        h = bdis.Bdis(bdis.Params(levels=5, iters=12, precision=precision))
+        L = torch.from_numpy(mis.left).cuda()
+        R = torch.from_numpy(mis.right).cuda()
+        d = torch.empty(L.shape, dtype=torch.float32, device=L.device)
+        v = torch.empty_like(d)
+        ms = timed(lambda: h.compute_2d(L, R, d, v), calls, 2)
+        print(json.dumps({"profile_leg": name, "calls": calls, "warmup": 2, "ms_per_call": ms,
+                          "mpixel_per_call": mis.left.size / 1e6, **accuracy([d], [mis])}), flush=True)
+        return
     else:
-        raise SystemExit(f"unknown --profile-leg {name!r}: batch, plain640 or learned640")
+        raise SystemExit(f"unknown --profile-leg {name!r}: batch, plain640, learned640 or search2d640")
     L, R, O, dm = _batch_io(pairs)
     ms = timed(lambda: h.compute_batch(L, R, O, max_disparity=dm), calls, 2)
     mpx = sum(p.left.size for p in pairs) / 1e6
@@ -468,6 +482,7 @@ def search2d_leg(steps, warmup, precision):
         m = np.isfinite(d2n) & pair.valid
         vt = vg if name == "misaligned" else np.zeros_like(d2n)
         a2["v_epe_px"] = float(np.abs(v2n[m] - vt[m]).mean())
+        a2["median_v_err_px"] = float(np.median(np.abs(v2n[m] - vt[m])))
         a2["median_d_err_px"] = float(np.median(np.abs(d2n[m] - pair.disp[m])))
         m1 = np.isfinite(d1.cpu().numpy()) & pair.valid
         a1["median_d_err_px"] = float(np.median(np.abs(d1.cpu().numpy()[m1] - pair.disp[m1])))
@@ -529,7 +544,7 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (scale for HBM byte counters) and exit")
-    ap.add_argument("--profile-leg", choices=("batch", "plain640", "learned640"), default=None,
+    ap.add_argument("--profile-leg", choices=("batch", "plain640", "learned640", "search2d640"), default=None,
                     help="only run this batched workload (for a profiler run) and exit")
     ap.add_argument("--profile-calls", type=int, default=50)
     args = ap.parse_args()
