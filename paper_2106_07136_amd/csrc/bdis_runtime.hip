@@ -705,20 +705,18 @@ void launch_one(bdis_t *h, const Launch &L, hipStream_t s) {
     case K_LK2: {
         const JobPack<Lk2Job> &pk = pack_of<Lk2Job>(L);
         const dim3 g(L.blocks), b(kBlock);
+        const bool w5 = L.kp.window <= 5;
+#define BDIS_LK2(PP, U, WW) hipLaunchKernelGGL((k_lk2d<T, PP, U, WW>), g, b, 0, s, pk, L.kp)
+#define BDIS_LK2_P(PP)                                                       \
+    if (L.u8) { if (w5) BDIS_LK2(PP, true, 5); else BDIS_LK2(PP, true, 9); } \
+    else { if (w5) BDIS_LK2(PP, false, 5); else BDIS_LK2(PP, false, 9); }
         switch (L.patch) {
-        case 4:
-            if (L.u8) hipLaunchKernelGGL((k_lk2d<T, 4, true>), g, b, 0, s, pk, L.kp);
-            else hipLaunchKernelGGL((k_lk2d<T, 4, false>), g, b, 0, s, pk, L.kp);
-            break;
-        case 6:
-            if (L.u8) hipLaunchKernelGGL((k_lk2d<T, 6, true>), g, b, 0, s, pk, L.kp);
-            else hipLaunchKernelGGL((k_lk2d<T, 6, false>), g, b, 0, s, pk, L.kp);
-            break;
-        default:
-            if (L.u8) hipLaunchKernelGGL((k_lk2d<T, 8, true>), g, b, 0, s, pk, L.kp);
-            else hipLaunchKernelGGL((k_lk2d<T, 8, false>), g, b, 0, s, pk, L.kp);
-            break;
+        case 4: BDIS_LK2_P(4) break;
+        case 6: BDIS_LK2_P(6) break;
+        default: BDIS_LK2_P(8) break;
         }
+#undef BDIS_LK2_P
+#undef BDIS_LK2
         break;
     }
     case K_DENSE2: {

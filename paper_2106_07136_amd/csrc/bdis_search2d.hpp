@@ -11,7 +11,7 @@
 // other lanes idle).  The right image is sampled bilinearly from global
 // memory (rows vary with v, so no row staging); the patch's taps are reused
 // across the iterations through L1.  Per-patch sums are wave reductions:
-// DPP inside each row of 16 lanes, then two cross-row exchanges.
+// DPP inside each row of 16 lanes, then the four row sums read by readlane.
 #pragma once
 #include "bdis_kernels.hpp"
 
@@ -48,21 +48,28 @@ __host__ __device__ constexpr int lk2_blocks(int nx, int ny) {
     return (nx * ny + kLk2PatchesPerBlock - 1) / kLk2PatchesPerBlock;
 }
 
-// Sum over the 64 lanes of a wave, every lane receiving the same bits (each
-// step adds a commuting pair).
+// Sum over the 64 lanes of a wave, every lane receiving the same bits: DPP
+// sums inside each row of 16 lanes, then the four row sums read from lanes
+// 0, 16, 32 and 48 and added in one fixed order.  All 64 lanes must be
+// active.
+__device__ __forceinline__ double lane_value(double v, int lane) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
+                            __builtin_amdgcn_readlane(__double2loint(v), lane));
+}
+__device__ __forceinline__ float lane_value(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
 template <int N, typename T>
 __device__ __forceinline__ void wave_sum_n(T *v) {
     seg_sum_n<16, N>(v);
 #pragma unroll
-    for (int i = 0; i < N; i++) v[i] += __shfl_xor(v[i], 16);
-#pragma unroll
-    for (int i = 0; i < N; i++) v[i] += __shfl_xor(v[i], 32);
+    for (int i = 0; i < N; i++)
+        v[i] = (lane_value(v[i], 0) + lane_value(v[i], 16)) + (lane_value(v[i], 32) + lane_value(v[i], 48));
 }
 __device__ __forceinline__ int wave_sum_i(int v) {
     v = seg_sum_i<16>(v);
-    v += __shfl_xor(v, 16);
-    v += __shfl_xor(v, 32);
-    return v;
+    return (__builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16)) +
+           (__builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48));
 }
 
 // Image value (|x| above level 0) and validity at (x, y), in the row.
@@ -86,7 +93,7 @@ __device__ __forceinline__ T sample2(const void *img, int pitch, int W, int H, T
     return bilinear_mix<T>(f00, f01, f10, f11, fx, fy);
 }
 
-template <typename T, int P, bool U8>
+template <typename T, int P, bool U8, int WN>
 __global__ __launch_bounds__(kBlock) void k_lk2d(const JobPack<Lk2Job> pk, KParams kp) {
     static_assert(P * P <= 64, "one lane per patch pixel");
     const Lk2Job &J = pk.j[find_job(pk, (int)blockIdx.x)];
@@ -131,6 +138,7 @@ __global__ __launch_bounds__(kBlock) void k_lk2d(const JobPack<Lk2Job> pk, KPara
         status = ST_DEGENERATE;
     } else {
         T step = 0;
+        const T idet = T(1) / det;
         for (int t = 0; t < kp.iters; t++) {
             bool ok;
             const T I = sample2<T, U8>(J.R, J.pitch, W, H, (T)x + u, (T)y + v, kp, ok);
@@ -138,7 +146,7 @@ __global__ __launch_bounds__(kBlock) void k_lk2d(const JobPack<Lk2Job> pk, KPara
             // sum J d equals sum J (d - mean d): the Jacobian sums to zero
             T b[2] = {jxv * d, jyv * d};
             wave_sum_n<2>(b);
-            const T du = (hyy * b[0] - hxy * b[1]) / det, dv = (hxx * b[1] - hxy * b[0]) / det;
+            const T du = (hyy * b[0] - hxy * b[1]) * idet, dv = (hxx * b[1] - hxy * b[0]) * idet;
             step = fmax(fabs(du), fabs(dv));
             u -= du;
             v -= dv;
@@ -150,7 +158,6 @@ __global__ __launch_bounds__(kBlock) void k_lk2d(const JobPack<Lk2Job> pk, KPara
             // window posterior along x at the converged v (two passes: the
             // mean of each sample's residuals, then the centred energies)
             const int cw = (kp.window - 1) / 2;
-            constexpr int WN = 9;
             T dres[WN], s[WN];
 #pragma unroll
             for (int i = 0; i < WN; i++) {
@@ -164,18 +171,23 @@ __global__ __launch_bounds__(kBlock) void k_lk2d(const JobPack<Lk2Job> pk, KPara
                 s[i] = dres[i];
             }
             wave_sum_n<WN>(s);
+            const T ninv = T(1) / (T)n;
 #pragma unroll
             for (int i = 0; i < WN; i++) {
-                const T q = val ? dres[i] - s[i] / (T)n : T(0);
+                const T q = val ? dres[i] - s[i] * ninv : T(0);
                 s[i] = q * q;
             }
             wave_sum_n<WN>(s);
-            T term = 0;
-            if (lane < kp.window) {
+            // lane i < window evaluates the term of sample i (one exponential
+            // per lane); the centre term is 1
+            T Ec = s[0], Ei = s[0];
 #pragma unroll
-                for (int i = 0; i < WN; i++)
-                    if (i == lane) term = i == cw ? T(1) : exp(-(s[i] - s[cw]) * (T)kp.inv_tau);
+            for (int i = 1; i < WN; i++) {
+                if (i == cw) Ec = s[i];
+                if (i == lane) Ei = s[i];
             }
+            const T e = exp(-(Ei - Ec) * (T)kp.inv_tau);
+            const T term = lane < kp.window ? (lane == cw ? T(1) : e) : T(0);
             T tsum[1] = {term};
             wave_sum_n<1>(tsum);
             post = T(1) / tsum[0];
