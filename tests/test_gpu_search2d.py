@@ -89,6 +89,31 @@ def test_misaligned_pair_parity(torch_cuda, ref, name):
     _both(torch_cuda, ref, gp, pair.left, pair.right, name)
 
 
+def test_wide_window_parity(torch_cuda, ref):
+    """Nine window samples 0.25 px apart (the kernel's wider window bound)
+    and s = patch side in eq. (4)."""
+    from paper_2106_07136_amd import bdis
+    pair, _ = synth.misaligned_pair(160, 120, 16.0, 3, v_max=2.0)
+    gp = bdis.Params(levels=3, iters=10, window=9, window_step=0.25, s_mode=1)
+    _both(torch_cuda, ref, gp, pair.left, pair.right, "window 9")
+
+
+@pytest.mark.parametrize("sx,sy", [(3, -2), (0, 1)])
+def test_fp32_recovers_integer_2d_shift(torch_cuda, sx, sy):
+    """FP32 (precision = 1, not held to the parity bar, as for the 1-D path):
+    the 2-D search still recovers a whole-pixel 2-D shift away from the
+    borders."""
+    from paper_2106_07136_amd import bdis
+    L = synth.integer_shift_pair(128, 96, 0, seed=21).left
+    R = _shift2d(L, sx, sy)
+    _, d, v = _run2d(torch_cuda, bdis.Params(levels=3, iters=12, precision=1), L, R)
+    m = 12
+    di, vi = d[m:-m, m + abs(sx):-m - abs(sx)], v[m:-m, m + abs(sx):-m - abs(sx)]
+    fin = np.isfinite(di)
+    assert fin.mean() > 0.98
+    assert (np.abs(di[fin] - sx) <= 1e-3).mean() >= 0.98 and (np.abs(vi[fin] + sy) <= 1e-3).mean() >= 0.98
+
+
 def test_one_level_padded_pitch(torch_cuda, ref):
     """A single level (level 0 is also the coarsest: zero initial field)
     with padded input rows and output rows, whose padding stays untouched."""
