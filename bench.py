@@ -54,6 +54,15 @@ def lk_flops(patches, patch, iters, window):
     return patches * patch * patch * (6 + 5 * iters + 7 * window)
 
 
+def lk2d_flops(patches, patch, iters, window):
+    """Algorithmic FLOPs of the 2-D LK + posterior kernel: per patch pixel 12
+    of set-up (two gradients, their means removed, three Hessian products),
+    14 per iteration (bilinear sample 9, residual 1, two products and sums
+    4) and 13 per window sample (bilinear 9, residual 1, centring and square
+    3)."""
+    return patches * patch * patch * (12 + 14 * iters + 13 * window)
+
+
 def lk_bytes(W, H, patches, esz, level0, coarse_px, fold=None):
     """Algorithmic bytes of one LK launch: both level images read once
     (uint8 at level 0, esz-byte elements above), the per-patch records
@@ -497,6 +506,15 @@ def search2d_leg(steps, warmup, precision):
     prof = h.profile()
     h.set_profiling(False)
     res["kernels"] = {k: {"launches": n, "avg_us": t / n * 1e3} for k, (n, t) in prof.items()}
+    # roofline of the dominant launch, the level-0 2-D LK (HIP events on its stream)
+    info = bdis.plan(prm, 640, 480)
+    n0, t0 = prof["lk2d_f64_p8_l0" if precision == 0 else "lk2d_f32_p8_l0"]
+    avg_s = t0 / n0 / 1e3
+    fl = lk2d_flops(info["nx"][0] * info["ny"][0], 8, 12, prm.window)
+    peak = PEAK_FP64_VECTOR if precision == 0 else PEAK_FP32_VECTOR
+    res["roofline"] = {"kernel": "lk2d_l0", "bound": "alu", "achieved": fl / avg_s / 1e12, "peak": peak / 1e12,
+                       "unit": "TFLOP/s", "frac": fl / avg_s / peak, "traffic": None, "algorithmic_flops": fl,
+                       "avg_us": avg_s * 1e6}
     h.close()
     return res
 
