@@ -104,7 +104,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+            raise ImportError(f"{LIB_PATH} is not built; run paper_2106_07136_amd.build.build()")
         L = C.CDLL(LIB_PATH)
         vp, i32 = C.c_void_p, C.c_int32
         L.bdis_default_params.argtypes = [C.POINTER(CParams)]
