@@ -89,6 +89,24 @@ def test_misaligned_pair_parity(torch_cuda, ref, name):
     _both(torch_cuda, ref, gp, pair.left, pair.right, name)
 
 
+def test_large_pair_parity(torch_cuda, ref):
+    """1280 x 720, six levels, up to 3 px of vertical offset: element parity
+    beyond the headline size."""
+    from paper_2106_07136_amd import bdis
+    pair, _ = synth.misaligned_pair(1280, 720, 128.0, 3001, v_max=4.0)
+    gp = bdis.Params(levels=6, iters=12)
+    _both(torch_cuda, ref, gp, pair.left, pair.right, "1280x720")
+
+
+def test_without_convergence_test_parity(torch_cuda, ref):
+    """conv_tol = 0: only a non-finite translation or one that moved more
+    than a patch side is discarded (the convergence test switched off)."""
+    from paper_2106_07136_amd import bdis
+    pair, _ = synth.misaligned_pair(160, 120, 16.0, 5, v_max=1.5)
+    gp = bdis.Params(levels=3, iters=8, conv_tol=0.0)
+    _both(torch_cuda, ref, gp, pair.left, pair.right, "conv_tol 0")
+
+
 def test_wide_window_parity(torch_cuda, ref):
     """Nine window samples 0.25 px apart (the kernel's wider window bound)
     and s = patch side in eq. (4)."""
