@@ -139,6 +139,33 @@ def test_stage_parity_small(torch_cuda, ref):
         assert np.abs(w - t["post"])[kept].max() <= 1e-4
 
 
+@pytest.mark.parametrize("W,H,levels", [(640, 480, 5), (333, 257, 5), (136, 130, 5), (1280, 720, 6),
+                                          (1920, 1080, 7)])
+def test_pyramid_levels_exact(torch_cuda, ref, W, H, levels):
+    """Every pyramid level of both images, values and validity, equal to
+    the oracle's: bit for bit in FP64 up to level 5 (dyadic sums of 8-bit
+    values are exact there), within rounding beyond it.  With at least five
+    levels one pair takes levels 1-4 from the four-level launch (and deeper
+    levels from the two-level one): tiles at odd sizes and at borders, where
+    the regions hold reflected values."""
+    from paper_2106_07136_amd import bdis
+    print(f"case {W}x{H} levels {levels}", flush=True)
+    pair = synth.make_pair(W, H, 0.1 * W, 4242 + W)
+    h, _ = _run(torch_cuda, bdis.Params(levels=levels, iters=4), pair.left, pair.right)
+    for stage, img in ((bdis.STAGE_PYR_L, pair.left), (bdis.STAGE_PYR_R, pair.right)):
+        v = img.astype(np.float64)
+        m = ref.mask_base(img)
+        for l in range(1, levels):
+            v = ref.blur_decimate(v)
+            m = ref.mask_down(m)
+            g = h.debug_stage(stage, l)
+            if l <= 5:
+                np.testing.assert_array_equal(np.abs(g), v)
+            else:
+                np.testing.assert_allclose(np.abs(g), v, rtol=1e-14, atol=0)
+            np.testing.assert_array_equal(~np.signbit(g), m.astype(bool))
+
+
 @pytest.mark.parametrize("s", [2, 7])
 def test_integer_shift_recovered(torch_cuda, s):
     from paper_2106_07136_amd import bdis
