@@ -461,7 +461,7 @@ def rectified_leg(pair, steps, warmup, precision):
     return res
 
 
-def search2d_leg(steps, warmup, precision):
+def search2d_leg(steps, warmup, precision, batch=None):
     """The 2-D (x, y) patch search against the 1-D search on the headline
     pair taken with an imperfect rectification (synth.misaligned_pair, seed
     2, up to 6 px of roll: a vertical offset of 1.1-3.4 px across the
@@ -516,6 +516,23 @@ def search2d_leg(steps, warmup, precision):
                        "unit": "TFLOP/s", "frac": fl / avg_s / peak, "traffic": None, "algorithmic_flops": fl,
                        "avg_us": avg_s * 1e6}
     h.close()
+    if batch is not None:
+        # the 64-pair mixed batch (aligned pairs): 2-D against 1-D batches
+        hb = bdis.Bdis(bdis.Params(levels=0, iters=12, precision=precision))
+        L, R, O, dm = _batch_io(batch)
+        V = [torch.empty_like(o) for o in O]
+        O1 = [torch.empty_like(o) for o in O]
+        ms2 = timed(lambda: hb.compute_batch_2d(L, R, O, V, max_disparity=dm), max(2, steps // 5), 2)
+        ms1 = timed(lambda: hb.compute_batch(L, R, O1, max_disparity=dm), max(2, steps // 5), 2)
+        mpx = sum(p.left.size for p in batch) / 1e6
+        res["batched"] = {"workload": "the 64-pair mixed batch (24x320x240, 24x640x480, 16x1280x720), levels from "
+                                      "each pair's max_disparity, patch 8, stride 4, 12 iterations",
+                          "search_2d": {"ms_per_batch": ms2, "value": mpx / (ms2 / 1e3), "unit": "Mpixel/s",
+                                        "accuracy": accuracy(O, batch)},
+                          "search_1d": {"ms_per_batch": ms1, "value": mpx / (ms1 / 1e3), "unit": "Mpixel/s",
+                                        "accuracy": accuracy(O1, batch)}}
+        log(f"bench: batched 2-D search {ms2:.3f} ms, 1-D {ms1:.3f} ms per 64 pairs")
+        hb.close()
     return res
 
 
@@ -700,7 +717,7 @@ def main():
             "per call, plain vs learned init (48-channel proposal net)")
         res["convergence_test"] = conv_tol_leg(pair, held, args.precision)
         res["rectified_pipeline"] = rectified_leg(pair, 50, 5, args.precision)
-        res["search_2d"] = search2d_leg(50, 5, args.precision)
+        res["search_2d"] = search2d_leg(50, 5, args.precision, batch)
         res["ablation_dis_vs_bdis"] = {
             "workload": "16 640x480 pairs per variant (diffuse: no gain field, no specular blobs, seeds "
                         "95000-95015; non-Lambertian: the full generator, seeds 95100-95115), BDIS against "

@@ -193,6 +193,26 @@ BDIS_API bdis_status bdis_compute_2d(bdis_t *h, const uint8_t *left, const uint8
                                      int32_t height, int32_t pitch_bytes, float *disp, int32_t disp_pitch_elems,
                                      float *vdisp, int32_t vdisp_pitch_elems, void *stream);
 
+/* One pair for bdis_compute_batch_2d: bdis_pair's fields and the vertical
+ * output (device float32, NULL for none, vdisp_pitch_elems >= width). */
+typedef struct {
+    const uint8_t *left;
+    const uint8_t *right;
+    float *disp;
+    float *vdisp;
+    int32_t width, height, pitch_bytes, disp_pitch_elems, vdisp_pitch_elems;
+    float max_disparity;
+} bdis_pair2d;
+
+/* bdis_compute_2d for n independent pairs of mixed sizes (1 <= n <= 4096)
+ * in one pass: per level, one 2-D LK launch and one densification launch
+ * for the pairs that have the level (at most 24 and 16 pairs a launch).
+ * Each pair gets its own level count from its max_disparity (0: the
+ * handle's) and the handle's patch and stride.  Results equal
+ * bdis_compute_2d's pair by pair, bit for bit.  Errors: as
+ * bdis_compute_2d; pairs are checked before anything is enqueued. */
+BDIS_API bdis_status bdis_compute_batch_2d(bdis_t *h, const bdis_pair2d *pairs, int32_t n, void *stream);
+
 /* The same for n independent pairs of mixed sizes in one pass: each kernel of
  * the path is launched once for all pairs (level by level, coarsest first).
  * `pairs` is a HOST array of n entries, read during the call only.  Each

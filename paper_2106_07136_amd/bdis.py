@@ -42,6 +42,12 @@ class CPair(C.Structure):
                 ("disp_pitch_elems", C.c_int32), ("max_disparity", C.c_float)]
 
 
+class CPair2d(C.Structure):
+    _fields_ = [("left", C.c_void_p), ("right", C.c_void_p), ("disp", C.c_void_p), ("vdisp", C.c_void_p),
+                ("width", C.c_int32), ("height", C.c_int32), ("pitch_bytes", C.c_int32),
+                ("disp_pitch_elems", C.c_int32), ("vdisp_pitch_elems", C.c_int32), ("max_disparity", C.c_float)]
+
+
 class CCamera(C.Structure):
     _fields_ = [(n, C.c_double) for n in ("fx", "fy", "cx", "cy", "k1", "k2", "p1", "p2", "k3")] + \
                [("R", C.c_double * 9)] + [(n, C.c_double) for n in ("nfx", "nfy", "ncx", "ncy")]
@@ -116,6 +122,7 @@ def lib():
         L.bdis_compute.argtypes = [vp, vp, vp, i32, i32, i32, vp, i32, vp]
         L.bdis_compute_noalloc.argtypes = [vp, vp, vp, i32, i32, i32, vp, i32, vp]
         L.bdis_compute_2d.argtypes = [vp, vp, vp, i32, i32, i32, vp, i32, vp, i32, vp]
+        L.bdis_compute_batch_2d.argtypes = [vp, C.POINTER(CPair2d), i32, vp]
         L.bdis_compute_batch.argtypes = [vp, C.POINTER(CPair), i32, vp]
         L.bdis_set_tuning.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
         L.bdis_debug_stage.argtypes = [vp, i32, i32, vp, C.c_size_t]
@@ -135,7 +142,7 @@ def lib():
         L.bdis_last_error.argtypes = [vp]
         L.bdis_last_error.restype = C.c_char_p
         for name in ("bdis_plan", "bdis_create", "bdis_set_params", "bdis_reserve", "bdis_compute",
-                     "bdis_compute_noalloc", "bdis_compute_2d",
+                     "bdis_compute_noalloc", "bdis_compute_2d", "bdis_compute_batch_2d",
                      "bdis_compute_batch", "bdis_set_tuning", "bdis_debug_stage",
                      "bdis_set_profiling", "bdis_get_profile", "bdis_set_batch_mode",
                      "bdis_batch_error", "bdis_set_net", "bdis_net_input", "bdis_set_fold_densify",
@@ -249,6 +256,33 @@ class Bdis:
                                      out.data_ptr(), out.stride(0), vout.data_ptr() if vout is not None else None,
                                      vout.stride(0) if vout is not None else 0, _stream_ptr(stream)), self._h)
         return out, vout
+
+    def compute_batch_2d(self, lefts, rights, outs=None, vouts=None, stream=None, max_disparity=None,
+                         with_v=True):
+        """The 2-D search on n pairs of mixed sizes in one pass; returns
+        (disparities, vertical offsets), vertical offsets None with
+        with_v=False.  max_disparity: optional per-pair list (0 = the
+        handle's)."""
+        import torch
+        n = len(lefts)
+        if outs is None:
+            outs = [torch.empty(l.shape, dtype=torch.float32, device=l.device) for l in lefts]
+        if vouts is None:
+            vouts = [torch.empty(l.shape, dtype=torch.float32, device=l.device) if with_v else None for l in lefts]
+        arr = (CPair2d * n)()
+        for i, (l, r, o, v) in enumerate(zip(lefts, rights, outs, vouts)):
+            if l.dtype != torch.uint8 or r.dtype != torch.uint8 or l.shape != r.shape:
+                raise ValueError(f"pair {i}: uint8 tensors of equal shape required")
+            if l.stride(1) != 1 or l.stride(0) != r.stride(0) or o.stride(1) != 1:
+                raise ValueError(f"pair {i}: rows must be contiguous with equal pitch")
+            if v is not None and (v.dtype != torch.float32 or v.shape != l.shape or v.stride(1) != 1):
+                raise ValueError(f"pair {i}: vertical output must be float32 of the image's shape")
+            dm = 0.0 if max_disparity is None else float(max_disparity[i])
+            arr[i] = CPair2d(l.data_ptr(), r.data_ptr(), o.data_ptr(), v.data_ptr() if v is not None else None,
+                             l.shape[1], l.shape[0], l.stride(0), o.stride(0), v.stride(0) if v is not None else 0,
+                             dm)
+        _check(lib().bdis_compute_batch_2d(self._h, arr, n, _stream_ptr(stream)), self._h)
+        return outs, vouts
 
     def set_net(self, net):
         """Attach a paper_2106_07136_amd.net.ProposalNet (None detaches); it is

@@ -1204,73 +1204,108 @@ size_t pair_ws2_bytes(const Geo &g, size_t esz, PairWs2 *w, char *base) {
     return off;
 }
 
-// The 2-D search on one pair: pyramid, then per level (coarsest first) the
-// 2-D LK launch and the two-field densification.
-bdis_status run_2d(bdis_t *h, const uint8_t *left, const uint8_t *right, int W, int H, int pitch, float *disp,
-                   int dpitch, float *vdisp, int vpitch, hipStream_t s) {
+// The 2-D search on a set of pairs (geometry already made, each pair's
+// vertical output and pitch in vout): pyramids, then per level (coarsest
+// first) the 2-D LK launch and the two-field densification of every pair
+// that has the level, at most a pack of jobs per launch.
+bdis_status run_2d(bdis_t *h, std::vector<PairIn> &ps, const std::vector<std::pair<float *, int>> &vout,
+                   hipStream_t s) {
     DeviceGuard dg(h->device);
     const bdis_params &prm = h->prm;
     const bool f64 = prm.precision == 0;
     const size_t esz = esize(prm);
-    PairIn p;
-    p.left = left; p.right = right; p.disp = disp;
-    p.W = W; p.H = H; p.pitch = pitch; p.dpitch = dpitch;
-    p.patch = prm.patch; p.stride = prm.stride; p.dmax = prm.max_disparity;
-    if (!make_geo(W, H, p.patch, p.stride, requested_levels(prm, p.dmax), p.g)) {
-        set_err(h->err, "image %dx%d smaller than patch %d", W, H, p.patch);
-        return BDIS_E_INVALID_ARG;
-    }
-    const size_t need = align_up(pair_ws2_bytes(p.g, esz, nullptr, nullptr));
+    size_t need = 0;
+    for (const PairIn &p : ps) need += align_up(pair_ws2_bytes(p.g, esz, nullptr, nullptr));
     bdis_status st = ensure_ws(h, need);
     if (st != BDIS_OK) return st;
-    PairWs2 w;
-    (void)pair_ws2_bytes(p.g, esz, &w, h->ws);
-    // the 1-D carve's pyramid pointers feed the shared pyramid planner
-    memset(&p.ws, 0, sizeof p.ws);
-    for (int l = 1; l < p.g.L; l++) { p.ws.pyr_l[l] = w.pyr_l[l]; p.ws.pyr_r[l] = w.pyr_r[l]; }
-    std::vector<PairIn> one{p};
+    std::vector<PairWs2> ws(ps.size());
+    int Lmax = 0;
+    size_t off = 0;
+    for (size_t i = 0; i < ps.size(); i++) {
+        PairIn &p = ps[i];
+        off += align_up(pair_ws2_bytes(p.g, esz, &ws[i], h->ws + off));
+        // the pyramid pointers feed the shared pyramid planner
+        memset(&p.ws, 0, sizeof p.ws);
+        for (int l = 1; l < p.g.L; l++) { p.ws.pyr_l[l] = ws[i].pyr_l[l]; p.ws.pyr_r[l] = ws[i].pyr_r[l]; }
+        Lmax = std::max(Lmax, p.g.L);
+    }
     std::vector<Launch> ls;
-    const KParams kp = make_kparams(prm, p.patch);
-    plan_pyramid(ls, one, p.g.Lp, f64, kp);
-    const void *gt = f64 ? (const void *)(h->gtab_d + gtab_offset(p.patch)) : (const void *)(h->gtab_f + gtab_offset(p.patch));
-    for (int l = p.g.L - 1; l >= 0; l--) {
-        const bool coarsest = l == p.g.L - 1;
-        Lk2Job j{};
-        j.L = l == 0 ? (const void *)left : w.pyr_l[l];
-        j.R = l == 0 ? (const void *)right : w.pyr_r[l];
-        j.Uc = coarsest ? nullptr : w.U[l + 1];
-        j.Vc = coarsest ? nullptr : w.V[l + 1];
-        j.rec_u = w.rec_u[l]; j.rec_v = w.rec_v[l]; j.rec_w = w.rec_w[l]; j.rec_st = w.rec_st[l];
-        j.pitch = l == 0 ? pitch : p.g.W[l];
-        j.W = p.g.W[l]; j.H = p.g.H[l];
-        j.Wc = coarsest ? 0 : p.g.W[l + 1]; j.Hc = coarsest ? 0 : p.g.H[l + 1];
-        j.nx = p.g.nx[l]; j.ny = p.g.ny[l]; j.stride = p.stride;
-        std::vector<Lk2Job> lj{j};
-        append(ls, K_LK2, l, p.patch, l == 0, f64, lj, kp, [](const Lk2Job &q) { return lk2_blocks(q.nx, q.ny); });
-        Dense2Job d{};
-        for (int f = 0; f < 2; f++) {
-            DenseView &D = f == 0 ? d.du : d.dv;
-            D.L = j.L; D.R = j.R;
-            D.rec_u = f == 0 ? w.rec_u[l] : w.rec_v[l];
-            D.rec_w = w.rec_w[l];
-            D.gtab = gt;
-            D.Uc = coarsest ? nullptr : (f == 0 ? w.U[l + 1] : w.V[l + 1]);
-            D.pitch = j.pitch; D.W = j.W; D.H = j.H; D.patch = p.patch; D.stride = p.stride;
-            D.nx = j.nx; D.ny = j.ny; D.Wc = j.Wc; D.Hc = j.Hc;
-            D.mode = l == 0 ? 2 : (coarsest ? 1 : 0);
+    const KParams kp = make_kparams(prm, prm.patch);
+    plan_pyramid(ls, ps, Lmax, f64, kp);
+    const void *gt = f64 ? (const void *)(h->gtab_d + gtab_offset(prm.patch))
+                         : (const void *)(h->gtab_f + gtab_offset(prm.patch));
+    for (int l = Lmax - 1; l >= 0; l--) {
+        std::vector<Lk2Job> lj;
+        std::vector<Dense2Job> dj;
+        for (size_t i = 0; i < ps.size(); i++) {
+            const PairIn &p = ps[i];
+            const PairWs2 &w = ws[i];
+            if (p.g.L <= l) continue;
+            const bool coarsest = l == p.g.L - 1;
+            Lk2Job j{};
+            j.L = l == 0 ? (const void *)p.left : w.pyr_l[l];
+            j.R = l == 0 ? (const void *)p.right : w.pyr_r[l];
+            j.Uc = coarsest ? nullptr : w.U[l + 1];
+            j.Vc = coarsest ? nullptr : w.V[l + 1];
+            j.rec_u = w.rec_u[l]; j.rec_v = w.rec_v[l]; j.rec_w = w.rec_w[l]; j.rec_st = w.rec_st[l];
+            j.pitch = l == 0 ? p.pitch : p.g.W[l];
+            j.W = p.g.W[l]; j.H = p.g.H[l];
+            j.Wc = coarsest ? 0 : p.g.W[l + 1]; j.Hc = coarsest ? 0 : p.g.H[l + 1];
+            j.nx = p.g.nx[l]; j.ny = p.g.ny[l]; j.stride = p.stride;
+            lj.push_back(j);
+            Dense2Job d{};
+            for (int f = 0; f < 2; f++) {
+                DenseView &D = f == 0 ? d.du : d.dv;
+                D.L = j.L; D.R = j.R;
+                D.rec_u = f == 0 ? w.rec_u[l] : w.rec_v[l];
+                D.rec_w = w.rec_w[l];
+                D.gtab = gt;
+                D.Uc = coarsest ? nullptr : (f == 0 ? w.U[l + 1] : w.V[l + 1]);
+                D.pitch = j.pitch; D.W = j.W; D.H = j.H; D.patch = p.patch; D.stride = p.stride;
+                D.nx = j.nx; D.ny = j.ny; D.Wc = j.Wc; D.Hc = j.Hc;
+                D.mode = l == 0 ? 2 : (coarsest ? 1 : 0);
+            }
+            d.Uo = l == 0 ? nullptr : w.U[l];
+            d.Vo = l == 0 ? nullptr : w.V[l];
+            d.out_d = l == 0 ? p.disp : nullptr;
+            d.out_v = l == 0 ? vout[i].first : nullptr;
+            d.out_pitch = p.dpitch; d.vout_pitch = vout[i].second;
+            dj.push_back(d);
         }
-        d.Uo = l == 0 ? nullptr : w.U[l];
-        d.Vo = l == 0 ? nullptr : w.V[l];
-        d.out_d = l == 0 ? disp : nullptr;
-        d.out_v = l == 0 ? vdisp : nullptr;
-        d.out_pitch = dpitch; d.vout_pitch = vpitch;
-        std::vector<Dense2Job> dj{d};
+        append(ls, K_LK2, l, prm.patch, l == 0, f64, lj, kp,
+               [](const Lk2Job &q) { return lk2_blocks(q.nx, q.ny); });
         append(ls, K_DENSE2, l, 0, l == 0, f64, dj, kp,
                [](const Dense2Job &q) { return (q.du.W * q.du.H + kBlock - 1) / kBlock; });
     }
     st = launch_all(h, ls, s);
     if (st != BDIS_OK) return st;
     HIPCHK(h, hipGetLastError());
+    return BDIS_OK;
+}
+
+// Checks that the handle's parameters suit the 2-D search.
+bdis_status check_2d(bdis_t *h) {
+    if (h->prm.patch > 8) {
+        set_err(h->err, "the 2-D search takes patch sides up to 8 (got %d)", h->prm.patch);
+        return BDIS_E_UNSUPPORTED;
+    }
+    if (h->prm.fusion != BDIS_FUSION_BAYES || learned(h)) {
+        set_err(h->err, "the 2-D search runs the Bayesian fusion with the zero init");
+        return BDIS_E_UNSUPPORTED;
+    }
+    return BDIS_OK;
+}
+
+// One 2-D pair's geometry: the handle's patch and stride, levels from dmax.
+bdis_status make_pair_2d(bdis_t *h, PairIn &p, const uint8_t *left, const uint8_t *right, int W, int H, int pitch,
+                         float *disp, int dpitch, float dmax) {
+    p.left = left; p.right = right; p.disp = disp;
+    p.W = W; p.H = H; p.pitch = pitch; p.dpitch = dpitch;
+    p.patch = h->prm.patch; p.stride = h->prm.stride; p.dmax = dmax;
+    if (!make_geo(W, H, p.patch, p.stride, requested_levels(h->prm, p.dmax), p.g)) {
+        set_err(h->err, "image %dx%d smaller than patch %d", W, H, p.patch);
+        return BDIS_E_INVALID_ARG;
+    }
     return BDIS_OK;
 }
 
@@ -1472,13 +1507,43 @@ bdis_status bdis_compute_2d(bdis_t *h, const uint8_t *left, const uint8_t *right
     bdis_status st = check_pair(h, left, right, width, height, pitch_bytes, disp, disp_pitch_elems, h->prm.patch);
     if (st != BDIS_OK) return st;
     if (vdisp && vdisp_pitch_elems < width) { set_err(h->err, "vertical output pitch smaller than width"); return BDIS_E_INVALID_ARG; }
-    if (h->prm.patch > 8) { set_err(h->err, "the 2-D search takes patch sides up to 8 (got %d)", h->prm.patch); return BDIS_E_UNSUPPORTED; }
-    if (h->prm.fusion != BDIS_FUSION_BAYES || learned(h)) {
-        set_err(h->err, "the 2-D search runs the Bayesian fusion with the zero init");
-        return BDIS_E_UNSUPPORTED;
+    if ((st = check_2d(h)) != BDIS_OK) return st;
+    std::vector<PairIn> ps(1);
+    st = make_pair_2d(h, ps[0], left, right, width, height, pitch_bytes, disp, disp_pitch_elems,
+                      h->prm.max_disparity);
+    if (st != BDIS_OK) return st;
+    std::vector<std::pair<float *, int>> vout{{vdisp, vdisp_pitch_elems}};
+    st = run_2d(h, ps, vout, (hipStream_t)stream);
+    h->have_last = false;
+    return st;
+}
+
+bdis_status bdis_compute_batch_2d(bdis_t *h, const bdis_pair2d *pairs, int32_t n, void *stream) {
+    if (!h) { set_err(g_thread_err, "handle is NULL"); return BDIS_E_INVALID_ARG; }
+    if (!pairs || n < 1 || n > 4096) { set_err(h->err, "need 1 <= n <= 4096 pairs"); return BDIS_E_INVALID_ARG; }
+    bdis_status st = check_2d(h);
+    if (st != BDIS_OK) return st;
+    std::vector<PairIn> ps(n);
+    std::vector<std::pair<float *, int>> vout(n);
+    for (int i = 0; i < n; i++) {
+        const bdis_pair2d &q = pairs[i];
+        st = check_pair(h, q.left, q.right, q.width, q.height, q.pitch_bytes, q.disp, q.disp_pitch_elems,
+                        h->prm.patch);
+        if (st != BDIS_OK) return st;
+        if (q.vdisp && q.vdisp_pitch_elems < q.width) {
+            set_err(h->err, "pair %d: vertical output pitch smaller than width", i);
+            return BDIS_E_INVALID_ARG;
+        }
+        if (!(q.max_disparity >= 0.f) || !std::isfinite(q.max_disparity)) {
+            set_err(h->err, "pair %d: max_disparity must be >= 0", i);
+            return BDIS_E_INVALID_ARG;
+        }
+        st = make_pair_2d(h, ps[i], q.left, q.right, q.width, q.height, q.pitch_bytes, q.disp, q.disp_pitch_elems,
+                          q.max_disparity > 0.f ? q.max_disparity : h->prm.max_disparity);
+        if (st != BDIS_OK) return st;
+        vout[i] = {q.vdisp, q.vdisp_pitch_elems};
     }
-    st = run_2d(h, left, right, width, height, pitch_bytes, disp, disp_pitch_elems, vdisp, vdisp_pitch_elems,
-                (hipStream_t)stream);
+    st = run_2d(h, ps, vout, (hipStream_t)stream);
     h->have_last = false;
     return st;
 }

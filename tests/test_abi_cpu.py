@@ -111,6 +111,16 @@ def test_create_without_gpu_reports_no_device():
     assert e.value.status == bdis.E_INVALID_ARG
 
 
+def test_pair_structs_match_the_header():
+    """bdis_pair: three pointers, four int32 and a float (then 4 bytes of
+    tail padding); bdis_pair2d: four pointers, five int32 and a float."""
+    import ctypes as C
+    assert C.sizeof(bdis.CPair) == 3 * 8 + 4 * 4 + 4 + 4  # trailing pad to 8
+    assert C.sizeof(bdis.CPair2d) == 4 * 8 + 5 * 4 + 4
+    txt = open(os.path.join(ROOT, "include", "bdis.h")).read()
+    assert "bdis_pair2d" in txt and "bdis_compute_batch_2d" in txt
+
+
 def test_geometry_structs_match_the_header():
     """bdis_camera is 22 doubles and bdis_rectify_job two pointers, six
     int32 and a camera, with no padding (the kernels take them by value)."""

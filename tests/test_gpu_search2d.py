@@ -179,6 +179,58 @@ def test_without_vertical_output(torch_cuda, ref):
     np.testing.assert_array_equal(d_a.cpu().numpy().view(np.uint32), d_b.cpu().numpy().view(np.uint32))
 
 
+def _batch_inputs(torch, spec):
+    pairs = [synth.misaligned_pair(W, H, dm, seed, v_max=vm)[0] for (W, H, dm, seed, vm) in spec]
+    L = [torch.from_numpy(p.left).cuda() for p in pairs]
+    R = [torch.from_numpy(p.right).cuda() for p in pairs]
+    return pairs, L, R
+
+
+def test_batch_equals_single_pairs_and_oracle(torch_cuda, ref):
+    """bdis_compute_batch_2d on pairs of mixed sizes (one without a vertical
+    output) equals bdis_compute_2d pair by pair, bit for bit, and the oracle
+    to the parity bar."""
+    from paper_2106_07136_amd import bdis
+    torch = torch_cuda
+    spec = [(160, 120, 16.0, 1, 1.5), (203, 97, 20.0, 7, 3.0), (320, 240, 32.0, 9, 4.0), (96, 64, 6.0, 11, 1.0)]
+    pairs, L, R = _batch_inputs(torch, spec)
+    gp = bdis.Params(levels=3, iters=10)
+    h = bdis.Bdis(gp)
+    vouts = [torch.empty(l.shape, dtype=torch.float32, device="cuda") for l in L]
+    vouts[3] = None
+    D, V = h.compute_batch_2d(L, R, vouts=vouts)
+    torch.cuda.synchronize()
+    assert V[3] is None
+    for i, p in enumerate(pairs):
+        d1, v1 = h.compute_2d(L[i], R[i])
+        np.testing.assert_array_equal(D[i].cpu().numpy().view(np.uint32), d1.cpu().numpy().view(np.uint32))
+        if V[i] is not None:
+            np.testing.assert_array_equal(V[i].cpu().numpy().view(np.uint32), v1.cpu().numpy().view(np.uint32))
+        ed, ev = ref.compute_2d(p.left, p.right, oracle_params(ref, gp))
+        assert_parity(D[i].cpu().numpy(), ed, f"batch pair {i} d")
+        if V[i] is not None:
+            assert_parity(V[i].cpu().numpy(), ev, f"batch pair {i} v")
+
+
+def test_batch_over_one_pack(torch_cuda):
+    """30 pairs, more than one launch's pack of jobs, each with its own
+    max_disparity hint and so its own level count (1 to 4): bit for bit the
+    single-pair results."""
+    from paper_2106_07136_amd import bdis
+    torch = torch_cuda
+    spec = [(96 + 8 * (i % 3), 64 + 4 * (i % 2), 6.0, 100 + i, 1.0) for i in range(30)]
+    pairs, L, R = _batch_inputs(torch, spec)
+    dm = [4.0 + i for i in range(30)]
+    h = bdis.Bdis(bdis.Params(levels=0, iters=8))
+    D, V = h.compute_batch_2d(L, R, max_disparity=dm)
+    torch.cuda.synchronize()
+    for i in range(30):
+        hs = bdis.Bdis(bdis.Params(levels=0, iters=8, max_disparity=dm[i]))
+        d1, v1 = hs.compute_2d(L[i], R[i])
+        np.testing.assert_array_equal(D[i].cpu().numpy().view(np.uint32), d1.cpu().numpy().view(np.uint32))
+        np.testing.assert_array_equal(V[i].cpu().numpy().view(np.uint32), v1.cpu().numpy().view(np.uint32))
+
+
 def test_rejections(torch_cuda):
     """Patch sides above 8, eq. (2)'s fusion and the learned init are
     refused before any launch; the handle still runs afterwards."""
