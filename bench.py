@@ -215,7 +215,8 @@ def profile_leg(name, calls, precision):
     held-out 640x480 pairs with the learned init (32 channels, 8 fine-level
     iterations), also in the level graph; 'plain640' the same pairs with the
     plain init; 'search2d640' the 2-D search on the misaligned 640x480
-    headline pair, one pair per call.  Prints one JSON line with the time
+    headline pair, one pair per call; 'batch2d' the 2-D search on the
+    64-pair mixed batch.  Prints one JSON line with the time
     per call.  The pairs are
     generated in this process, one after another: under a profiler the GPU
     is initialised before this function runs, and a forked worker pool would
@@ -234,6 +235,16 @@ def profile_leg(name, calls, precision):
         pn.set_params(flat)
         h = bdis.Bdis(bdis.Params(levels=0, iters=12, precision=precision, init=1, learned_iters=8))
         h.set_net(pn)
+    elif name == "batch2d":
+        pairs = synth.make_pairs(synth.mixed_batch_spec(3000), workers=1)
+        h = bdis.Bdis(bdis.Params(levels=0, iters=12, precision=precision))
+        L, R, O, dm = _batch_io(pairs)
+        V = [o.clone() for o in O]
+        ms = timed(lambda: h.compute_batch_2d(L, R, O, V, max_disparity=dm), calls, 2)
+        print(json.dumps({"profile_leg": name, "calls": calls, "warmup": 2, "ms_per_call": ms,
+                          "mpixel_per_call": sum(p.left.size for p in pairs) / 1e6, **accuracy(O, pairs)}),
+              flush=True)
+        return
     elif name == "search2d640":
         import torch
         mis, _ = synth.misaligned_pair(640, 480, 64.0, 2, v_max=6.0)
@@ -247,7 +258,7 @@ def profile_leg(name, calls, precision):
                           "mpixel_per_call": mis.left.size / 1e6, **accuracy([d], [mis])}), flush=True)
         return
     else:
-        raise SystemExit(f"unknown --profile-leg {name!r}: batch, plain640, learned640 or search2d640")
+        raise SystemExit(f"unknown --profile-leg {name!r}: batch, plain640, learned640, search2d640 or batch2d")
     L, R, O, dm = _batch_io(pairs)
     ms = timed(lambda: h.compute_batch(L, R, O, max_disparity=dm), calls, 2)
     mpx = sum(p.left.size for p in pairs) / 1e6
@@ -579,7 +590,8 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (scale for HBM byte counters) and exit")
-    ap.add_argument("--profile-leg", choices=("batch", "plain640", "learned640", "search2d640"), default=None,
+    ap.add_argument("--profile-leg", choices=("batch", "plain640", "learned640", "search2d640", "batch2d"),
+                    default=None,
                     help="only run this batched workload (for a profiler run) and exit")
     ap.add_argument("--profile-calls", type=int, default=50)
     args = ap.parse_args()
