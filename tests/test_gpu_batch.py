@@ -110,6 +110,37 @@ def test_batch_pair_matches_oracle(torch_cuda, ref):
         assert_parity(g, exp, f"batch {W}x{H}")
 
 
+def test_bench_batch_matches_oracle(torch_cuda, ref):
+    """The batched workload as the bench times it: the 64 pairs of mixed
+    sizes (24 x 320x240, 24 x 640x480, 16 x 1280x720, seeds from 3000,
+    disparity up to 10 % of the width) in one level-graph call at patch 8,
+    stride 4, 12 iterations, levels from each pair's max_disparity: every
+    pair's whole disparity map at the parity bar against the oracle."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from paper_2106_07136_amd import bdis
+    torch = torch_cuda
+    spec = synth.mixed_batch_spec(3000)
+    with ThreadPoolExecutor(16) as ex:
+        pairs = list(ex.map(lambda a: synth.make_pair(*a), spec))
+    base = bdis.Params(levels=0, iters=12)
+    h = bdis.Bdis(base)
+    L = [torch.from_numpy(p.left).cuda() for p in pairs]
+    R = [torch.from_numpy(p.right).cuda() for p in pairs]
+    outs = h.compute_batch(L, R, max_disparity=[p.d_max for p in pairs])
+    got = [o.cpu().numpy() for o in outs]
+
+    def oracle_of(p):
+        H, W = p.left.shape
+        lv = bdis.plan(bdis.Params(levels=0, max_disparity=p.d_max), W, H)["levels"]
+        return ref.compute(p.left, p.right, oracle_params(ref, bdis.Params(levels=lv, iters=12)))
+
+    with ThreadPoolExecutor(16) as ex:
+        exp = list(ex.map(oracle_of, pairs))
+    for i, (p, g, e) in enumerate(zip(pairs, got, exp)):
+        assert_parity(g, e, f"bench batch pair {i} {p.left.shape[1]}x{p.left.shape[0]}")
+
+
 @pytest.mark.parametrize("mode", [0, 2])
 def test_graph_replay_with_new_buffers(torch_cuda, mode):
     """Graph modes: mode 0 updates its graph for new buffers, mode 2 keeps
