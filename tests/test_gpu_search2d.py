@@ -231,6 +231,36 @@ def test_batch_over_one_pack(torch_cuda):
         np.testing.assert_array_equal(V[i].cpu().numpy().view(np.uint32), v1.cpu().numpy().view(np.uint32))
 
 
+def test_bench_batch_matches_oracle(torch_cuda, ref):
+    """The batched 2-D workload the bench times: the 64 mixed pairs (24 x
+    320x240, 24 x 640x480, 16 x 1280x720, seeds from 3000), levels from each
+    pair's max_disparity, in one call: every pair's d and v at the parity
+    bar against the oracle."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from paper_2106_07136_amd import bdis
+    torch = torch_cuda
+    with ThreadPoolExecutor(16) as ex:
+        pairs = list(ex.map(lambda a: synth.make_pair(*a), synth.mixed_batch_spec(3000)))
+    h = bdis.Bdis(bdis.Params(levels=0, iters=12))
+    L = [torch.from_numpy(p.left).cuda() for p in pairs]
+    R = [torch.from_numpy(p.right).cuda() for p in pairs]
+    D, V = h.compute_batch_2d(L, R, max_disparity=[p.d_max for p in pairs])
+    D = [d.cpu().numpy() for d in D]
+    V = [v.cpu().numpy() for v in V]
+
+    def oracle_of(p):
+        H, W = p.left.shape
+        lv = bdis.plan(bdis.Params(levels=0, max_disparity=p.d_max), W, H)["levels"]
+        return ref.compute_2d(p.left, p.right, oracle_params(ref, bdis.Params(levels=lv, iters=12)))
+
+    with ThreadPoolExecutor(16) as ex:
+        exp = list(ex.map(oracle_of, pairs))
+    for i, (p, d, v, (ed, ev)) in enumerate(zip(pairs, D, V, exp)):
+        assert_parity(d, ed, f"2-D bench batch pair {i} d")
+        assert_parity(v, ev, f"2-D bench batch pair {i} v")
+
+
 def test_rejections(torch_cuda):
     """Patch sides above 8, eq. (2)'s fusion and the learned init are
     refused before any launch; the handle still runs afterwards."""
