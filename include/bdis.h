@@ -208,8 +208,9 @@ typedef struct {
  * in one pass: per level, one 2-D LK launch and one densification launch
  * for the pairs that have the level (at most 24 and 16 pairs a launch).
  * Each pair gets its own level count from its max_disparity (0: the
- * handle's) and the handle's patch and stride.  Results equal
- * bdis_compute_2d's pair by pair, bit for bit.  Errors: as
+ * handle's) and the handle's patch and stride.  Each pair's results equal,
+ * bit for bit, bdis_compute_2d's on a handle whose max_disparity is the
+ * pair's.  `pairs` is a host array read during the call only.  Errors: as
  * bdis_compute_2d; pairs are checked before anything is enqueued. */
 BDIS_API bdis_status bdis_compute_batch_2d(bdis_t *h, const bdis_pair2d *pairs, int32_t n, void *stream);
 
