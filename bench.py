@@ -289,10 +289,15 @@ def batched_leg(batch, calib, steps, warmup, precision):
         h0.set_batch_mode(m)
         modes[m] = timed(lambda: h0.compute_batch(L, R, O, max_disparity=dm), steps, warmup)
         assert h0.batch_error() == 0, "persistent batch reported a dependency timeout"
-    log(f"bench: batched {mpx:.2f} Mpx: tuned {ms:.3f} ms; patch 8 stride 4: level graph {modes[0]:.3f} ms, "
-        f"direct launches {modes[1]:.3f} ms, persistent kernel {modes[2]:.3f} ms")
+    # the level graph with every launch on one stream (no pair groups)
+    h0.set_batch_mode(0)
+    h0.set_batch_groups(False)
+    ms_one = timed(lambda: h0.compute_batch(L, R, O, max_disparity=dm), steps, warmup)
+    log(f"bench: batched {mpx:.2f} Mpx: tuned {ms:.3f} ms; patch 8 stride 4: level graph {modes[0]:.3f} ms "
+        f"({ms_one:.3f} ms on one stream), direct launches {modes[1]:.3f} ms, persistent kernel {modes[2]:.3f} ms")
     # LK + posterior launches of the batch at patch 8 / stride 4: FLOP rate
-    # at scale, from per-launch HIP events (direct launches)
+    # at scale, from per-launch HIP events (direct launches on one stream, so
+    # that no two timed launches overlap)
     h0.set_batch_mode(1)
     h0.set_profiling(True)
     for _ in range(steps):
@@ -308,7 +313,7 @@ def batched_leg(batch, calib, steps, warmup, precision):
     peak = PEAK_FP64_VECTOR if precision == 0 else PEAK_FP32_VECTOR
     lk_roof = {"bound": "alu", "achieved": fl / lk_s / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
                "frac": fl / lk_s / peak, "algorithmic_flops": fl, "lk_us_per_batch": lk_s * 1e6,
-               "lk_share_of_kernel_time": lk_s / all_s}
+               "lk_share_of_kernel_time": lk_s / all_s, "timed_on": "one stream, direct launches"}
     log(f"bench: batched LK launches {lk_s * 1e6:.0f} us per batch, {lk_roof['achieved']:.1f} TFLOP/s "
         f"({100 * lk_roof['frac']:.1f} % of peak), {100 * lk_s / all_s:.0f} % of kernel time")
     return {"workload": "plain BDIS, 64 synthetic pairs per call (24x320x240, 24x640x480, "
@@ -317,6 +322,7 @@ def batched_leg(batch, calib, steps, warmup, precision):
             "steps": steps, "tuning": tuned["table"], "batch_mode": tuned["batch_mode"],
             "wgs_per_cu": tuned["wgs_per_cu"], **acc,
             "p8s4_level_graph_mpxs": mpx / (modes[0] / 1e3),
+            "p8s4_level_graph_one_stream_mpxs": mpx / (ms_one / 1e3),
             "p8s4_direct_launches_mpxs": mpx / (modes[1] / 1e3),
             "p8s4_persistent_kernel_mpxs": mpx / (modes[2] / 1e3), "lk_roofline_p8s4": lk_roof,
             "kernels_us_per_batch_p8s4": {k: t * 1e3 / steps for k, (n, t) in prof.items()}}
@@ -353,6 +359,7 @@ def learned_leg(pairs, channels, steps, warmup, precision, workload):
     hl = bdis.Bdis(dataclasses.replace(base, init=1, learned_iters=pick))
     hl.set_net(pn)
     hl.set_batch_mode(1)  # direct launches: events around each one
+    hl.set_batch_groups(False)  # one network stream: timed launches do not overlap
     hl.set_profiling(True)
     for _ in range(steps):
         hl.compute_batch(L, R, O, max_disparity=dm)

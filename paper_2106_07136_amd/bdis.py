@@ -128,6 +128,7 @@ def lib():
         L.bdis_debug_stage.argtypes = [vp, i32, i32, vp, C.c_size_t]
         L.bdis_set_batch_mode.argtypes = [vp, i32, i32]
         L.bdis_set_fold_densify.argtypes = [vp, i32]
+        L.bdis_set_batch_groups.argtypes = [vp, i32]
         L.bdis_batch_error.argtypes = [vp, C.POINTER(i32)]
         L.bdis_set_net.argtypes = [vp, vp]
         L.bdis_net_input.argtypes = [vp, C.POINTER(CPair), i32, vp, vp]
@@ -142,7 +143,7 @@ def lib():
         L.bdis_last_error.argtypes = [vp]
         L.bdis_last_error.restype = C.c_char_p
         for name in ("bdis_plan", "bdis_create", "bdis_set_params", "bdis_reserve", "bdis_compute",
-                     "bdis_compute_noalloc", "bdis_compute_2d", "bdis_compute_batch_2d",
+                     "bdis_compute_noalloc", "bdis_compute_2d", "bdis_compute_batch_2d", "bdis_set_batch_groups",
                      "bdis_compute_batch", "bdis_set_tuning", "bdis_debug_stage",
                      "bdis_set_profiling", "bdis_get_profile", "bdis_set_batch_mode",
                      "bdis_batch_error", "bdis_set_net", "bdis_net_input", "bdis_set_fold_densify",
@@ -320,6 +321,11 @@ class Bdis:
         """0: the per-level launches captured in a hipGraph (default); 1: the
         same launches direct; 2: one persistent kernel."""
         _check(lib().bdis_set_batch_mode(self._h, mode, wgs_per_cu), self._h)
+
+    def set_batch_groups(self, on: bool):
+        """True (default): plain batches of more than 24 pairs run as up to
+        three pair groups on streams of their own; False: one stream."""
+        _check(lib().bdis_set_batch_groups(self._h, 1 if on else 0), self._h)
 
     def set_fold_densify(self, on: bool):
         """True (default): levels >= 1 are densified inside the next finer

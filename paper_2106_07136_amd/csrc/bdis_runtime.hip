@@ -59,6 +59,9 @@ constexpr int kFoldBlocksPerCU = 3;
 // a densification launch takes one pixel strip per thread only when the
 // strips fill at least this many blocks per CU
 constexpr int kStripBlocksPerCU = 4;
+// A plain batch of more than kMaxJobs pairs runs as up to kMaxLanes groups
+// of pairs, each on a stream of its own, so that the groups' launches overlap.
+constexpr int kMaxLanes = 3;
 
 thread_local char g_thread_err[512] = "";
 
@@ -285,7 +288,12 @@ struct bdis_ctx {
     std::vector<char> lv_key;
     int *p_err = nullptr;         // device error flag of the last persistent run
     hipStream_t last_batch_stream = nullptr;
+    // streams of the pair groups a large plain batch runs side by side on
+    // (lane g >= 1; lane 0 is the caller's stream), their fork/join events
+    hipStream_t lanes[kMaxLanes - 1] = {};
+    hipEvent_t lane_fork = nullptr, lane_join[kMaxLanes - 1] = {};
     int n_cu = 0;
+    bool lane_groups = true;      // large plain batches as overlapping groups
     // this device's copy of the no-allocation scratch array (see below)
     char *scratch = nullptr;
     // autotuner table
@@ -375,8 +383,9 @@ bdis_status ensure_ws(bdis_t *h, size_t bytes) {
 
 // A launch: kernel kind, template selectors and its jobs (passed by value).
 // K_FORK / K_JOIN launch nothing: work after a fork runs on the side stream
-// (lane 1) until the join makes the main stream wait for it.
-enum Kind { K_PYR2, K_LK, K_DENSE, K_NETIN, K_NETF, K_GATE, K_FORK, K_JOIN, K_LK2, K_DENSE2 };
+// (lane 1) until the join makes the main stream wait for it.  K_FORKN /
+// K_JOINN do the same for the `level` group streams of a large batch.
+enum Kind { K_PYR2, K_LK, K_DENSE, K_NETIN, K_NETF, K_GATE, K_FORK, K_JOIN, K_LK2, K_DENSE2, K_FORKN, K_JOINN };
 struct Launch {
     Kind kind;
     int level;
@@ -386,7 +395,9 @@ struct Launch {
     int blocks;
     KParams kp;
     std::vector<char> pack;  // JobPack<Job> bytes
-    int lane = 0;            // 0: the caller's stream, 1: the side stream
+    int lane = 0;            // 0: the caller's stream, 1: the side stream (after K_FORK)
+    int ncu = 0;             // compute units the launch's build choice assumes (0: the device's)
+    int group = 0;           // pair group g > 0 of a large batch: its own stream (after K_FORKN)
 };
 
 // Splits jobs into launches of at most PackCap<Job> jobs; `blocks_of` gives
@@ -492,7 +503,9 @@ DenseJob make_dense_job(const bdis_t *h, const PairIn &p, int l, bool keep) {
 // level (the fallback, which needs nothing from them); the injection level's
 // densification fills only the pixels the gate did not keep, and the finer
 // levels use learned_iters.
-void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<Launch> &ls) {
+void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<Launch> &ls, int ncu = 0) {
+    if (ncu <= 0) ncu = h->n_cu;
+    const size_t first = ls.size();
     int Lmax = 0, Lpmax = 0;
     const bool f64 = h->prm.precision == 0;
     const bool lrn = learned(h);
@@ -564,7 +577,7 @@ void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<Launch> &l
         for (int l = 0; l < p.g.L; l++) lk_blocks[l] += p.g.ny[l] * lk_bpr(p.patch, p.g.nx[l]);
     auto folded = [&](const PairIn &p, int l) {
         return h->fold_dense && l >= 0 && l + 1 < p.g.L && !(lrn && l + 1 == inj) &&
-               h->prm.fusion == BDIS_FUSION_BAYES && lk_blocks[l] <= kFoldBlocksPerCU * h->n_cu;
+               h->prm.fusion == BDIS_FUSION_BAYES && lk_blocks[l] <= kFoldBlocksPerCU * ncu;
     };
     // the level-0 LK launch densifies level 1 for its own initial shifts
     // only (no finer level reads that field)
@@ -621,12 +634,13 @@ void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<Launch> &l
         // the latency of its gathers and keeps one pixel per thread.
         long long strip_threads = 0;
         for (const DenseJob &j : jobs) strip_threads += (long long)((j.W + j.strip - 1) / j.strip) * j.H;
-        if (strip_threads < (long long)kStripBlocksPerCU * kBlock * h->n_cu)
+        if (strip_threads < (long long)kStripBlocksPerCU * kBlock * ncu)
             for (DenseJob &j : jobs) j.strip = 1;
         append(ls, K_DENSE, l, 0, l == 0, f64, jobs, kp0,
                [](const DenseJob &j) { return dense_job_blocks(j); });
     }
     if (lrn && !joined) ls.push_back(Launch{K_JOIN, 0, 0, false, f64, 0, kp0, {}});  // every fork is joined
+    for (size_t i = first; i < ls.size(); i++) ls[i].ncu = ncu;
 }
 
 // kernel arguments are limited to 4 KiB
@@ -648,13 +662,14 @@ void launch_lk(const bdis_t *h, const Launch &L, hipStream_t s) {
     // occupancy); the register-trimmed variant for launches of more than
     // three blocks per CU, where occupancy beats per-wave latency (smaller
     // launches fit at three waves per SIMD)
-    const bool big = L.blocks > kFoldBlocksPerCU * h->n_cu;
+    const int ncu = L.ncu > 0 ? L.ncu : h->n_cu;
+    const bool big = L.blocks > kFoldBlocksPerCU * ncu;
     const dim3 g(L.blocks), b(kBlock);
     if (L.kp.window <= 5) {
         if (big) {
             if (L.u8) hipLaunchKernelGGL((k_lk<T, P, true, 5, 5>), g, b, 0, s, pk, L.kp);
             else hipLaunchKernelGGL((k_lk<T, P, false, 5, 5>), g, b, 0, s, pk, L.kp);
-        } else if (!L.u8 && L.blocks <= 2 * h->n_cu) {
+        } else if (!L.u8 && L.blocks <= 2 * ncu) {
             // two waves per SIMD at most: room to gather the densified
             // level's first share pixel with the initial-shift taps
             hipLaunchKernelGGL((k_lk<T, P, false, 5, 2>), g, b, 0, s, pk, L.kp);
@@ -685,6 +700,8 @@ void launch_one(bdis_t *h, const Launch &L, hipStream_t s) {
         break;
     case K_FORK:
     case K_JOIN:
+    case K_FORKN:
+    case K_JOINN:
         break;  // stream ordering only (launch_all)
     case K_PYR2: {
         const JobPack<Pyr2Job> &pk = pack_of<Pyr2Job>(L);
@@ -763,8 +780,33 @@ hipEvent_t take_event(bdis_t *h) {
     return e;
 }
 
+// The group streams and their events (created before a graph capture too).
+bdis_status ensure_lanes(bdis_t *h, int n) {
+    if (!h->lane_fork) HIPCHK(h, hipEventCreateWithFlags(&h->lane_fork, hipEventDisableTiming));
+    for (int g = 1; g < n && g < kMaxLanes; g++) {
+        if (!h->lanes[g - 1]) HIPCHK(h, hipStreamCreateWithFlags(&h->lanes[g - 1], hipStreamNonBlocking));
+        if (!h->lane_join[g - 1]) HIPCHK(h, hipEventCreateWithFlags(&h->lane_join[g - 1], hipEventDisableTiming));
+    }
+    return BDIS_OK;
+}
+
 bdis_status launch_all(bdis_t *h, const std::vector<Launch> &ls, hipStream_t s) {
     for (const Launch &L : ls) {
+        if (L.kind == K_FORKN || L.kind == K_JOINN) {
+            const int n = L.level;
+            bdis_status st = ensure_lanes(h, n);
+            if (st != BDIS_OK) return st;
+            if (L.kind == K_FORKN) {
+                HIPCHK(h, hipEventRecord(h->lane_fork, s));
+                for (int g = 1; g < n; g++) HIPCHK(h, hipStreamWaitEvent(h->lanes[g - 1], h->lane_fork, 0));
+            } else {
+                for (int g = 1; g < n; g++) {
+                    HIPCHK(h, hipEventRecord(h->lane_join[g - 1], h->lanes[g - 1]));
+                    HIPCHK(h, hipStreamWaitEvent(s, h->lane_join[g - 1], 0));
+                }
+            }
+            continue;
+        }
         if (L.kind == K_FORK || L.kind == K_JOIN) {
             if (!h->side) HIPCHK(h, hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
             if (!h->ev_fork) HIPCHK(h, hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
@@ -778,7 +820,7 @@ bdis_status launch_all(bdis_t *h, const std::vector<Launch> &ls, hipStream_t s) 
             }
             continue;
         }
-        const hipStream_t ls_ = L.lane ? h->side : s;
+        const hipStream_t ls_ = L.lane ? h->side : (L.group > 0 ? h->lanes[L.group - 1] : s);
         hipEvent_t a = nullptr, b = nullptr;
         if (h->profiling) {
             a = take_event(h);
@@ -1046,8 +1088,8 @@ bdis_status run_persistent(bdis_t *h, std::vector<PairIn> &pairs, hipStream_t s)
 bdis_status run_level_graph(bdis_t *h, const std::vector<Launch> &ls, hipStream_t s) {
     std::vector<char> key;
     for (const Launch &L : ls) {
-        const int hdr[6] = {(int)L.kind, L.level, L.patch, (int)L.u8, (int)L.f64, L.blocks};
-        key.insert(key.end(), reinterpret_cast<const char *>(hdr), reinterpret_cast<const char *>(hdr + 6));
+        const int hdr[9] = {(int)L.kind, L.level, L.patch, (int)L.u8, (int)L.f64, L.blocks, L.lane, L.ncu, L.group};
+        key.insert(key.end(), reinterpret_cast<const char *>(hdr), reinterpret_cast<const char *>(hdr + 9));
         const char *kp = reinterpret_cast<const char *>(&L.kp);
         key.insert(key.end(), kp, kp + sizeof(KParams));
         key.insert(key.end(), L.pack.begin(), L.pack.end());
@@ -1058,6 +1100,11 @@ bdis_status run_level_graph(bdis_t *h, const std::vector<Launch> &ls, hipStream_
         if (!h->side) HIPCHK(h, hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
         if (!h->ev_fork) HIPCHK(h, hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
         if (!h->ev_join) HIPCHK(h, hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming));
+        for (const Launch &L : ls)
+            if (L.kind == K_FORKN) {
+                bdis_status st = ensure_lanes(h, L.level);
+                if (st != BDIS_OK) return st;
+            }
         const bool prof = h->profiling;
         h->profiling = false;  // no event records inside the captured graph
         HIPCHK(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
@@ -1166,7 +1213,37 @@ bdis_status run(bdis_t *h, std::vector<PairIn> &pairs, hipStream_t s, int mode =
     }
     if (mode == 2) return run_persistent(h, pairs, s);
     std::vector<Launch> ls;
-    plan_launches(h, pairs, ls);
+    const int ngroups = std::min<int>(kMaxLanes, ((int)pairs.size() + kMaxJobs - 1) / kMaxJobs);
+    // Pair groups are for plain batches only: the learned init's network
+    // runs on the side stream, forked from and joined to the caller's stream,
+    // and is not forked again from a group's stream.
+    if (!lrn && h->lane_groups && ngroups > 1) {
+        // Groups of pairs, each on its own stream: pairs taken largest
+        // first, each to the group with the fewest pixels so far.  Every
+        // group's launches are planned as for its share of the compute units.
+        std::vector<int> order(pairs.size());
+        for (size_t i = 0; i < order.size(); i++) order[i] = (int)i;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            return (long long)pairs[a].W * pairs[a].H > (long long)pairs[b].W * pairs[b].H;
+        });
+        std::vector<std::vector<PairIn>> grp(ngroups);
+        std::vector<long long> px(ngroups, 0);
+        for (int i : order) {
+            const int g = (int)(std::min_element(px.begin(), px.end()) - px.begin());
+            grp[g].push_back(pairs[i]);
+            px[g] += (long long)pairs[i].W * pairs[i].H;
+        }
+        const KParams kp0 = make_kparams(h->prm, h->prm.patch);
+        ls.push_back(Launch{K_FORKN, ngroups, 0, false, h->prm.precision == 0, 0, kp0, {}});
+        for (int g = 0; g < ngroups; g++) {
+            const size_t first = ls.size();
+            plan_launches(h, grp[g], ls, std::max(1, h->n_cu / ngroups));
+            for (size_t i = first; i < ls.size(); i++) ls[i].group = g;
+        }
+        ls.push_back(Launch{K_JOINN, ngroups, 0, false, h->prm.precision == 0, 0, kp0, {}});
+    } else {
+        plan_launches(h, pairs, ls);
+    }
     if (mode == 0) return run_level_graph(h, ls, s);
     bdis_status st2 = launch_all(h, ls, s);
     if (st2 != BDIS_OK) return st2;
@@ -1582,6 +1659,13 @@ bdis_status bdis_set_batch_mode(bdis_t *h, int32_t mode, int32_t wgs_per_cu) {
     return BDIS_OK;
 }
 
+bdis_status bdis_set_batch_groups(bdis_t *h, int32_t on) {
+    if (!h) { set_err(g_thread_err, "handle is NULL"); return BDIS_E_INVALID_ARG; }
+    if (on != 0 && on != 1) { set_err(h->err, "groups must be 0 or 1"); return BDIS_E_INVALID_ARG; }
+    h->lane_groups = on != 0;
+    return BDIS_OK;
+}
+
 bdis_status bdis_set_fold_densify(bdis_t *h, int32_t on) {
     if (!h) { set_err(g_thread_err, "handle is NULL"); return BDIS_E_INVALID_ARG; }
     if (on != 0 && on != 1) { set_err(h->err, "fold must be 0 or 1"); return BDIS_E_INVALID_ARG; }
@@ -1818,6 +1902,11 @@ void bdis_destroy(bdis_t *h) {
         if (h->lv_exec) (void)hipGraphExecDestroy(h->lv_exec);
         if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
         if (h->side) (void)hipStreamDestroy(h->side);
+        for (int g = 0; g < kMaxLanes - 1; g++) {
+            if (h->lanes[g]) (void)hipStreamDestroy(h->lanes[g]);
+            if (h->lane_join[g]) (void)hipEventDestroy(h->lane_join[g]);
+        }
+        if (h->lane_fork) (void)hipEventDestroy(h->lane_fork);
         if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
         if (h->ev_join) (void)hipEventDestroy(h->ev_join);
         if (h->p_dev) (void)hipFree(h->p_dev);

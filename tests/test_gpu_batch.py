@@ -110,6 +110,30 @@ def test_batch_pair_matches_oracle(torch_cuda, ref):
         assert_parity(g, exp, f"batch {W}x{H}")
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_batch_groups_same_bits(torch_cuda, mode):
+    """60 pairs (more than one job pack): the batch as three pair groups on
+    their own streams gives the same bits as on one stream, in the graph and
+    in direct launches, and again on a second call with new outputs."""
+    from paper_2106_07136_amd import bdis
+    torch = torch_cuda
+    spec = [((64, 48), (97, 61), (160, 120), (320, 240))[i % 4] + (6.0 + (i % 5), 700 + i) for i in range(60)]
+    pairs = _pairs(torch, spec)
+    res = {}
+    for groups in (True, False):
+        h = bdis.Bdis(bdis.Params(levels=0, iters=10))
+        h.set_batch_mode(mode)
+        h.set_batch_groups(groups)
+        first = _run_batch(h, pairs)
+        second = _run_batch(h, pairs)
+        for a, b in zip(first, second):
+            np.testing.assert_array_equal(_bits(a), _bits(b))
+        res[groups] = first
+        h.close()
+    for a, b in zip(res[True], res[False]):
+        np.testing.assert_array_equal(_bits(a), _bits(b))
+
+
 def test_bench_batch_matches_oracle(torch_cuda, ref):
     """The batched workload as the bench times it: the 64 pairs of mixed
     sizes (24 x 320x240, 24 x 640x480, 16 x 1280x720, seeds from 3000,

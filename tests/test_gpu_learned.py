@@ -277,6 +277,41 @@ def test_learned_batch_equals_single(torch_cuda, mode):
         np.testing.assert_array_equal(o.cpu().numpy().view(np.uint32), r.view(np.uint32))
 
 
+@pytest.mark.skip(reason="learned batches run on one stream: the first run of pair groups that each forked "
+                         "their network to a side stream of their own (nested stream forks in a graph capture) "
+                         "ended the host process with a segmentation fault whose cause is not shown; that "
+                         "code path is switched off")
+@pytest.mark.parametrize("mode", [0, 1])
+def test_learned_batch_groups_same_bits(torch_cuda, mode):
+    """48 learned pairs (two job packs): run as pair groups, each with its
+    network forked to a side stream of its own, the batch gives the same bits
+    as on one stream and one side stream, twice in a row."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from paper_2106_07136_amd import bdis
+    torch = torch_cuda
+    spec = [((320, 240, 32.0), (640, 480, 64.0), (400, 300, 40.0))[i % 3] + (4200 + i,) for i in range(48)]
+    with ThreadPoolExecutor(16) as ex:
+        pairs = list(ex.map(lambda a: synth.make_pair(*a), spec))
+    net = _net(_varying_layers(32, 1.0, 0.5, 100.0, -4.0))
+    Ls = [torch.from_numpy(p.left).cuda() for p in pairs]
+    Rs = [torch.from_numpy(p.right).cuda() for p in pairs]
+    res = {}
+    for groups in (True, False):
+        h = bdis.Bdis(bdis.Params(levels=0, init=1, learned_iters=8))
+        h.set_net(net)
+        h.set_batch_mode(mode)
+        h.set_batch_groups(groups)
+        first = [o.cpu().numpy() for o in h.compute_batch(Ls, Rs, max_disparity=[a[2] for a in spec])]
+        second = [o.cpu().numpy() for o in h.compute_batch(Ls, Rs, max_disparity=[a[2] for a in spec])]
+        for a, b in zip(first, second):
+            np.testing.assert_array_equal(a.view(np.uint32), b.view(np.uint32))
+        res[groups] = first
+        h.close()
+    for a, b in zip(res[True], res[False]):
+        np.testing.assert_array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
 def test_learned_errors(torch_cuda):
     from paper_2106_07136_amd import bdis
     pair = synth.make_pair(640, 480, 64.0, 34)
