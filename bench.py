@@ -211,7 +211,8 @@ def _batch_io(pairs):
 
 def profile_leg(name, calls, precision):
     """One batched workload alone, for a profiler run: 'batch' is the 64-pair
-    mixed batch at patch 8 / stride 4 in the level graph; 'learned640' the 64
+    mixed batch at patch 8 / stride 4 in the level graph (as pair groups on
+    three streams; 'batch_one_stream' on one stream); 'learned640' the 64
     held-out 640x480 pairs with the learned init (32 channels, 8 fine-level
     iterations), also in the level graph; 'plain640' the same pairs with the
     plain init; 'search2d640' the 2-D search on the misaligned 640x480
@@ -222,9 +223,10 @@ def profile_leg(name, calls, precision):
     is initialised before this function runs, and a forked worker pool would
     copy that state."""
     from paper_2106_07136_amd import bdis, net, synth, train
-    if name == "batch":
+    if name in ("batch", "batch_one_stream"):
         pairs = synth.make_pairs(synth.mixed_batch_spec(3000), workers=1)
         h = bdis.Bdis(bdis.Params(levels=0, iters=12, precision=precision))
+        h.set_batch_groups(name == "batch")
     elif name == "plain640":
         pairs = synth.make_pairs([(640, 480, 64.0, 90000 + i) for i in range(64)], workers=1)
         h = bdis.Bdis(bdis.Params(levels=0, iters=12, precision=precision))
@@ -258,7 +260,8 @@ def profile_leg(name, calls, precision):
                           "mpixel_per_call": mis.left.size / 1e6, **accuracy([d], [mis])}), flush=True)
         return
     else:
-        raise SystemExit(f"unknown --profile-leg {name!r}: batch, plain640, learned640, search2d640 or batch2d")
+        raise SystemExit(f"unknown --profile-leg {name!r}: batch, batch_one_stream, plain640, learned640, "
+                         "search2d640 or batch2d")
     L, R, O, dm = _batch_io(pairs)
     ms = timed(lambda: h.compute_batch(L, R, O, max_disparity=dm), calls, 2)
     mpx = sum(p.left.size for p in pairs) / 1e6
@@ -340,9 +343,13 @@ def learned_leg(pairs, channels, steps, warmup, precision, workload):
     mpx = sum(p.left.size for p in pairs) / 1e6
     base = bdis.Params(levels=0, iters=12, precision=precision)
     hp = bdis.Bdis(base)
+    # the plain batch on one stream, as the learned batch runs
+    hp.set_batch_groups(False)
+    ms_plain_one = timed(lambda: hp.compute_batch(L, R, O, max_disparity=dm), steps, warmup)
+    hp.set_batch_groups(True)
     ms_plain = timed(lambda: hp.compute_batch(L, R, O, max_disparity=dm), steps, warmup)
     acc_plain = accuracy(O, pairs)
-    log(f"bench: {workload[:24]}: plain {ms_plain:.3f} ms {acc_plain}")
+    log(f"bench: {workload[:24]}: plain {ms_plain:.3f} ms ({ms_plain_one:.3f} ms on one stream) {acc_plain}")
     runs = {}
     for it in (12, 8, 6, 4):
         hl = bdis.Bdis(dataclasses.replace(base, init=1, learned_iters=it))
@@ -379,7 +386,8 @@ def learned_leg(pairs, channels, steps, warmup, precision, workload):
             "plain": {"value": mpx / (ms_plain / 1e3), "ms_per_batch": ms_plain, **acc_plain},
             "learned": {"value": mpx / (ms_l / 1e3), "ms_per_batch": ms_l, "learned_iters": pick,
                         "channels": C, **acc_l},
-            "speedup": ms_plain / ms_l, "net_mfma": mfma,
+            "plain_one_stream_ms_per_batch": ms_plain_one,
+            "speedup": ms_plain / ms_l, "speedup_vs_plain_one_stream": ms_plain_one / ms_l, "net_mfma": mfma,
             "sweep": {str(k): {"ms_per_batch": v[0], **v[1]} for k, v in runs.items()}}
 
 
@@ -597,7 +605,8 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (scale for HBM byte counters) and exit")
-    ap.add_argument("--profile-leg", choices=("batch", "plain640", "learned640", "search2d640", "batch2d"),
+    ap.add_argument("--profile-leg", choices=("batch", "batch_one_stream", "plain640", "learned640", "search2d640",
+                                              "batch2d"),
                     default=None,
                     help="only run this batched workload (for a profiler run) and exit")
     ap.add_argument("--profile-calls", type=int, default=50)
