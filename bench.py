@@ -307,7 +307,7 @@ def batched_leg(batch, calib, steps, warmup, precision):
         h0.compute_batch(L, R, O, max_disparity=dm)
     prof = h0.profile()
     h0.set_profiling(False)
-    lk_s = sum(t for k, (n, t) in prof.items() if k.startswith("lk_")) / 1e3 / steps
+    lk_s = sum(t for k, (n, t) in prof.items() if k.startswith(("lk_", "lkw_"))) / 1e3 / steps
     all_s = sum(t for k, (n, t) in prof.items()) / 1e3 / steps
     fl = 0
     for p in batch:

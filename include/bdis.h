@@ -257,6 +257,15 @@ BDIS_API bdis_status bdis_set_batch_groups(bdis_t *h, int32_t on);
  * BDIS_E_INVALID_ARG for a NULL handle or on not in {0, 1}. */
 BDIS_API bdis_status bdis_set_fold_densify(bdis_t *h, int32_t on);
 
+/* LK launches of the 1-D search (Sec. 2.1, eqs. (3)-(4)) with patch sides up
+ * to 8 and at most patches_per_cu patches per compute unit (default 8: the
+ * coarse levels of one pair) run one wave per patch, one lane per pixel,
+ * instead of one lane per patch row: a shorter chain of dependent steps per
+ * patch where the launch leaves the chip mostly idle.  Both kernels sum in
+ * one fixed order, so results are the same bits either way.  0 = never.
+ * Errors: BDIS_E_INVALID_ARG for a NULL handle or a negative count. */
+BDIS_API bdis_status bdis_set_wave_lk(bdis_t *h, int32_t patches_per_cu);
+
 /* Waits for the last bdis_compute_batch and reports whether the persistent
  * kernel had to give up a dependency wait (*flag = 1: that batch's results are
  * not valid; it cannot happen when the kernel owns the GPU).  *flag = 0 in

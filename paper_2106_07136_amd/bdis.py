@@ -128,6 +128,7 @@ def lib():
         L.bdis_debug_stage.argtypes = [vp, i32, i32, vp, C.c_size_t]
         L.bdis_set_batch_mode.argtypes = [vp, i32, i32]
         L.bdis_set_fold_densify.argtypes = [vp, i32]
+        L.bdis_set_wave_lk.argtypes = [vp, i32]
         L.bdis_set_batch_groups.argtypes = [vp, i32]
         L.bdis_batch_error.argtypes = [vp, C.POINTER(i32)]
         L.bdis_set_net.argtypes = [vp, vp]
@@ -146,7 +147,7 @@ def lib():
                      "bdis_compute_noalloc", "bdis_compute_2d", "bdis_compute_batch_2d", "bdis_set_batch_groups",
                      "bdis_compute_batch", "bdis_set_tuning", "bdis_debug_stage",
                      "bdis_set_profiling", "bdis_get_profile", "bdis_set_batch_mode",
-                     "bdis_batch_error", "bdis_set_net", "bdis_net_input", "bdis_set_fold_densify",
+                     "bdis_batch_error", "bdis_set_net", "bdis_net_input", "bdis_set_fold_densify", "bdis_set_wave_lk",
                      "bdis_rectify", "bdis_depth_from_disparity"):
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -331,6 +332,12 @@ class Bdis:
         """True (default): levels >= 1 are densified inside the next finer
         level's LK launch; False: one densify launch per level."""
         _check(lib().bdis_set_fold_densify(self._h, 1 if on else 0), self._h)
+
+    def set_wave_lk(self, patches_per_cu: int):
+        """LK launches (patch side <= 8) of at most this many patches per
+        compute unit run one wave per patch (default 8; 0: never).  The
+        results are the same bits either way."""
+        _check(lib().bdis_set_wave_lk(self._h, int(patches_per_cu)), self._h)
 
     def batch_error(self) -> int:
         f = C.c_int32()

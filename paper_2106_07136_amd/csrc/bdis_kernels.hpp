@@ -289,6 +289,26 @@ __device__ __forceinline__ int seg_sum_i(int v) {
     return v;
 }
 
+// Sums over the eight column slots of a patch row (patch sides up to 8; the
+// slots past the patch side hold zeros), in one fixed order: pairs (0, 1),
+// (2, 3), (4, 5), (6, 7), then pairs of pairs, then the two halves.  A sum
+// of products fuses each pair into one FMA, a0 b0 + round(a1 b1).  The
+// one-lane-per-pixel LK kernel forms the same sums with lane swizzles, so
+// both give the same bits.
+template <typename T>
+__device__ __forceinline__ T row_sum8(const T (&t)[8]) {
+#pragma clang fp contract(off)
+    return ((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7]));
+}
+template <typename T>
+__device__ __forceinline__ T row_dot8(const T (&a)[8], const T (&b)[8]) {
+#pragma clang fp contract(off)
+    T q[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) q[j] = fma(a[2 * j], b[2 * j], a[2 * j + 1] * b[2 * j + 1]);
+    return (q[0] + q[1]) + (q[2] + q[3]);
+}
+
 // Bilinear read of a coarse field, coordinates clamped to the field.
 template <typename T>
 __device__ __forceinline__ void bilinear_taps(int W, int H, T X, T Y, int &mx, int &my, int &mx1, int &my1, T &fx,
@@ -842,8 +862,14 @@ __host__ __device__ constexpr int lk_lds_bytes() { return P * LkShape<P>::NCROW 
 // registers: for launches of at most two blocks per CU).
 template <typename T, int P, bool U8, int WN = 9, bool FOLD = false, bool MERGE = false>
 __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KParams &kp, T *__restrict__ Rs) {
+    // no implicit contraction: every fused multiply-add is written out, so
+    // that the one-lane-per-pixel kernel can repeat the arithmetic exactly
+#pragma clang fp contract(off)
     using S = LkShape<P>;
     constexpr int SEG = S::SEG, PPB = S::PPB, NCMAX = S::NCMAX, NCROW = S::NCROW, PADC = S::PADC;
+    // patch sides up to 8: sums over the eight column slots of each row in
+    // the fixed order of row_sum8 / row_dot8
+    constexpr bool CAN = P <= 8;
 
     const int W = J.W;
     const int bpr = lk_blocks_per_row<P>(J.nx);
@@ -1070,17 +1096,35 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
 
     int nloc = 0;
     T gsum = 0;
+    if constexpr (CAN) {
+        T t[8];
 #pragma unroll
-    for (int c = 0; c < P; c++)
-        if ((vmask >> c) & 1u) { gsum += Jg[c]; nloc++; }
+        for (int c = 0; c < 8; c++) t[c] = (c < P && ((vmask >> c) & 1u)) ? Jg[c < P ? c : 0] : T(0);
+        gsum = row_sum8(t);
+        nloc = __builtin_popcount(vmask);
+    } else {
+#pragma unroll
+        for (int c = 0; c < P; c++)
+            if ((vmask >> c) & 1u) { gsum += Jg[c]; nloc++; }
+    }
     const int n = seg_sum_i<SEG>(nloc);
     gsum = seg_sum<SEG>(gsum);
     const T gmean = n > 0 ? gsum / (T)n : T(0);
     T hloc = 0;
 #pragma unroll
-    for (int c = 0; c < P; c++) {
-        Jg[c] = ((vmask >> c) & 1u) ? Jg[c] - gmean : T(0);
-        hloc += Jg[c] * Jg[c];
+    for (int c = 0; c < P; c++) Jg[c] = ((vmask >> c) & 1u) ? Jg[c] - gmean : T(0);
+    // J and T in eight slots (zeros past the patch side)
+    T J8[8], T8[8];
+#pragma unroll
+    for (int c = 0; c < 8; c++) {
+        J8[c] = c < P ? Jg[c < P ? c : 0] : T(0);
+        T8[c] = c < P ? Tv[c < P ? c : 0] : T(0);
+    }
+    if constexpr (CAN) {
+        hloc = row_dot8(J8, J8);
+    } else {
+#pragma unroll
+        for (int c = 0; c < P; c++) hloc = fma(Jg[c], Jg[c], hloc);
     }
     const T Hs = seg_sum<SEG>(hloc);
 
@@ -1093,13 +1137,17 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
         const T invH = T(1) / Hs;
         // sum_c J_c T_c of this lane's row: the template part of sum J e
         T jt0 = 0, jt1 = 0;
+        if constexpr (CAN) {
+            jt0 = row_dot8(J8, T8);
+        } else {
 #pragma unroll
-        for (int c = 0; c < P; c += 2) {
-            jt0 += Jg[c] * Tv[c];
-            if (c + 1 < P) jt1 += Jg[c + 1] * Tv[c + 1];
+            for (int c = 0; c < P; c += 2) {
+                jt0 = fma(Jg[c], Tv[c], jt0);
+                if (c + 1 < P) jt1 = fma(Jg[c + 1], Tv[c + 1], jt1);
+            }
         }
         // sum J T over the patch (constant over the iterations)
-        const T JT = seg_sum<SEG>(jt0 + jt1);
+        const T JT = seg_sum<SEG>(CAN ? jt0 : jt0 + jt1);
         // The residual sum is linear in the fraction within one cell of the
         // shift: sum J I = A + f (B - A) over the patch, with A (B) the dot
         // product of J with the tap each sample takes at f = 0 (f = 1).
@@ -1124,22 +1172,38 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
                 T v[P + 1];
                 load_run(xi0, v);
                 T a0 = 0, a1 = 0, b0 = 0, b1 = 0;
+                if constexpr (CAN) {
+                    // row_dot8 of J with the taps at f = 0 and f = 1, pair by pair
+                    T pa[4], pb[4];
 #pragma unroll
-                for (int c = 0; c < P; c += 2) {
-                    a0 += Jg[c] * v[c];
-                    b0 += Jg[c] * v[c + 1];
-                    if (c + 1 < P) {
-                        a1 += Jg[c + 1] * v[c + 1];
-                        b1 += Jg[c + 1] * v[c + 2];
+                    for (int j = 0; j < 4; j++) {
+                        const int c0 = 2 * j, c1 = 2 * j + 1;
+                        const T v0 = c0 < P ? v[c0 < P ? c0 : 0] : T(0), v1 = c1 < P ? v[c1 < P ? c1 : 0] : T(0);
+                        const T v2 = c1 < P ? v[c1 < P ? c1 + 1 : 0] : T(0);
+                        const T w1 = c0 < P ? v[c0 < P ? c0 + 1 : 0] : T(0);
+                        pa[j] = fma(J8[c0], v0, J8[c1] * v1);
+                        pb[j] = fma(J8[c0], w1, J8[c1] * v2);
+                    }
+                    a0 = (pa[0] + pa[1]) + (pa[2] + pa[3]);
+                    b0 = (pb[0] + pb[1]) + (pb[2] + pb[3]);
+                } else {
+#pragma unroll
+                    for (int c = 0; c < P; c += 2) {
+                        a0 = fma(Jg[c], v[c], a0);
+                        b0 = fma(Jg[c], v[c + 1], b0);
+                        if (c + 1 < P) {
+                            a1 = fma(Jg[c + 1], v[c + 1], a1);
+                            b1 = fma(Jg[c + 1], v[c + 2], b1);
+                        }
                     }
                 }
-                const T A = a0 + a1, B = b0 + b1;
+                const T A = CAN ? a0 : a0 + a1, B = CAN ? b0 : b0 + b1;
                 T ab[2] = {A, B};
                 seg_sum_n<SEG, 2>(ab);
                 SA = ab[0] - JT;
                 SD = ab[1] - ab[0];
             }
-            step = (SA + uf * SD) * invH;
+            step = fma(uf, SD, SA) * invH;
             u = u - step;
         }
         const bool unconverged = kp.conv_tol > 0 && kp.iters > 0 && !(fabs(step) <= (T)kp.conv_tol);
@@ -1221,30 +1285,51 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
                             load_run(x0 + ishift(ud, uf), v);
                         }
                         const T omf = T(1) - uf;
-                        // two interleaved chains per sum: half the dependent
-                        // adds (one wave per SIMD at the small levels).  The
-                        // left-valid mask enters as a 0/1 factor of the
+                        // The left-valid mask enters as a 0/1 factor of the
                         // residual (the same bits as selecting it), and not
                         // at all in waves whose rows are all valid.
                         T s0 = 0, s1 = 0, e0 = 0, e1 = 0;
-                        if (allv) {
+                        if constexpr (CAN) {
+                            // row_sum8 of m and row_dot8 of (m, q), pair by
+                            // pair (slots past the patch side: zeros)
+                            T sp[4], ep[4];
+#pragma unroll
+                            for (int j = 0; j < 4; j++) {
+                                T qv[2] = {T(0), T(0)}, mq[2] = {T(0), T(0)};
+#pragma unroll
+                                for (int h = 0; h < 2; h++) {
+                                    const int c = 2 * j + h;
+                                    if (c < P) {
+                                        const int cc = c < P ? c : 0;
+                                        qv[h] = fma(omf, v[cc], uf * v[cc + 1]) - Tv[cc];
+                                        mq[h] = allv ? qv[h] : mv[cc] * qv[h];
+                                    }
+                                }
+                                sp[j] = mq[0] + mq[1];
+                                ep[j] = fma(mq[0], qv[0], mq[1] * qv[1]);
+                            }
+                            s0 = (sp[0] + sp[1]) + (sp[2] + sp[3]);
+                            e0 = (ep[0] + ep[1]) + (ep[2] + ep[3]);
+                        } else if (allv) {
+                            // two interleaved chains per sum: half the
+                            // dependent adds
 #pragma unroll
                             for (int c = 0; c < P; c++) {
-                                const T q = (omf * v[c] + uf * v[c + 1]) - Tv[c];
+                                const T q = fma(omf, v[c], uf * v[c + 1]) - Tv[c];
                                 if (c & 1) { s1 += q; e1 = fma(q, q, e1); }
                                 else { s0 += q; e0 = fma(q, q, e0); }
                             }
                         } else {
 #pragma unroll
                             for (int c = 0; c < P; c++) {
-                                const T q = (omf * v[c] + uf * v[c + 1]) - Tv[c];
+                                const T q = fma(omf, v[c], uf * v[c + 1]) - Tv[c];
                                 const T mq = mv[c] * q;
                                 if (c & 1) { s1 = fma(mv[c], q, s1); e1 = fma(mq, q, e1); }
                                 else { s0 = fma(mv[c], q, s0); e0 = fma(mq, q, e0); }
                             }
                         }
-                        acc[2 * i] = s0 + s1;
-                        acc[2 * i + 1] = e0 + e1;
+                        acc[2 * i] = CAN ? s0 : s0 + s1;
+                        acc[2 * i + 1] = CAN ? e0 : e0 + e1;
                     }
                 }
                 seg_sum_n<SEG, 2 * WN>(acc);

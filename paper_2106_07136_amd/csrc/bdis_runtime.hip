@@ -18,6 +18,7 @@
 #include "bdis_kernels.hpp"
 #include "bdis_persist.hpp"
 #include "bdis_search2d.hpp"
+#include "bdis_lkwave.hpp"
 #include "bdisnet_internal.hpp"
 
 using namespace bdis;
@@ -62,6 +63,10 @@ constexpr int kStripBlocksPerCU = 4;
 // A plain batch of more than kMaxJobs pairs runs as up to kMaxLanes groups
 // of pairs, each on a stream of its own, so that the groups' launches overlap.
 constexpr int kMaxLanes = 3;
+// An LK launch (patch side <= 8) of at most this many patches per CU runs
+// one wave per patch (k_lkw) instead of one lane per patch row: the same
+// bits, a shorter chain per patch where the chip is far from full.
+constexpr int kWavePatchesPerCU = 8;
 
 thread_local char g_thread_err[512] = "";
 
@@ -268,6 +273,8 @@ struct bdis_ctx {
     int wgs_per_cu = 0;
     // densify levels >= 1 inside the next finer level's LK launch
     bool fold_dense = true;
+    // LK launches of at most this many patches per CU run k_lkw (0: never)
+    int wave_patches_per_cu = kWavePatchesPerCU;
     hipStream_t cap_stream = nullptr;
     // second stream and its fork/join events (learned init: the network
     // runs beside the plain coarse levels)
@@ -385,7 +392,7 @@ bdis_status ensure_ws(bdis_t *h, size_t bytes) {
 // K_FORK / K_JOIN launch nothing: work after a fork runs on the side stream
 // (lane 1) until the join makes the main stream wait for it.  K_FORKN /
 // K_JOINN do the same for the `level` group streams of a large batch.
-enum Kind { K_PYR2, K_LK, K_DENSE, K_NETIN, K_NETF, K_GATE, K_FORK, K_JOIN, K_LK2, K_DENSE2, K_FORKN, K_JOINN };
+enum Kind { K_PYR2, K_LK, K_DENSE, K_NETIN, K_NETF, K_GATE, K_FORK, K_JOIN, K_LK2, K_DENSE2, K_FORKN, K_JOINN, K_LKW };
 struct Launch {
     Kind kind;
     int level;
@@ -617,8 +624,13 @@ void plan_launches(bdis_t *h, std::vector<PairIn> &pairs, std::vector<Launch> &l
             }
             KParams kpp = make_kparams(h->prm, P);
             kpp.iters = kpl.iters;
-            append(ls, K_LK, l, P, l == 0, f64, jobs, kpp,
-                   [P](const LkJob &j) { return j.ny * lk_bpr(P, j.nx); });
+            long long npatch = 0;
+            for (const LkJob &j : jobs) npatch += (long long)j.nx * j.ny;
+            if (P <= 8 && npatch <= (long long)h->wave_patches_per_cu * ncu)
+                append(ls, K_LKW, l, P, l == 0, f64, jobs, kpp, [](const LkJob &j) { return lkw_blocks(j.nx, j.ny); });
+            else
+                append(ls, K_LK, l, P, l == 0, f64, jobs, kpp,
+                       [P](const LkJob &j) { return j.ny * lk_bpr(P, j.nx); });
         }
         if (lrn && l == inj) {
             ls.push_back(Launch{K_JOIN, 0, 0, false, f64, 0, kp0, {}});
@@ -683,6 +695,19 @@ void launch_lk(const bdis_t *h, const Launch &L, hipStream_t s) {
     }
 }
 
+template <typename T, int P>
+void launch_lkw(const Launch &L, hipStream_t s) {
+    const JobPack<LkJob> &pk = pack_of<LkJob>(L);
+    const dim3 g(L.blocks), b(kBlock);
+    if (L.kp.window <= 5) {
+        if (L.u8) hipLaunchKernelGGL((k_lkw<T, P, true, 5>), g, b, 0, s, pk, L.kp);
+        else hipLaunchKernelGGL((k_lkw<T, P, false, 5>), g, b, 0, s, pk, L.kp);
+    } else {
+        if (L.u8) hipLaunchKernelGGL((k_lkw<T, P, true, 9>), g, b, 0, s, pk, L.kp);
+        else hipLaunchKernelGGL((k_lkw<T, P, false, 9>), g, b, 0, s, pk, L.kp);
+    }
+}
+
 template <typename T>
 void launch_one(bdis_t *h, const Launch &L, hipStream_t s) {
     switch (L.kind) {
@@ -717,6 +742,13 @@ void launch_one(bdis_t *h, const Launch &L, hipStream_t s) {
         case 10: launch_lk<T, 10>(h, L, s); break;
         case 12: launch_lk<T, 12>(h, L, s); break;
         case 16: launch_lk<T, 16>(h, L, s); break;
+        }
+        break;
+    case K_LKW:
+        switch (L.patch) {
+        case 4: launch_lkw<T, 4>(L, s); break;
+        case 6: launch_lkw<T, 6>(L, s); break;
+        case 8: launch_lkw<T, 8>(L, s); break;
         }
         break;
     case K_LK2: {
@@ -757,6 +789,7 @@ std::string launch_name(const Launch &L) {
     switch (L.kind) {
     case K_PYR2: snprintf(buf, sizeof buf, "pyr2_%s_l%d", t, L.level); break;
     case K_LK: snprintf(buf, sizeof buf, "lk_%s_p%d_l%d", t, L.patch, L.level); break;
+    case K_LKW: snprintf(buf, sizeof buf, "lkw_%s_p%d_l%d", t, L.patch, L.level); break;
     case K_DENSE: snprintf(buf, sizeof buf, "dense_%s_l%d", t, L.level); break;
     case K_NETIN: snprintf(buf, sizeof buf, "netin_%s", t); break;
     case K_NETF: snprintf(buf, sizeof buf, "net_forward"); break;
@@ -1663,6 +1696,13 @@ bdis_status bdis_set_batch_groups(bdis_t *h, int32_t on) {
     if (!h) { set_err(g_thread_err, "handle is NULL"); return BDIS_E_INVALID_ARG; }
     if (on != 0 && on != 1) { set_err(h->err, "groups must be 0 or 1"); return BDIS_E_INVALID_ARG; }
     h->lane_groups = on != 0;
+    return BDIS_OK;
+}
+
+bdis_status bdis_set_wave_lk(bdis_t *h, int32_t patches_per_cu) {
+    if (!h) { set_err(g_thread_err, "handle is NULL"); return BDIS_E_INVALID_ARG; }
+    if (patches_per_cu < 0) { set_err(h->err, "patches_per_cu must be >= 0"); return BDIS_E_INVALID_ARG; }
+    h->wave_patches_per_cu = patches_per_cu;
     return BDIS_OK;
 }
 
