@@ -1290,24 +1290,31 @@ __device__ __forceinline__ void lk_block(const LkJob &J, const int lb, const KPa
                         // at all in waves whose rows are all valid.
                         T s0 = 0, s1 = 0, e0 = 0, e1 = 0;
                         if constexpr (CAN) {
-                            // row_sum8 of m and row_dot8 of (m, q), pair by
-                            // pair (slots past the patch side: zeros)
+                            // row_sum8 of m = mask q and row_dot8 of (m, q),
+                            // pair by pair (slots past the patch side:
+                            // zeros); a wave whose rows are all valid takes
+                            // m = q, the same bits as 1 q
                             T sp[4], ep[4];
+                            auto pairs = [&](auto masked_) {
+                                constexpr bool MASKED = decltype(masked_)::value;
 #pragma unroll
-                            for (int j = 0; j < 4; j++) {
-                                T qv[2] = {T(0), T(0)}, mq[2] = {T(0), T(0)};
+                                for (int j = 0; j < 4; j++) {
+                                    T qv[2] = {T(0), T(0)}, mq[2] = {T(0), T(0)};
 #pragma unroll
-                                for (int h = 0; h < 2; h++) {
-                                    const int c = 2 * j + h;
-                                    if (c < P) {
-                                        const int cc = c < P ? c : 0;
-                                        qv[h] = fma(omf, v[cc], uf * v[cc + 1]) - Tv[cc];
-                                        mq[h] = allv ? qv[h] : mv[cc] * qv[h];
+                                    for (int h = 0; h < 2; h++) {
+                                        const int c = 2 * j + h;
+                                        if (c < P) {
+                                            const int cc = c < P ? c : 0;
+                                            qv[h] = fma(omf, v[cc], uf * v[cc + 1]) - Tv[cc];
+                                            mq[h] = MASKED ? mv[cc] * qv[h] : qv[h];
+                                        }
                                     }
+                                    sp[j] = mq[0] + mq[1];
+                                    ep[j] = fma(mq[0], qv[0], mq[1] * qv[1]);
                                 }
-                                sp[j] = mq[0] + mq[1];
-                                ep[j] = fma(mq[0], qv[0], mq[1] * qv[1]);
-                            }
+                            };
+                            if (allv) pairs(std::false_type());
+                            else pairs(std::true_type());
                             s0 = (sp[0] + sp[1]) + (sp[2] + sp[3]);
                             e0 = (ep[0] + ep[1]) + (ep[2] + ep[3]);
                         } else if (allv) {
