@@ -91,10 +91,10 @@ def dense_flops(pixels, taps):
 # WRITE_SIZE, scaled by a 256 MiB device copy (fetch x 1.9998, write x 1.0);
 # valid only for the kernel source they were taken on (sha256 prefix).
 KERNEL_SRC = os.path.join(ROOT, "paper_2106_07136_amd", "csrc", "bdis_kernels.hpp")
-MEASURED_TRAFFIC = {("lk_f64_p8_l0", "205453deaaadc00e"): 5600599}
+MEASURED_TRAFFIC = {("lk_f64_p8_l0", "b3a9450808efccf7"): 5607766}
 # LDS bytes read + written per launch: rocprofv3 SQ_INSTS_LDS_LOAD_BANDWIDTH
 # + SQ_INSTS_LDS_STORE_BANDWIDTH (64-byte units), same validity rule.
-MEASURED_LDS = {("lk_f64_p8_l0", "205453deaaadc00e"): (1333382 + 228480) * 64}
+MEASURED_LDS = {("lk_f64_p8_l0", "b3a9450808efccf7"): (1333382 + 228480) * 64}
 
 
 def _kernel_sha():
