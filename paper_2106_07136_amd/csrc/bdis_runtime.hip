@@ -661,6 +661,8 @@ static_assert(sizeof(JobPack<LkJob>) + sizeof(KParams) <= 4000, "LK job pack too
 static_assert(sizeof(JobPack<DenseJob>) + sizeof(KParams) <= 4000, "densify job pack too large");
 static_assert(sizeof(JobPack<NetInJob>) <= 4000 && sizeof(JobPack<GateJob>) <= 4000, "job pack too large");
 static_assert(sizeof(bdisnet::FusedPack) <= 4000, "fused network job pack too large");
+static_assert(sizeof(JobPack<Lk2Job>) + sizeof(KParams) <= 4000, "2-D LK job pack too large");
+static_assert(sizeof(JobPack<Dense2Job>) + sizeof(KParams) <= 4000, "2-D densify job pack too large");
 
 template <typename Job>
 const JobPack<Job> &pack_of(const Launch &L) {
@@ -755,7 +757,15 @@ void launch_one(bdis_t *h, const Launch &L, hipStream_t s) {
         const JobPack<Lk2Job> &pk = pack_of<Lk2Job>(L);
         const dim3 g(L.blocks), b(kBlock);
         const bool w5 = L.kp.window <= 5;
-#define BDIS_LK2(PP, U, WW) hipLaunchKernelGGL((k_lk2d<T, PP, U, WW>), g, b, 0, s, pk, L.kp)
+        // the build with the densification when any job densifies level + 1
+        // (a pair at its coarsest level in the same launch does not)
+        bool fold = false;
+        for (int i = 0; i < pk.n; i++) fold = fold || pk.j[i].rec_w1 != nullptr;
+#define BDIS_LK2(PP, U, WW)                                                                   \
+    do {                                                                                        \
+        if (fold) hipLaunchKernelGGL((k_lk2d<T, PP, U, WW, true>), g, b, 0, s, pk, L.kp);       \
+        else hipLaunchKernelGGL((k_lk2d<T, PP, U, WW, false>), g, b, 0, s, pk, L.kp);           \
+    } while (0)
 #define BDIS_LK2_P(PP)                                                       \
     if (L.u8) { if (w5) BDIS_LK2(PP, true, 5); else BDIS_LK2(PP, true, 9); } \
     else { if (w5) BDIS_LK2(PP, false, 5); else BDIS_LK2(PP, false, 9); }
@@ -1344,7 +1354,20 @@ bdis_status run_2d(bdis_t *h, std::vector<PairIn> &ps, const std::vector<std::pa
     plan_pyramid(ls, ps, Lmax, f64, kp);
     const void *gt = f64 ? (const void *)(h->gtab_d + gtab_offset(prm.patch))
                          : (const void *)(h->gtab_f + gtab_offset(prm.patch));
+    // A small LK launch (at most kFoldBlocksPerCU blocks per CU, as the
+    // coarse levels of one pair) densifies the level above it (both fields,
+    // its share of them and its patches' initial-shift taps), as the 1-D
+    // path's small launches do, in place of that level's densify launch.
+    // The same bits either way.
+    std::vector<char> fold_at(Lmax, 0);
+    for (int l = 0; l < Lmax; l++) {
+        long long blocks = 0;
+        for (const PairIn &p : ps)
+            if (p.g.L > l) blocks += lk2_blocks(p.g.nx[l], p.g.ny[l]);
+        fold_at[l] = h->fold_dense && blocks <= (long long)kFoldBlocksPerCU * h->n_cu;
+    }
     for (int l = Lmax - 1; l >= 0; l--) {
+        const bool fold = fold_at[l];
         std::vector<Lk2Job> lj;
         std::vector<Dense2Job> dj;
         for (size_t i = 0; i < ps.size(); i++) {
@@ -1358,11 +1381,18 @@ bdis_status run_2d(bdis_t *h, std::vector<PairIn> &ps, const std::vector<std::pa
             j.Uc = coarsest ? nullptr : w.U[l + 1];
             j.Vc = coarsest ? nullptr : w.V[l + 1];
             j.rec_u = w.rec_u[l]; j.rec_v = w.rec_v[l]; j.rec_w = w.rec_w[l]; j.rec_st = w.rec_st[l];
+            if (fold && !coarsest) {
+                j.rec_u1 = w.rec_u[l + 1]; j.rec_v1 = w.rec_v[l + 1]; j.rec_w1 = w.rec_w[l + 1];
+                j.gtab1 = gt;
+                j.U2 = l + 2 < p.g.L ? w.U[l + 2] : nullptr;
+                j.V2 = l + 2 < p.g.L ? w.V[l + 2] : nullptr;
+            }
             j.pitch = l == 0 ? p.pitch : p.g.W[l];
             j.W = p.g.W[l]; j.H = p.g.H[l];
             j.Wc = coarsest ? 0 : p.g.W[l + 1]; j.Hc = coarsest ? 0 : p.g.H[l + 1];
             j.nx = p.g.nx[l]; j.ny = p.g.ny[l]; j.stride = p.stride;
             lj.push_back(j);
+            if (l > 0 && fold_at[l - 1]) continue;  // densified by the level l - 1 LK launch
             Dense2Job d{};
             for (int f = 0; f < 2; f++) {
                 DenseView &D = f == 0 ? d.du : d.dv;

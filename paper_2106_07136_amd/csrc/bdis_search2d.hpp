@@ -19,14 +19,20 @@ namespace bdis {
 
 struct Lk2Job {
     const void *L, *R;              // this level's images (uint8 at level 0)
-    const void *Uc, *Vc;            // fields of level + 1 (null at the coarsest)
+    void *Uc, *Vc;                  // fields of level + 1 (null at the coarsest): read for the
+                                    // initial (u, v), or -- when the job densifies level + 1
+                                    // itself (rec_w1 set) -- written (this launch's share)
     void *rec_u, *rec_v, *rec_w;    // per-patch records (arithmetic type)
     int8_t *rec_st;                 // per-patch outcome
+    // Densification of level + 1 folded into this launch: its records, the
+    // spatial weights and the fallback fields (level + 2, null when level + 1
+    // is the coarsest); rec_w1 null: Uc and Vc are read as they are
+    const void *rec_u1, *rec_v1, *rec_w1, *gtab1, *U2, *V2;
     int pitch, W, H, Wc, Hc, nx, ny, stride;
     int block0;
     int pad_;
 };
-static_assert(sizeof(Lk2Job) == 8 * 8 + 10 * 4, "Lk2Job must have no padding");
+static_assert(sizeof(Lk2Job) == 14 * 8 + 10 * 4, "Lk2Job must have no padding");
 
 // The two fusions of one level: same weights, records and fallback fields
 // of u or of v.
@@ -93,13 +99,18 @@ __device__ __forceinline__ T sample2(const void *img, int pitch, int W, int H, T
     return bilinear_mix<T>(f00, f01, f10, f11, fx, fy);
 }
 
-template <typename T, int P, bool U8, int WN>
+// FOLD compiles the densification of level + 1 in (used when J.rec_w1 is
+// set; the small launches): its gathers cost registers, so the large
+// launches take the build without it.
+template <typename T, int P, bool U8, int WN, bool FOLD>
 __global__ __launch_bounds__(kBlock) void k_lk2d(const JobPack<Lk2Job> pk, KParams kp) {
     static_assert(P * P <= 64, "one lane per patch pixel");
     const Lk2Job &J = pk.j[find_job(pk, (int)blockIdx.x)];
     const int lane = (int)threadIdx.x & 63;
-    const int k = ((int)blockIdx.x - J.block0) * kLk2PatchesPerBlock + (int)threadIdx.x / 64;
-    if (k >= J.nx * J.ny) return;  // uniform per wave
+    const int lb = (int)blockIdx.x - J.block0;
+    const int kraw = lb * kLk2PatchesPerBlock + (int)threadIdx.x / 64;
+    const bool live = kraw < J.nx * J.ny;  // uniform per wave
+    const int k = live ? kraw : J.nx * J.ny - 1;
     const int jy = k / J.nx, jx = k - jy * J.nx;
     const int x0 = grid_pos(jx, J.W, P, J.stride), y0 = grid_pos(jy, J.H, P, J.stride);
     const bool on = lane < P * P;
@@ -114,13 +125,51 @@ __global__ __launch_bounds__(kBlock) void k_lk2d(const JobPack<Lk2Job> pk, KPara
     const T gy = T(0.5) * (pix2<T, U8>(J.L, J.pitch, x, min(y + 1, H - 1), kp, d2) -
                            pix2<T, U8>(J.L, J.pitch, x, max(y - 1, 0), kp, d3));
     const bool val = on && vl;
-    // initial translation: twice the coarse fields at the patch centre
+    // initial translation: twice the coarse fields at the patch centre,
+    // those fields densified here when this launch densifies level + 1
     T u0 = 0, v0 = 0;
     if (J.Uc) {
         const T cx = (T)x0 + T(0.5) * (T)(P - 1), cy = (T)y0 + T(0.5) * (T)(P - 1);
-        u0 = T(2) * bilinear<T>(static_cast<const T *>(J.Uc), J.Wc, J.Hc, T(0.5) * cx, T(0.5) * cy);
-        v0 = T(2) * bilinear<T>(static_cast<const T *>(J.Vc), J.Wc, J.Hc, T(0.5) * cx, T(0.5) * cy);
+        if (!FOLD || !J.rec_w1) {
+            u0 = T(2) * bilinear<T>(static_cast<const T *>(J.Uc), J.Wc, J.Hc, T(0.5) * cx, T(0.5) * cy);
+            v0 = T(2) * bilinear<T>(static_cast<const T *>(J.Vc), J.Wc, J.Hc, T(0.5) * cx, T(0.5) * cy);
+        } else if constexpr (FOLD) {
+            // the 1-D fold's arithmetic for both fields: the same weights,
+            // the records and fallback of u or of v
+            DenseView Du;
+            Du.L = Du.R = nullptr;
+            Du.rec_u = J.rec_u1; Du.rec_w = J.rec_w1; Du.gtab = J.gtab1; Du.Uc = J.U2;
+            Du.pitch = 0; Du.W = J.Wc; Du.H = J.Hc; Du.patch = P; Du.stride = J.stride;
+            Du.nx = J.Wc < P ? 0 : (J.Wc - P + J.stride - 1) / J.stride + 1;
+            Du.ny = J.Hc < P ? 0 : (J.Hc - P + J.stride - 1) / J.stride + 1;
+            Du.Wc = (J.Wc + 1) / 2; Du.Hc = (J.Hc + 1) / 2;
+            Du.mode = J.U2 ? 0 : 1;
+            DenseView Dv = Du;
+            Dv.rec_u = J.rec_v1; Dv.Uc = J.V2;
+            int mx, my, mx1, my1;
+            T fx, fy;
+            bilinear_taps<T>(J.Wc, J.Hc, T(0.5) * cx, T(0.5) * cy, mx, my, mx1, my1, fx, fy);
+            const int tap = lane & 3, tx = (tap & 1) ? mx1 : mx, ty = (tap & 2) ? my1 : my;
+            const T Fu = dense_value<T, false, 3>(Du, tx, ty, kp);
+            const T Fv = dense_value<T, false, 3>(Dv, tx, ty, kp);
+            if constexpr (!U8) {
+                // this block's share of both level + 1 fields (the next finer
+                // level's fallback reads them); no finer level reads level 1
+                // of a level-0 launch
+                const int n1 = J.Wc * J.Hc, nblk = lk2_blocks(J.nx, J.ny), chunk = (n1 + nblk - 1) / nblk;
+                const int i1 = min(n1, (lb + 1) * chunk);
+                const double inv_wc = 1.0 / (double)J.Wc;
+                for (int i = lb * chunk + (int)threadIdx.x; i < i1; i += kBlock) {
+                    const int yy = div_exact(i, inv_wc), xx = i - yy * J.Wc;
+                    static_cast<T *>(J.Uc)[i] = dense_value<T, false, 3>(Du, xx, yy, kp);
+                    static_cast<T *>(J.Vc)[i] = dense_value<T, false, 3>(Dv, xx, yy, kp);
+                }
+            }
+            u0 = T(2) * bilinear_mix<T>(dpp_v<0x00>(Fu), dpp_v<0x55>(Fu), dpp_v<0xAA>(Fu), dpp_v<0xFF>(Fu), fx, fy);
+            v0 = T(2) * bilinear_mix<T>(dpp_v<0x00>(Fv), dpp_v<0x55>(Fv), dpp_v<0xAA>(Fv), dpp_v<0xFF>(Fv), fx, fy);
+        }
     }
+    if (!live) return;  // uniform per wave; no block-wide step follows
     const int n = wave_sum_i(val ? 1 : 0);
     T g[2] = {val ? gx : T(0), val ? gy : T(0)};
     wave_sum_n<2>(g);

@@ -261,6 +261,40 @@ def test_bench_batch_matches_oracle(torch_cuda, ref):
         assert_parity(v, ev, f"2-D bench batch pair {i} v")
 
 
+@pytest.mark.parametrize("name,W,H,dmax,kw", [
+    ("640x480", 640, 480, 64.0, dict(levels=5)),
+    ("160x120_level0_folds", 160, 120, 16.0, dict(levels=3)),
+    ("203x97_p6", 203, 97, 20.0, dict(levels=3, patch=6, stride=3)),
+    ("150x77_p4_w9", 150, 77, 15.0, dict(levels=3, patch=4, stride=2, window=9, window_step=0.25)),
+])
+def test_folded_densify_same_bits(torch_cuda, name, W, H, dmax, kw):
+    """The small LK launches densify the level above them (both fields)
+    in place of that level's densify launch: the same d and v bits as one
+    densify launch per level, on a single pair and in a batch."""
+    from paper_2106_07136_amd import bdis
+    torch = torch_cuda
+    print(f"case {name}", flush=True)
+    mis, _ = synth.misaligned_pair(W, H, dmax, W + H, v_max=3.0)
+    L = torch.from_numpy(mis.left).cuda()
+    R = torch.from_numpy(mis.right).cuda()
+    res = {}
+    for fold in (True, False):
+        h = bdis.Bdis(bdis.Params(**kw))
+        h.set_fold_densify(fold)
+        d = torch.empty(L.shape, dtype=torch.float32, device="cuda")
+        v = torch.empty_like(d)
+        h.compute_2d(L, R, d, v)
+        ds, vs = h.compute_batch_2d([L, L], [R, R], max_disparity=[dmax] * 2)
+        res[fold] = (d.cpu().numpy(), v.cpu().numpy(), [(a.cpu().numpy(), b.cpu().numpy()) for a, b in zip(ds, vs)])
+        h.close()
+    for a, b in zip(res[True][:2], res[False][:2]):
+        np.testing.assert_array_equal(a.view(np.uint32), b.view(np.uint32))
+    assert np.isfinite(res[True][0]).mean() > 0.3
+    for (a1, b1), (a2, b2) in zip(res[True][2], res[False][2]):
+        np.testing.assert_array_equal(a1.view(np.uint32), a2.view(np.uint32))
+        np.testing.assert_array_equal(b1.view(np.uint32), b2.view(np.uint32))
+
+
 def test_rejections(torch_cuda):
     """Patch sides above 8, eq. (2)'s fusion and the learned init are
     refused before any launch; the handle still runs afterwards."""
