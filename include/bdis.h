@@ -232,17 +232,19 @@ BDIS_API bdis_status bdis_compute_batch(bdis_t *h, const bdis_pair *pairs, int32
  *     captured with a counter-reset kernel in a hipGraph; new buffer pointers
  *     only re-upload the task tables.  Patch sides 8 and 12 only.
  * wgs_per_cu: persistent workgroups per compute unit (0 = as many as fit).
+ * bdis_compute_batch_2d replays its launches from a hipGraph in mode 0 and
+ * launches them directly otherwise.
  * Results are the same in every mode, bit for bit. */
 BDIS_API bdis_status bdis_set_batch_mode(bdis_t *h, int32_t mode, int32_t wgs_per_cu);
 
-/* bdis_compute_batch on more than 24 pairs (modes 0 and 1, plain init)
- * runs them as up to three groups of pairs, each group's launches on a
- * stream of its own so that they overlap: pairs go largest first to the
- * group with the fewest pixels, and each group's launches take the kernel
- * builds for its share of the compute units.  A learned-init batch always
- * runs on one stream (with its network on one side stream).  Results are
- * the same bits either way.  on: 1 (default) or 0 (one stream).
- * Errors: BDIS_E_INVALID_ARG. */
+/* bdis_compute_batch (modes 0 and 1, plain init) and bdis_compute_batch_2d
+ * on more than 24 pairs run them as up to three groups of pairs, each
+ * group's launches on a stream of its own so that they overlap: pairs go
+ * largest first to the group with the fewest pixels, and each group's
+ * launches take the kernel builds for its share of the compute units.  A
+ * learned-init batch always runs on one stream (with its network on one
+ * side stream).  Results are the same bits either way.  on: 1 (default) or
+ * 0 (one stream).  Errors: BDIS_E_INVALID_ARG. */
 BDIS_API bdis_status bdis_set_batch_groups(bdis_t *h, int32_t on);
 
 /* Launch layout of the per-launch executions (bdis_compute, batch modes 0 and

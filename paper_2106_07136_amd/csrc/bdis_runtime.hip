@@ -1328,29 +1328,16 @@ size_t pair_ws2_bytes(const Geo &g, size_t esz, PairWs2 *w, char *base) {
 // vertical output and pitch in vout): pyramids, then per level (coarsest
 // first) the 2-D LK launch and the two-field densification of every pair
 // that has the level, at most a pack of jobs per launch.
-bdis_status run_2d(bdis_t *h, std::vector<PairIn> &ps, const std::vector<std::pair<float *, int>> &vout,
-                   hipStream_t s) {
-    DeviceGuard dg(h->device);
+// The launches of the 2-D search for pairs ps (their workspaces ws), planned
+// for ncu compute units.
+void plan_2d(bdis_t *h, const std::vector<PairIn> &ps, const std::vector<PairWs2> &ws,
+             const std::vector<std::pair<float *, int>> &vout, std::vector<Launch> &ls, int ncu) {
     const bdis_params &prm = h->prm;
     const bool f64 = prm.precision == 0;
-    const size_t esz = esize(prm);
-    size_t need = 0;
-    for (const PairIn &p : ps) need += align_up(pair_ws2_bytes(p.g, esz, nullptr, nullptr));
-    bdis_status st = ensure_ws(h, need);
-    if (st != BDIS_OK) return st;
-    std::vector<PairWs2> ws(ps.size());
     int Lmax = 0;
-    size_t off = 0;
-    for (size_t i = 0; i < ps.size(); i++) {
-        PairIn &p = ps[i];
-        off += align_up(pair_ws2_bytes(p.g, esz, &ws[i], h->ws + off));
-        // the pyramid pointers feed the shared pyramid planner
-        memset(&p.ws, 0, sizeof p.ws);
-        for (int l = 1; l < p.g.L; l++) { p.ws.pyr_l[l] = ws[i].pyr_l[l]; p.ws.pyr_r[l] = ws[i].pyr_r[l]; }
-        Lmax = std::max(Lmax, p.g.L);
-    }
-    std::vector<Launch> ls;
+    for (const PairIn &p : ps) Lmax = std::max(Lmax, p.g.L);
     const KParams kp = make_kparams(prm, prm.patch);
+    const size_t first = ls.size();
     plan_pyramid(ls, ps, Lmax, f64, kp);
     const void *gt = f64 ? (const void *)(h->gtab_d + gtab_offset(prm.patch))
                          : (const void *)(h->gtab_f + gtab_offset(prm.patch));
@@ -1364,7 +1351,7 @@ bdis_status run_2d(bdis_t *h, std::vector<PairIn> &ps, const std::vector<std::pa
         long long blocks = 0;
         for (const PairIn &p : ps)
             if (p.g.L > l) blocks += lk2_blocks(p.g.nx[l], p.g.ny[l]);
-        fold_at[l] = h->fold_dense && blocks <= (long long)kFoldBlocksPerCU * h->n_cu;
+        fold_at[l] = h->fold_dense && blocks <= (long long)kFoldBlocksPerCU * ncu;
     }
     for (int l = Lmax - 1; l >= 0; l--) {
         const bool fold = fold_at[l];
@@ -1417,6 +1404,59 @@ bdis_status run_2d(bdis_t *h, std::vector<PairIn> &ps, const std::vector<std::pa
         append(ls, K_DENSE2, l, 0, l == 0, f64, dj, kp,
                [](const Dense2Job &q) { return (q.du.W * q.du.H + kBlock - 1) / kBlock; });
     }
+    for (size_t i = first; i < ls.size(); i++) ls[i].ncu = ncu;
+}
+
+bdis_status run_2d(bdis_t *h, std::vector<PairIn> &ps, const std::vector<std::pair<float *, int>> &vout,
+                   hipStream_t s) {
+    DeviceGuard dg(h->device);
+    const bdis_params &prm = h->prm;
+    const size_t esz = esize(prm);
+    size_t need = 0;
+    for (const PairIn &p : ps) need += align_up(pair_ws2_bytes(p.g, esz, nullptr, nullptr));
+    bdis_status st = ensure_ws(h, need);
+    if (st != BDIS_OK) return st;
+    std::vector<PairWs2> ws(ps.size());
+    size_t off = 0;
+    for (size_t i = 0; i < ps.size(); i++) {
+        PairIn &p = ps[i];
+        off += align_up(pair_ws2_bytes(p.g, esz, &ws[i], h->ws + off));
+        // the pyramid pointers feed the shared pyramid planner
+        memset(&p.ws, 0, sizeof p.ws);
+        for (int l = 1; l < p.g.L; l++) { p.ws.pyr_l[l] = ws[i].pyr_l[l]; p.ws.pyr_r[l] = ws[i].pyr_r[l]; }
+    }
+    std::vector<Launch> ls;
+    const int ngroups = std::min<int>(kMaxLanes, ((int)ps.size() + kMaxJobs - 1) / kMaxJobs);
+    if (h->lane_groups && ngroups > 1) {
+        // pair groups on streams of their own, as bdis_compute_batch's
+        std::vector<int> order(ps.size());
+        for (size_t i = 0; i < order.size(); i++) order[i] = (int)i;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            return (long long)ps[a].W * ps[a].H > (long long)ps[b].W * ps[b].H;
+        });
+        std::vector<std::vector<int>> grp(ngroups);
+        std::vector<long long> px(ngroups, 0);
+        for (int i : order) {
+            const int g = (int)(std::min_element(px.begin(), px.end()) - px.begin());
+            grp[g].push_back(i);
+            px[g] += (long long)ps[i].W * ps[i].H;
+        }
+        const KParams kp0 = make_kparams(prm, prm.patch);
+        ls.push_back(Launch{K_FORKN, ngroups, 0, false, prm.precision == 0, 0, kp0, {}});
+        for (int g = 0; g < ngroups; g++) {
+            std::vector<PairIn> gp;
+            std::vector<PairWs2> gw;
+            std::vector<std::pair<float *, int>> gv;
+            for (int i : grp[g]) { gp.push_back(ps[i]); gw.push_back(ws[i]); gv.push_back(vout[i]); }
+            const size_t first = ls.size();
+            plan_2d(h, gp, gw, gv, ls, std::max(1, h->n_cu / ngroups));
+            for (size_t i = first; i < ls.size(); i++) ls[i].group = g;
+        }
+        ls.push_back(Launch{K_JOINN, ngroups, 0, false, prm.precision == 0, 0, kp0, {}});
+    } else {
+        plan_2d(h, ps, ws, vout, ls, h->n_cu);
+    }
+    if (h->batch_mode == 0 && ps.size() > 1) return run_level_graph(h, ls, s);
     st = launch_all(h, ls, s);
     if (st != BDIS_OK) return st;
     HIPCHK(h, hipGetLastError());

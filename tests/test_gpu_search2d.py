@@ -231,6 +231,33 @@ def test_batch_over_one_pack(torch_cuda):
         np.testing.assert_array_equal(V[i].cpu().numpy().view(np.uint32), v1.cpu().numpy().view(np.uint32))
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_batch_groups_and_graph_same_bits(torch_cuda, mode):
+    """30 pairs: as pair groups on streams of their own or on one stream,
+    replayed from the level graph (mode 0, twice) or launched directly (mode
+    1), the batched 2-D search gives the same d and v bits."""
+    from paper_2106_07136_amd import bdis
+    torch = torch_cuda
+    spec = [(96 + 8 * (i % 3), 64 + 4 * (i % 2), 6.0, 300 + i, 1.0) for i in range(30)]
+    pairs, L, R = _batch_inputs(torch, spec)
+    dm = [4.0 + i for i in range(30)]
+    res = {}
+    for groups in (True, False):
+        h = bdis.Bdis(bdis.Params(levels=0, iters=8))
+        h.set_batch_mode(mode)
+        h.set_batch_groups(groups)
+        runs = []
+        for _ in range(2):
+            D, V = h.compute_batch_2d(L, R, max_disparity=dm)
+            runs.append(([d.cpu().numpy() for d in D], [v.cpu().numpy() for v in V]))
+        h.close()
+        for a, b in zip(runs[0][0] + runs[0][1], runs[1][0] + runs[1][1]):
+            np.testing.assert_array_equal(a.view(np.uint32), b.view(np.uint32))
+        res[groups] = runs[0]
+    for a, b in zip(res[True][0] + res[True][1], res[False][0] + res[False][1]):
+        np.testing.assert_array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
 def test_bench_batch_matches_oracle(torch_cuda, ref):
     """The batched 2-D workload the bench times: the 64 mixed pairs (24 x
     320x240, 24 x 640x480, 16 x 1280x720, seeds from 3000), levels from each
