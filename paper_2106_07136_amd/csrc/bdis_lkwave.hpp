@@ -211,6 +211,16 @@ __global__ __launch_bounds__(kBlock) void k_lkw(const JobPack<LkJob> pk, KParams
             // samples u + (i - c) step, the row kernel's arithmetic
             const int cw = (kp.window - 1) / 2;
             const T mv = val ? T(1) : T(0);
+            // the gamma gate's taps at the final shift (Sec. 3, Sec. 3.2),
+            // loaded here so that they arrive with the window's samples
+            const T uc = fmin(fmax(u, ulo), uhi);
+            const T ui = floor(uc), ufr = uc - ui;
+            const int xc = x0 + (int)ui + c;
+            using RawT = std::conditional_t<U8, uint8_t, T>;
+            auto raw = [&](int xq) -> RawT {
+                return static_cast<const RawT *>(J.R)[row0 + (size_t)min(max(xq, 0), W - 1)];
+            };
+            const RawT g0 = raw(xc), g1 = raw(xc + 1), e0 = raw(W - 2), e1 = raw(W - 1);
             T m[WN], q[WN], acc[2 * WN];
 #pragma unroll
             for (int i = 0; i < WN; i++) {
@@ -256,23 +266,14 @@ __global__ __launch_bounds__(kBlock) void k_lkw(const JobPack<LkJob> pk, KParams
             }
             post = T(1) / seg_sum<8>(term);
             // gamma gate at the final shift: left valid, sample inside the
-            // row, both right taps valid (Sec. 3, Sec. 3.2)
-            const T uc = fmin(fmax(u, ulo), uhi);
-            const T ui = floor(uc), ufr = uc - ui;
-            const int xi0 = x0 + (int)ui;
-            auto tap_ok = [&](int xc) -> bool {
-                const size_t g = row0 + (size_t)min(max(xc, 0), W - 1);
-                if constexpr (U8) {
-                    const int v = static_cast<const uint8_t *>(J.R)[g];
-                    return v >= kp.vlo && v <= kp.vhi;
-                } else {
-                    return !signbit(static_cast<const T *>(J.R)[g]);
-                }
+            // row, both right taps valid
+            auto tap_ok = [&](RawT v) -> bool {
+                if constexpr (U8) return (int)v >= kp.vlo && (int)v <= kp.vhi;
+                else return !signbit(v);
             };
-            const int xc = xi0 + c;
             bool good = false;
-            if (xc >= 0 && xc <= W - 2) good = tap_ok(xc) && tap_ok(xc + 1);
-            else if (ufr == T(0) && xc == W - 1) good = tap_ok(W - 2) && tap_ok(W - 1);
+            if (xc >= 0 && xc <= W - 2) good = tap_ok(g0) && tap_ok(g1);
+            else if (ufr == T(0) && xc == W - 1) good = tap_ok(e0) && tap_ok(e1);
             const int cnt = lkw_sum_i(val && good ? 1 : 0);
             if (cnt < kp.min_valid) {
                 status = ST_GATED;
