@@ -40,10 +40,26 @@ __device__ __forceinline__ float lkw_lane(float v, int lane) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
+// Row broadcasts across the rows of 16 lanes (rows not in ROWS keep 0).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_bcast(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_bcast(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, false));
+}
+constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143;
+
 // Sums over the patch of N values whose column pairs are already formed
 // (each lane of a pair holding the pair's sum): pairs of pairs, halves, row
-// pairs, then the four row-pair sums in a fixed order.  Every lane receives
-// the total.  All 64 lanes must be active.
+// pairs, then the four row-pair sums s0..s3 (one per row of 16 lanes) as
+// (s3 + s2) + (s1 + s0): row 1 adds row 0's and row 3 adds row 2's (row
+// broadcast of lane 15), row 3 then adds row 1's (row broadcast of lane 31),
+// and lane 63's total is read.  Every lane receives the total.  All 64 lanes
+// must be active.
 template <int N, typename T>
 __device__ __forceinline__ void lkw_tail_n(T *v) {
 #pragma clang fp contract(off)
@@ -54,7 +70,11 @@ __device__ __forceinline__ void lkw_tail_n(T *v) {
 #pragma unroll
     for (int i = 0; i < N; i++) v[i] += dpp_v<kDppMirror>(v[i]);
 #pragma unroll
-    for (int i = 0; i < N; i++) v[i] = (lkw_lane(v[i], 0) + lkw_lane(v[i], 16)) + (lkw_lane(v[i], 32) + lkw_lane(v[i], 48));
+    for (int i = 0; i < N; i++) v[i] += dpp_bcast<kDppRowBcast15, 0xA>(v[i]);
+#pragma unroll
+    for (int i = 0; i < N; i++) v[i] += dpp_bcast<kDppRowBcast31, 0xC>(v[i]);
+#pragma unroll
+    for (int i = 0; i < N; i++) v[i] = lkw_lane(v[i], 63);
 }
 // row_sum8 per row, then over the rows
 template <int N, typename T>

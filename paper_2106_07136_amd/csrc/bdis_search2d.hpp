@@ -14,6 +14,7 @@
 // DPP inside each row of 16 lanes, then the four row sums read by readlane.
 #pragma once
 #include "bdis_kernels.hpp"
+#include "bdis_lkwave.hpp"
 
 namespace bdis {
 
@@ -55,9 +56,9 @@ __host__ __device__ constexpr int lk2_blocks(int nx, int ny) {
 }
 
 // Sum over the 64 lanes of a wave, every lane receiving the same bits: DPP
-// sums inside each row of 16 lanes, then the four row sums read from lanes
-// 0, 16, 32 and 48 and added in one fixed order.  All 64 lanes must be
-// active.
+// sums inside each row of 16 lanes, then the four row sums s0..s3 added as
+// (s3 + s2) + (s1 + s0) by two row broadcasts, and lane 63's total read.
+// All 64 lanes must be active.
 __device__ __forceinline__ double lane_value(double v, int lane) {
     return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
                             __builtin_amdgcn_readlane(__double2loint(v), lane));
@@ -69,8 +70,11 @@ template <int N, typename T>
 __device__ __forceinline__ void wave_sum_n(T *v) {
     seg_sum_n<16, N>(v);
 #pragma unroll
-    for (int i = 0; i < N; i++)
-        v[i] = (lane_value(v[i], 0) + lane_value(v[i], 16)) + (lane_value(v[i], 32) + lane_value(v[i], 48));
+    for (int i = 0; i < N; i++) v[i] += dpp_bcast<kDppRowBcast15, 0xA>(v[i]);
+#pragma unroll
+    for (int i = 0; i < N; i++) v[i] += dpp_bcast<kDppRowBcast31, 0xC>(v[i]);
+#pragma unroll
+    for (int i = 0; i < N; i++) v[i] = lane_value(v[i], 63);
 }
 __device__ __forceinline__ int wave_sum_i(int v) {
     v = seg_sum_i<16>(v);
