@@ -13,9 +13,10 @@
 //     row_sum8's order; a product sum first fuses each even slot's product
 //     with its odd neighbour's, rounded, then copies that pair sum to the odd
 //     lane, as row_dot8 does;
-//   - the row mirror then adds rows (0, 1), and the row sums of lanes 0, 16,
-//     32 and 48 are read and added as ((0 + 1) + (2 + 3)), the row kernel's
-//     xor 1 / xor 2 / half-mirror order over its eight row lanes.
+//   - the row mirror then adds rows (0, 1), and the four row-pair sums (one
+//     per row of 16 lanes) are added as ((3 + 2) + (1 + 0)) by two DPP row
+//     broadcasts: the row kernel's xor 1 / xor 2 / half-mirror order over its
+//     eight row lanes, each add's operands swapped (the same bits).
 // The right image is read from global memory (through L1) rather than
 // staged in LDS: the same values as the row kernel's staged copy, and at
 // these launch sizes staging measured no faster.

@@ -11,7 +11,8 @@
 // other lanes idle).  The right image is sampled bilinearly from global
 // memory (rows vary with v, so no row staging); the patch's taps are reused
 // across the iterations through L1.  Per-patch sums are wave reductions:
-// DPP inside each row of 16 lanes, then the four row sums read by readlane.
+// DPP inside each row of 16 lanes, then the four row sums combined by two
+// DPP row broadcasts and read from the last lane.
 #pragma once
 #include "bdis_kernels.hpp"
 #include "bdis_lkwave.hpp"
